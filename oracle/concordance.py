@@ -1,0 +1,113 @@
+"""Track-by-track and cluster-by-cluster concordance of two tracker outputs.
+
+Test infrastructure.  This is the comparison of section 3.3 of the paper:
+the tracks of two runs are put in one-to-one correspondence, then for every
+pair each row is checked for an identical cluster; a track without a
+counterpart counts as entirely different.
+
+Readings used where the paper gives no detail:
+  * tracks a (run A) and b (run B) correspond when each is the other's best
+    partner by shared clusters (ties: the smaller seed id) and they share more
+    than half of the shorter one;
+  * per pair the rows of both tracks are checked, so a row where only one of
+    them has a cluster counts as a disagreement;
+  * the figure is reported in both directions, A->B counting A's unmatched
+    tracks and B->A counting B's.
+
+Both outputs use the tracker's output layout: track_par [n, 8] (x, y, z,
+sinphi, tanl, qpt, chi2, ndf), track_meta [n, 4] (sector, n_clusters, first,
+seed_id), track_cluster (cluster indices), cluster_track [n_clusters].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+PAR_FLOORS = np.array([1.0, 1.0, 0.1, 0.1, 0.1])   # y, z cm; sinphi; tanl; q/pT 1/GeV
+
+
+def _track_of_clusters(res):
+    meta = np.asarray(res["track_meta"]).reshape(-1, 4)
+    n = meta[:, 1].astype(np.int64)
+    owner = np.repeat(np.arange(meta.shape[0], dtype=np.int64), n)
+    first = meta[:, 2].astype(np.int64)
+    idx = np.concatenate([np.arange(f, f + k) for f, k in zip(first, n)]) if len(n) else \
+        np.zeros(0, np.int64)
+    cl = np.asarray(res["track_cluster"])[idx].astype(np.int64)
+    return cl, owner, n, meta[:, 3].astype(np.int64)
+
+
+def _best_partner(cl_a, own_a, n_a, ct_b, seed_b):
+    """For each track of A: (best track of B or -1, shared clusters)."""
+    lab = np.asarray(ct_b)[cl_a].astype(np.int64)
+    ok = lab >= 0
+    a, b = own_a[ok], lab[ok]
+    best = np.full(n_a.shape[0], -1, np.int64)
+    shared = np.zeros(n_a.shape[0], np.int64)
+    if a.size == 0:
+        return best, shared
+    nb = int(b.max()) + 1
+    keys, cnt = np.unique(a * nb + b, return_counts=True)
+    ka, kb = keys // nb, keys % nb
+    # order: by a, then count descending, then seed id ascending -> first per a wins
+    order = np.lexsort((seed_b[kb], -cnt, ka))
+    ka, kb, cnt = ka[order], kb[order], cnt[order]
+    firsts = np.ones(ka.shape[0], bool)
+    firsts[1:] = ka[1:] != ka[:-1]
+    best[ka[firsts]] = kb[firsts]
+    shared[ka[firsts]] = cnt[firsts]
+    return best, shared
+
+
+def compare(res_a, res_b, n_clusters: int, rel_tol: float = 1e-3) -> dict:
+    """Concordance of run B against run A (A = reference, e.g. the oracle)."""
+    cl_a, own_a, n_a, seed_a = _track_of_clusters(res_a)
+    cl_b, own_b, n_b, seed_b = _track_of_clusters(res_b)
+    ct_a = np.asarray(res_a["cluster_track"])[:n_clusters]
+    ct_b = np.asarray(res_b["cluster_track"])[:n_clusters]
+    best_ab, sh_ab = _best_partner(cl_a, own_a, n_a, ct_b, seed_b)
+    best_ba, sh_ba = _best_partner(cl_b, own_b, n_b, ct_a, seed_a)
+    ia = np.arange(n_a.shape[0])
+    mutual = best_ab >= 0
+    mutual[mutual] &= best_ba[best_ab[mutual]] == ia[mutual]
+    mutual &= 2 * sh_ab > np.minimum(n_a, n_b[np.maximum(best_ab, 0)] if n_b.size else 0)
+    match_a = np.where(mutual, best_ab, -1)
+    match_b = np.full(n_b.shape[0], -1, np.int64)
+    match_b[match_a[mutual]] = ia[mutual]
+    # per matched pair: identical clusters (same cluster => same row) and the union of rows
+    agree = np.where(mutual, sh_ab, 0)
+    union = np.where(mutual, n_a + n_b[np.maximum(match_a, 0)] - sh_ab if n_b.size else n_a, n_a)
+    tot_ab = union.sum()
+    tot_ba = np.where(match_b >= 0, 0, n_b).sum() + union[mutual].sum()
+    agree_sum = agree.sum()
+    out = dict(
+        n_tracks_a=int(n_a.shape[0]), n_tracks_b=int(n_b.shape[0]),
+        matched=int(mutual.sum()),
+        track_concordance_ab=float(mutual.sum() / max(1, n_a.shape[0])),
+        track_concordance_ba=float(mutual.sum() / max(1, n_b.shape[0])),
+        cluster_concordance_ab=float(agree_sum / max(1, tot_ab)),
+        cluster_concordance_ba=float(agree_sum / max(1, tot_ba)),
+        clusters_a=int(n_a.sum()), clusters_b=int(n_b.sum()),
+    )
+    # parameters of matched pairs with identical cluster sets and the same reference x
+    same = mutual & (agree == n_a) & (n_a == n_b[np.maximum(match_a, 0)] if n_b.size else False)
+    pa = np.asarray(res_a["track_par"]).reshape(-1, 8)
+    pb = np.asarray(res_b["track_par"]).reshape(-1, 8)
+    ia_s = ia[same]
+    ib_s = match_a[same]
+    if ia_s.size:
+        samex = pa[ia_s, 0] == pb[ib_s, 0]
+        ia_s, ib_s = ia_s[samex], ib_s[samex]
+    if ia_s.size:
+        A = pa[ia_s, 1:6]
+        B = pb[ib_s, 1:6].astype(np.float64)
+        scale = np.maximum(np.abs(A), PAR_FLOORS)
+        rel = np.abs(B - A) / scale
+        worst = rel.max(axis=1)
+        out.update(par_compared=int(ia_s.size), par_max_rel=float(worst.max()),
+                   par_fail=int((worst > rel_tol).sum()),
+                   par_fail_frac=float((worst > rel_tol).mean()))
+    else:
+        out.update(par_compared=0, par_max_rel=0.0, par_fail=0, par_fail_frac=0.0)
+    out["cluster_concordance"] = min(out["cluster_concordance_ab"], out["cluster_concordance_ba"])
+    out["track_concordance"] = min(out["track_concordance_ab"], out["track_concordance_ba"])
+    return out
