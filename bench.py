@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Throughput of the TPC sector tracker on one MI355X.
+
+Workload: a central Pb-Pb-like event (36 sectors x 159 pad rows, 8000 primary
+helix tracks, 5% noise clusters, about 1.33M clusters), tracked by the plain
+per-event path (tpc_track_event).  One step = one whole event through every
+stage: grid build, neighbours finder, evolution, seeds, tracklet
+construction, assignment, selection, output.  Inputs are resident in HBM
+before the timed region starts; outputs are preallocated.
+
+Prints one JSON line.  Everything else goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "events/s & clusters/s at ≥99.99% track match; p50/p99 event latency"
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+
+# Algorithmic FP32 operations of the constructor, counted from its arithmetic
+# (a fused multiply-add counts as two): one exact helix step with the
+# covariance transport, one Kalman update, one candidate tested against the
+# chi^2 gate (plus the gate set-up, charged once per step).
+FLOP_STEP = 174 + 20
+FLOP_UPDATE = 129
+FLOP_CAND = 11
+# Algorithmic HBM bytes per cluster of the streaming kernels (read once,
+# written once): see the design notes for the accounting.
+BYTES_PER_CLUSTER = {"k_grid": 8 + 8 + 12 + 8 + 4, "k_nf": 8 + 24 + 8, "k_evo": 8 + 8 + 9}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_src_sha():
+    p = os.path.join(ROOT, "paper_1712_09407_amd", "csrc", "tpc_kernels.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def cpu_baseline(ev_host, geo_t, bz, gpu_res, n_clusters, seconds):
+    """The FP64 oracle on this host's cores, on repeats of the same event."""
+    import oracle
+    from oracle import concordance
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    runs, t0 = 0, time.perf_counter()
+    ref = None
+    while True:
+        ref = oracle.track_event(ev_host, geo_t, bz, oracle.default_params(), n_threads=cores)
+        runs += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or runs >= 200:
+            break
+    rep = concordance.compare(ref, gpu_res, n_clusters)
+    base = dict(value=runs / el, unit="events/s", cores=cores, kind="oracle",
+                sample=f"{runs} run(s) of the benchmark event ({n_clusters} clusters), "
+                       f"{el:.1f} s wall, {cores} threads over sectors")
+    conc = {k: rep[k] for k in ("cluster_concordance", "track_concordance", "cluster_concordance_ab",
+                                "cluster_concordance_ba", "n_tracks_a", "n_tracks_b",
+                                "par_compared", "par_fail", "par_max_rel")}
+    conc["reference"] = "FP64 oracle"
+    return base, conc
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="wall time of the oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one plain 256 MiB device copy first (counter scale for rocprofv3)")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on a single GPU; --gpus must be 1 "
+              "(the path shards by event across GPUs, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1712_09407_amd import synth, tpc
+    import ctypes as C
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    log("generating the central event, seed", args.seed)
+    e = synth.make_preset("c2_central", args.seed)
+    N = e.n_clusters
+    geo = tpc.make_geometry(synth.ROW_X, synth.TAN_HALF, synth.Z_MAX)
+    dev_ev = tpc.DeviceEvent.from_host(e.y, e.z, e.row_offsets, e.sector_id, device=dev)
+    prm = tpc.default_params()
+    tr = tpc.Tracker(0)
+    cap_t, cap_c = max(1024, N // 40), N
+    out = dict(track_par=torch.empty((cap_t, 8), dtype=torch.float32, device=dev),
+               track_meta=torch.empty((cap_t, 4), dtype=torch.int32, device=dev),
+               track_cluster=torch.empty(cap_c, dtype=torch.int32, device=dev),
+               cluster_track=torch.empty(N, dtype=torch.int32, device=dev))
+    if args.copy_probe:
+        a = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy probe: 268435456 bytes read, 268435456 bytes written")
+        del a, b
+    stream = torch.cuda.current_stream()
+    sh = C.c_void_p(stream.cuda_stream)
+    nt, nc = C.c_int32(0), C.c_int32(0)
+    tracks = tpc.Tracks(cap_t, cap_c, C.pointer(nt), C.pointer(nc), out["track_par"].data_ptr(),
+                        out["track_meta"].data_ptr(), out["track_cluster"].data_ptr(),
+                        out["cluster_track"].data_ptr())
+    cev = dev_ev.cstruct()
+
+    def step():
+        rc = tr.track_event_raw(cev, geo, e.bz, prm, tracks, sh)
+        if rc != 0:
+            raise tpc.TpcError(rc, tpc.last_error())
+
+    # warm-up with every kernel timed: find the dominant kernel
+    tr.set_timing(None)
+    for i in range(max(1, args.warmup)):
+        step()
+    st = tr.stats()
+    per = {k: st["kernel_ms"][k] / max(1, st["kernel_launches"][k]) for k in st["kernel_ms"]}
+    dominant = max(per, key=per.get)
+    log("warm-up kernel ms:", {k: round(v, 4) for k, v in per.items()}, "dominant:", dominant)
+
+    # timed region: only the dominant kernel carries an event pair
+    tr.reset_stats()
+    tr.set_timing([dominant])
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        step()
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = tr.stats()
+    log(f"timed {args.steps} steps in {el:.4f} s")
+    res = dict(n_tracks=nt.value, n_track_clusters=nc.value,
+               track_par=out["track_par"][:nt.value].cpu().numpy(),
+               track_meta=out["track_meta"][:nt.value].cpu().numpy(),
+               track_cluster=out["track_cluster"][:nc.value].cpu().numpy(),
+               cluster_track=out["cluster_track"][:N].cpu().numpy())
+
+    dom_ms = st["kernel_ms"][dominant] / max(1, st["kernel_launches"][dominant])
+    ev_n = max(1, st["events"])
+    if dominant == "k_construct":
+        flops = (st["steps"] * FLOP_STEP + st["updates"] * FLOP_UPDATE +
+                 st["candidates"] * FLOP_CAND) / ev_n
+        achieved = flops / (dom_ms * 1e-3) / 1e12
+        roof = dict(bound="alu", achieved=round(achieved, 4), peak=PEAK_FP32_TFLOPS,
+                    unit="TFLOP/s", frac=round(achieved / PEAK_FP32_TFLOPS, 6),
+                    kernel=dominant, kernel_ms=round(dom_ms, 5),
+                    algorithmic_per_launch=f"{flops:.4g} FLOP")
+        work_key = "flop_per_launch"
+    else:
+        nbytes = BYTES_PER_CLUSTER.get(dominant, 16) * N
+        achieved = nbytes / (dom_ms * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=round(achieved, 2), peak=PEAK_HBM_GBS, unit="GB/s",
+                    frac=round(achieved / PEAK_HBM_GBS, 6), kernel=dominant,
+                    kernel_ms=round(dom_ms, 5), algorithmic_per_launch=f"{nbytes} B")
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        tj = json.load(open(args.traffic_json))
+        if tj.get("kernel") == dominant and tj.get("kernel_src_sha") == kernel_src_sha():
+            traffic = tj.get("bytes_per_launch")
+    roof["traffic"] = traffic
+
+    ms = el / args.steps * 1e3
+    lat_ms = sorted(x * 1e3 for x in lat)
+    p = lambda q: lat_ms[min(len(lat_ms) - 1, int(math.ceil(q * len(lat_ms))) - 1)]
+    line = dict(metric=METRIC, value=round(args.steps / el, 3), unit="events/s", n_gpus=1,
+                steps=args.steps, warmup=args.warmup, ms_per_step=round(ms, 4),
+                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+                data="synthetic",
+                config=dict(workload="central Pb-Pb-like event, plain per-event path: 36 sectors "
+                                     "x 159 rows, 8000 primary helix tracks, 5% noise clusters",
+                            n_clusters=N, seed=args.seed, bz_tesla=e.bz),
+                clusters_per_s=round(N * args.steps / el, 1),
+                latency_ms=dict(p50=round(p(0.5), 4), p99=round(p(0.99), 4)),
+                n_tracks=nt.value,
+                kernels_ms={k: round(v, 5) for k, v in per.items()},
+                work_per_event=dict(tracklets=st["tracklets"] / ev_n, steps=st["steps"] / ev_n,
+                                    updates=st["updates"] / ev_n,
+                                    candidates=st["candidates"] / ev_n),
+                roofline=roof)
+    if not args.no_cpu_baseline:
+        log("oracle baseline on the host cores ...")
+        ev_host = dict(y=e.y, z=e.z, row_offsets=e.row_offsets, sector_id=e.sector_id)
+        base, conc = cpu_baseline(ev_host, (synth.ROW_X, synth.TAN_HALF, synth.Z_MAX), e.bz,
+                                  res, N, args.cpu_seconds)
+        line["cpu_baseline"] = base
+        line["concordance"] = conc
+    else:
+        line["cpu_baseline"] = None
+    tr.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

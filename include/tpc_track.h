@@ -1,0 +1,176 @@
+/*
+ * tpc_track.h -- C ABI of the MI355X (gfx950) TPC sector tracker.
+ *
+ * Method: Rohr et al., "ALICE HLT TPC Tracking of Pb-Pb Events on GPUs".
+ * Section 1 defines the steps run here, all on the GPU in hand-written HIP:
+ *   neighbours finder -> evolution step -> chains of one-to-one links ->
+ *   tracklet construction (Kalman fit, extrapolation, chi^2 condition,
+ *   refit) -> tracklet selection.
+ * Section 3.1 defines the cluster weight w = n (alpha - chi^2/beta) that
+ * decides which tracklet keeps a shared cluster; section 3.2 the sorted track
+ * output; section 5 the 30-cluster minimum of a sector track.
+ *
+ * Conventions
+ *  - Units cm, GeV, Tesla.  Sector-local frame: x along the sector's centre
+ *    line (pad rows at fixed x), y across it, z along the beam.
+ *  - Track state at a row: (y, z, sin phi, tan lambda, q/pT), phi the angle
+ *    to the local x axis.  Curvature kappa = 0.00299792458 * Bz * q/pT.
+ *  - Clusters of an event are one structure-of-arrays, sorted by
+ *    (sector slot, row); the order inside a row is free.  Cluster indices in
+ *    every output are event-global int32 indices into that array.
+ *  - The device path computes in FP32.
+ *
+ * Pointers: every array inside tpc_event and tpc_tracks is DEVICE memory on
+ * the context's GPU; tpc_geometry.row_x, tpc_params and the size fields
+ * tpc_tracks.n_tracks / n_track_clusters are HOST memory.  The caller owns
+ * all of them; the library keeps no pointer after a call returns.
+ *
+ * Errors: every call returns TPC_OK (0) or a TPC_ERR_* code and never throws;
+ * tpc_last_error() gives a message for the calling thread.
+ *
+ * Threads: a context may be used by one thread at a time.  Calls that share
+ * a context are serialised by the caller.
+ */
+#ifndef TPC_TRACK_H
+#define TPC_TRACK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  TPC_OK = 0,
+  TPC_ERR_INVALID_ARG = 1, /* bad sizes, null pointers, bad offsets or params */
+  TPC_ERR_CAPACITY = 2,    /* output arrays too small; required sizes written */
+  TPC_ERR_OOM = 3,         /* device memory beyond the context budget */
+  TPC_ERR_DEVICE = 4,      /* a HIP call failed */
+  TPC_ERR_OVERFLOW = 5,    /* internal tracklet buffer too small after retry */
+  TPC_ERR_BUSY = 6         /* server: event not admitted now, try again */
+};
+
+#define TPC_MAX_ROWS 160
+
+typedef struct tpc_ctx tpc_ctx;
+
+/* Pad-row geometry of one sector (section 1: 159 rows per sector). */
+typedef struct {
+  int32_t n_rows;        /* rows per sector, 3 .. TPC_MAX_ROWS */
+  const float* row_x;    /* HOST [n_rows]: local x of each row, strictly increasing */
+  float tan_half_angle;  /* sector half opening: a row spans |y| <= x*tan_half_angle */
+  float z_max;           /* drift length: |z| <= z_max */
+} tpc_geometry;
+
+/* One event (section 1: 2 x 18 trapezoidal sectors tracked independently). */
+typedef struct {
+  int32_t n_sectors;          /* sector slots in this event (1 .. 4096) */
+  const int32_t* sector_id;   /* DEVICE [n_sectors]: physical sector of each slot,
+                                 copied to the output only */
+  int64_t n_clusters;         /* 0 .. 2^31 - 1 */
+  const float* y;             /* DEVICE [n_clusters] local y */
+  const float* z;             /* DEVICE [n_clusters] z */
+  const int32_t* row_offsets; /* DEVICE [n_sectors*n_rows + 1]: row (s, r) holds
+                                 clusters [off[s*n_rows + r], off[s*n_rows + r + 1]);
+                                 off[0] = 0, off[last] = n_clusters, non-decreasing.
+                                 Violations are detected on the device and return
+                                 TPC_ERR_INVALID_ARG. */
+} tpc_event;
+
+/* Constants of the method.  alpha = 6 (section 3.1) and min_clusters = 30
+ * (section 5) are the paper's; it gives no values for the others. */
+typedef struct {
+  float sigma_y, sigma_z;   /* cluster resolution (cm) */
+  float nf_win_y, nf_win_z; /* neighbours finder: |dy|, |dz| window on rows k+-1 */
+  float nf_chi2_max;        /* neighbours finder: straight-line chi^2 cut */
+  int32_t min_seed_len;     /* shortest chain of one-to-one links used as a seed */
+  float chi2_gate;          /* construction: chi^2 condition for collecting a cluster */
+  int32_t max_miss;         /* construction: stop after more consecutive empty rows */
+  float max_sinphi;         /* construction: |sin phi| limit */
+  float alpha, beta;        /* weight w = n (alpha - (chi2/ndf)/beta) */
+  int32_t min_clusters;     /* pre-cut for competing and final cut on owned clusters */
+  float min_pt;             /* low-momentum cut (GeV), not applied when Bz == 0 */
+  float prior_sinphi, prior_tanl, prior_qpt; /* initial variances of the fit */
+  int32_t max_tracklets;    /* tracklet reservation, 0 = automatic (grown on overflow) */
+} tpc_params;
+
+/* Caller-allocated outputs. */
+typedef struct {
+  int32_t cap_tracks;          /* rows of track_par / track_meta */
+  int32_t cap_track_clusters;  /* length of track_cluster */
+  int32_t* n_tracks;           /* HOST out: number of tracks (also on CAPACITY) */
+  int32_t* n_track_clusters;   /* HOST out: clusters in all tracks (also on CAPACITY) */
+  float* track_par;            /* DEVICE [cap_tracks][8]: x, y, z, sinphi, tanl, q/pT
+                                  at the innermost collected cluster, chi2, ndf */
+  int32_t* track_meta;         /* DEVICE [cap_tracks][4]: sector_id, n_clusters,
+                                  first (offset into track_cluster), seed id */
+  int32_t* track_cluster;      /* DEVICE [cap_track_clusters]: cluster indices,
+                                  row-ascending per track */
+  int32_t* cluster_track;      /* DEVICE [n_clusters]: track index or -1 */
+} tpc_tracks;
+
+/* Fill p with the default constants. */
+void tpc_params_default(tpc_params* p);
+
+/* Host-only argument checks of tpc_track_event (sizes, pointers, geometry,
+ * parameters); touches no device memory and needs no GPU.  Device-side
+ * checks (offsets, non-finite coordinates) happen in tpc_track_event. */
+int tpc_validate(const tpc_event* ev, const tpc_geometry* geo, const tpc_params* params);
+
+/* Create a context on HIP device `device` that may hold up to
+ * hbm_budget_bytes of scratch memory (0 = no limit).  Scratch is allocated on
+ * first use and grows as needed. */
+int tpc_ctx_create(int device, size_t hbm_budget_bytes, tpc_ctx** out);
+void tpc_ctx_destroy(tpc_ctx* ctx);
+
+/* Track one event (sections 1, 3.1, 3.2).  All kernels are enqueued on
+ * hip_stream (a hipStream_t, NULL = default stream); the call returns after
+ * the stream has finished this event, with tracks sorted by (sector slot,
+ * seed id) and each track's clusters in row order.
+ * Returns TPC_ERR_CAPACITY with *n_tracks / *n_track_clusters set when the
+ * outputs are too small (their contents are then unspecified). */
+int tpc_track_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float bz_tesla,
+                    const tpc_params* params, tpc_tracks* out, void* hip_stream);
+
+/* Stage-by-stage access for checks (same kernels as tpc_track_event).
+ * Runs the neighbours finder and the evolution step and copies the link
+ * arrays into DEVICE buffers of n_clusters int32 each (any may be NULL):
+ * up/dn before evolution, up2/dn2 after it. */
+int tpc_debug_links(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo,
+                    const tpc_params* params, int32_t* up, int32_t* dn, int32_t* up2,
+                    int32_t* dn2, void* hip_stream);
+
+/* Runs the path up to tracklet construction and copies the tracklets into
+ * DEVICE buffers: seeds [cap] (start cluster of each tracklet, increasing),
+ * hits [cap][n_rows] (cluster per row or -1, valid on [row_lo, row_hi]),
+ * row_lo, row_hi, n (0 = dropped), ndf [cap] int32, chi2 [cap] float,
+ * par [cap][6] float (x, y, z, sinphi, tanl, q/pT).  *n_tracklets (HOST)
+ * receives the count; TPC_ERR_CAPACITY if it exceeds cap. */
+int tpc_debug_tracklets(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo,
+                        float bz_tesla, const tpc_params* params, int32_t cap,
+                        int32_t* n_tracklets, int32_t* seeds, int32_t* hits, int32_t* row_lo,
+                        int32_t* row_hi, int32_t* n, int32_t* ndf, float* chi2, float* par,
+                        void* hip_stream);
+
+/* ---- measurement -------------------------------------------------------
+ * Kernels of one event are numbered 0 .. tpc_kernel_count()-1 in launch
+ * order; tpc_kernel_name(i) names them.  With a non-zero mask, later calls
+ * record a HIP event pair on the call's stream around each selected kernel
+ * (bit i = kernel i) and add the elapsed time to per-kernel totals. */
+int tpc_kernel_count(void);
+const char* tpc_kernel_name(int i);
+int tpc_ctx_set_timing(tpc_ctx* ctx, uint32_t kernel_mask);
+/* Totals since the last reset: kernel_ms / kernel_launches [tpc_kernel_count()]
+ * and work[5] = events, tracklets, constructor helix steps, Kalman updates,
+ * candidate clusters tested (any pointer may be NULL). */
+int tpc_ctx_get_stats(tpc_ctx* ctx, double* kernel_ms, int64_t* kernel_launches, int64_t* work);
+int tpc_ctx_reset_stats(tpc_ctx* ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* tpc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TPC_TRACK_H */

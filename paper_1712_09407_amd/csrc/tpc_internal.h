@@ -1,0 +1,114 @@
+// Internal interface between the host runtime (tpc_runtime.cpp) and the
+// kernels (tpc_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tpc_track.h"
+
+namespace tpc {
+
+// Per-call constants, passed by value as a kernel argument (no copies needed).
+struct KParams {
+  float row_x[TPC_MAX_ROWS];
+  int32_t n_rows;
+  float tan_half, z_max, bz, k_curv;  // k_curv = 0.00299792458 * bz
+  float sigma_y, sigma_z, sy2, sz2;
+  float nf_win_y, nf_win_z, nf_chi2_max;
+  int32_t min_seed_len;
+  float chi2_gate;
+  int32_t max_miss;
+  float max_sinphi;
+  float alpha, beta;
+  int32_t min_clusters;
+  float max_qpt;  // 1 / min_pt
+  float prior_sinphi, prior_tanl, prior_qpt;
+};
+
+struct DevEvent {
+  const float* y;
+  const float* z;
+  const int32_t* ro;
+  const int32_t* sector_id;
+  int32_t n_sectors;
+  int32_t n_clusters;
+};
+
+// Per-row search grid: clusters of a row counting-sorted into ny x nz bins.
+struct RowGrid {
+  float y0, z0, iby, ibz;
+  int32_t ny, nz, bin_base, n;
+};
+
+enum Counter {
+  C_ERR = 0,        // error bits
+  C_NONFINITE = 1,  // clusters with a non-finite coordinate
+  C_SEEDS = 2,      // tracklets found (may exceed the reservation)
+  C_TRACKS = 3,
+  C_TRACK_CLUSTERS = 4,
+  C_STEPS = 5,      // constructor: helix steps taken
+  C_UPDATES = 6,    // constructor: Kalman updates
+  C_CANDS = 7,      // constructor: candidate clusters tested against the gate
+  C_COUNT = 16
+};
+enum ErrBits { E_OFFSETS = 1, E_NONFINITE = 2, E_TL_OVERFLOW = 4, E_CAPACITY = 8 };
+
+constexpr int kHitStride = 160;  // per-tracklet row slots (>= n_rows, padded)
+
+// Device scratch of one event.
+struct Scratch {
+  int32_t* counters;       // [C_COUNT]
+  RowGrid* grid;           // [R]
+  int32_t* bins;           // [N + R + 1]
+  float2* g_yz;            // [N] grid order
+  int32_t* g_id;           // [N] grid order -> event index
+  int32_t *up, *dn;        // [N]
+  int32_t *up2, *dn2;      // [N]
+  uint8_t* start;          // [N]
+  unsigned long long* own; // [N] owner key per cluster
+  int32_t* row_cnt;        // [R + 1] seeds per row, then exclusive offsets
+  int32_t cap_tl;          // tracklet reservation T
+  int32_t* seeds;          // [T]
+  int32_t* seed_rs;        // [T]
+  int32_t* hits;           // [T * kHitStride]
+  int32_t *row_lo, *row_hi, *n, *ndf;  // [T]
+  float* chi2;             // [T]
+  float* par;              // [T * 6]
+  unsigned long long* key; // [T]
+  int32_t *owned, *kept;   // [T]
+  int32_t *trk_idx, *trk_off; // [T]
+};
+
+struct Outputs {
+  int32_t cap_tracks, cap_track_clusters;
+  float* track_par;
+  int32_t* track_meta;
+  int32_t* track_cluster;
+  int32_t* cluster_track;
+};
+
+size_t scratch_bytes(int64_t n_clusters, int64_t n_rowslots, int64_t cap_tl);
+void scratch_carve(void* base, int64_t n_clusters, int64_t n_rowslots, int64_t cap_tl,
+                   Scratch* sc);
+
+// Kernels of one event, in launch order (index into timing tables).
+enum KernelId {
+  K_ZERO, K_GRID, K_NF, K_EVO, K_SCAN_ROWS, K_SEED_WRITE, K_CONSTRUCT, K_ASSIGN, K_SELECT,
+  K_SCAN_TL, K_OUTPUT, K_NUM
+};
+extern const char* const kKernelNames[K_NUM];
+
+// Optional HIP events recorded around selected kernels (mask bit = KernelId).
+struct KernelTimer {
+  uint32_t mask = 0;
+  hipEvent_t ev[K_NUM][2] = {};
+};
+
+// Stage groups; each enqueues its kernels on `st` and returns the first error.
+enum Stage { STAGE_LINKS = 1, STAGE_SEEDS = 2, STAGE_TRACKLETS = 3, STAGE_ALL = 4 };
+hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& sc,
+                         const Outputs& out, int upto, hipStream_t st,
+                         const KernelTimer* timer = nullptr);
+
+}  // namespace tpc

@@ -1,0 +1,433 @@
+// Host runtime of the C ABI (include/tpc_track.h): argument validation,
+// device scratch arena, launch of the per-event kernel sequence, overflow
+// retry and error reporting.  No exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "tpc_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(TPC_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace
+
+struct tpc_ctx {
+  int device = 0;
+  size_t budget = 0;        // 0 = unlimited
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
+  int32_t* h_counters = nullptr;  // pinned
+  int64_t learned_tl = 0;   // tracklet reservation learned from overflows
+  tpc::KernelTimer timer;   // HIP events around selected kernels
+  bool timer_ready = false;
+  double kernel_ms[tpc::K_NUM] = {};
+  int64_t kernel_launches[tpc::K_NUM] = {};
+  int64_t work[5] = {};     // events, tracklets, helix steps, updates, candidates
+};
+
+namespace tpc {
+
+// Host-side checks of everything that can be checked without touching device
+// memory.  Offsets and coordinates are checked on the device.
+int validate(const tpc_event* ev, const tpc_geometry* geo, const tpc_params* p) {
+  if (!ev || !geo || !p) return fail(TPC_ERR_INVALID_ARG, "null event, geometry or params");
+  if (geo->n_rows < 3 || geo->n_rows > TPC_MAX_ROWS)
+    return fail(TPC_ERR_INVALID_ARG, "n_rows %d outside [3, %d]", geo->n_rows, TPC_MAX_ROWS);
+  if (!geo->row_x) return fail(TPC_ERR_INVALID_ARG, "row_x is null");
+  for (int r = 0; r < geo->n_rows; ++r) {
+    if (!std::isfinite(geo->row_x[r]) || geo->row_x[r] <= 0.f)
+      return fail(TPC_ERR_INVALID_ARG, "row_x[%d] not finite and positive", r);
+    if (r && !(geo->row_x[r] > geo->row_x[r - 1]))
+      return fail(TPC_ERR_INVALID_ARG, "row_x not strictly increasing at %d", r);
+  }
+  if (!(geo->tan_half_angle > 0.f) || !std::isfinite(geo->tan_half_angle))
+    return fail(TPC_ERR_INVALID_ARG, "tan_half_angle must be positive");
+  if (!(geo->z_max > 0.f) || !std::isfinite(geo->z_max))
+    return fail(TPC_ERR_INVALID_ARG, "z_max must be positive");
+  if (ev->n_sectors < 1 || ev->n_sectors > 4096)
+    return fail(TPC_ERR_INVALID_ARG, "n_sectors %d outside [1, 4096]", ev->n_sectors);
+  if (ev->n_clusters < 0 || ev->n_clusters > 0x7fffffffLL)
+    return fail(TPC_ERR_INVALID_ARG, "n_clusters %lld outside [0, 2^31-1]",
+                (long long)ev->n_clusters);
+  if ((int64_t)ev->n_sectors * geo->n_rows + ev->n_clusters + 1 > 0x7fffffffLL)
+    return fail(TPC_ERR_INVALID_ARG, "event too large for int32 indexing");
+  if (!ev->row_offsets || !ev->sector_id)
+    return fail(TPC_ERR_INVALID_ARG, "row_offsets or sector_id is null");
+  if (ev->n_clusters > 0 && (!ev->y || !ev->z)) return fail(TPC_ERR_INVALID_ARG, "y or z is null");
+  auto pos = [](float v) { return std::isfinite(v) && v > 0.f; };
+  if (!pos(p->sigma_y) || !pos(p->sigma_z)) return fail(TPC_ERR_INVALID_ARG, "sigma must be > 0");
+  if (!pos(p->nf_win_y) || !pos(p->nf_win_z)) return fail(TPC_ERR_INVALID_ARG, "nf window must be > 0");
+  if (!(p->nf_chi2_max >= 0.f)) return fail(TPC_ERR_INVALID_ARG, "nf_chi2_max must be >= 0");
+  if (p->min_seed_len < 2 || p->min_seed_len > geo->n_rows)
+    return fail(TPC_ERR_INVALID_ARG, "min_seed_len must be in [2, n_rows]");
+  if (!pos(p->chi2_gate)) return fail(TPC_ERR_INVALID_ARG, "chi2_gate must be > 0");
+  if (p->max_miss < 0) return fail(TPC_ERR_INVALID_ARG, "max_miss must be >= 0");
+  if (!(p->max_sinphi > 0.f && p->max_sinphi < 1.f))
+    return fail(TPC_ERR_INVALID_ARG, "max_sinphi must be in (0, 1)");
+  if (!std::isfinite(p->alpha) || !std::isfinite(p->beta) || p->beta == 0.f)
+    return fail(TPC_ERR_INVALID_ARG, "alpha must be finite, beta finite and non-zero");
+  if (p->min_clusters < 3) return fail(TPC_ERR_INVALID_ARG, "min_clusters must be >= 3");
+  if (!pos(p->min_pt)) return fail(TPC_ERR_INVALID_ARG, "min_pt must be > 0");
+  if (!pos(p->prior_sinphi) || !pos(p->prior_tanl) || !pos(p->prior_qpt))
+    return fail(TPC_ERR_INVALID_ARG, "prior variances must be > 0");
+  if (p->max_tracklets < 0) return fail(TPC_ERR_INVALID_ARG, "max_tracklets must be >= 0");
+  return TPC_OK;
+}
+
+KParams make_kparams(const tpc_geometry* geo, float bz, const tpc_params* p) {
+  KParams k;
+  std::memset(&k, 0, sizeof(k));
+  for (int r = 0; r < geo->n_rows; ++r) k.row_x[r] = geo->row_x[r];
+  k.n_rows = geo->n_rows;
+  k.tan_half = geo->tan_half_angle;
+  k.z_max = geo->z_max;
+  k.bz = bz;
+  k.k_curv = 0.00299792458f * bz;
+  k.sigma_y = p->sigma_y;
+  k.sigma_z = p->sigma_z;
+  k.sy2 = p->sigma_y * p->sigma_y;
+  k.sz2 = p->sigma_z * p->sigma_z;
+  k.nf_win_y = p->nf_win_y;
+  k.nf_win_z = p->nf_win_z;
+  k.nf_chi2_max = p->nf_chi2_max;
+  k.min_seed_len = p->min_seed_len;
+  k.chi2_gate = p->chi2_gate;
+  k.max_miss = p->max_miss;
+  k.max_sinphi = p->max_sinphi;
+  k.alpha = p->alpha;
+  k.beta = p->beta;
+  k.min_clusters = p->min_clusters;
+  k.max_qpt = 1.f / p->min_pt;
+  k.prior_sinphi = p->prior_sinphi;
+  k.prior_tanl = p->prior_tanl;
+  k.prior_qpt = p->prior_qpt;
+  return k;
+}
+
+DevEvent make_devevent(const tpc_event* ev) {
+  DevEvent d;
+  d.y = ev->y;
+  d.z = ev->z;
+  d.ro = ev->row_offsets;
+  d.sector_id = ev->sector_id;
+  d.n_sectors = ev->n_sectors;
+  d.n_clusters = (int32_t)ev->n_clusters;
+  return d;
+}
+
+int64_t default_tracklets(const tpc_ctx* ctx, int64_t N, const tpc_params* p) {
+  if (p->max_tracklets > 0) return p->max_tracklets;
+  int64_t t = N / 24 + 256;  // central events start about one tracklet per 80 clusters
+  if (ctx->learned_tl > t) t = ctx->learned_tl;
+  return t;
+}
+
+int ensure_arena(tpc_ctx* ctx, int64_t N, int64_t R, int64_t T, hipStream_t st) {
+  size_t need = scratch_bytes(N, R, T);
+  if (need <= ctx->arena_bytes) return TPC_OK;
+  size_t want = need + need / 4;
+  if (ctx->budget && want > ctx->budget) want = need;
+  if (ctx->budget && need > ctx->budget)
+    return fail(TPC_ERR_OOM, "scratch of %zu bytes exceeds the context budget %zu", need,
+                ctx->budget);
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  if (ctx->arena) {
+    e = hipFree(ctx->arena);
+    ctx->arena = nullptr;
+    ctx->arena_bytes = 0;
+    if (e != hipSuccess) return hip_fail(e, "hipFree");
+  }
+  e = hipMalloc(&ctx->arena, want);
+  if (e != hipSuccess) {
+    ctx->arena = nullptr;
+    (void)hipGetLastError();
+    return fail(TPC_ERR_OOM, "hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+  }
+  ctx->arena_bytes = want;
+  return TPC_OK;
+}
+
+// Runs the kernels up to `upto`, reads the counters back, maps device error
+// bits to return codes.  On a tracklet overflow the reservation is raised and
+// the event is run once more (results do not depend on the reservation).
+int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float bz,
+              const tpc_params* p, const Outputs& out, int upto, hipStream_t st,
+              Scratch* sc_out) {
+  int rc = validate(ev, geo, p);
+  if (rc) return rc;
+  if (!std::isfinite(bz)) return fail(TPC_ERR_INVALID_ARG, "bz must be finite");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  const int64_t N = ev->n_clusters, R = (int64_t)ev->n_sectors * geo->n_rows;
+  const KParams kp = make_kparams(geo, bz, p);
+  const DevEvent dev = make_devevent(ev);
+  int64_t T = default_tracklets(ctx, N, p);
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    rc = ensure_arena(ctx, N, R, T, st);
+    if (rc) return rc;
+    Scratch sc;
+    scratch_carve(ctx->arena, N, R, T, &sc);
+    const bool timed = ctx->timer.mask != 0;
+    e = enqueue_event(dev, kp, sc, out, upto, st, timed ? &ctx->timer : nullptr);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    e = hipMemcpyAsync(ctx->h_counters, sc.counters, sizeof(int32_t) * C_COUNT,
+                       hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(counters)");
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    const int32_t* c = ctx->h_counters;
+    if (c[C_ERR] & E_OFFSETS)
+      return fail(TPC_ERR_INVALID_ARG, "row_offsets are not a valid non-decreasing partition "
+                                       "of [0, n_clusters]");
+    if (c[C_ERR] & E_NONFINITE)
+      return fail(TPC_ERR_INVALID_ARG, "%d clusters have non-finite coordinates", c[C_NONFINITE]);
+    if (upto >= STAGE_TRACKLETS && (c[C_ERR] & E_TL_OVERFLOW)) {
+      const int64_t need = c[C_SEEDS];
+      if (p->max_tracklets > 0 || attempt == 1)
+        return fail(TPC_ERR_OVERFLOW, "%lld tracklets exceed the reservation of %lld",
+                    (long long)need, (long long)T);
+      T = need + need / 8 + 64;
+      if (T > ctx->learned_tl) ctx->learned_tl = T;
+      continue;
+    }
+    if (timed) {
+      const int last = upto >= STAGE_ALL ? K_OUTPUT
+                       : upto >= STAGE_TRACKLETS ? K_CONSTRUCT
+                       : upto >= STAGE_SEEDS ? K_SEED_WRITE : K_EVO;
+      for (int k = 0; k <= last; ++k) {
+        if (!(ctx->timer.mask >> k & 1u)) continue;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ctx->timer.ev[k][0], ctx->timer.ev[k][1]) == hipSuccess) {
+          ctx->kernel_ms[k] += ms;
+          ctx->kernel_launches[k] += 1;
+        }
+      }
+    }
+    ctx->work[0] += 1;
+    ctx->work[1] += c[C_SEEDS];
+    ctx->work[2] += (uint32_t)c[C_STEPS];
+    ctx->work[3] += (uint32_t)c[C_UPDATES];
+    ctx->work[4] += (uint32_t)c[C_CANDS];
+    if (sc_out) *sc_out = sc;
+    return TPC_OK;
+  }
+  return fail(TPC_ERR_OVERFLOW, "tracklet reservation retry failed");
+}
+
+}  // namespace tpc
+
+using namespace tpc;
+
+extern "C" {
+
+void tpc_params_default(tpc_params* p) {
+  if (!p) return;
+  p->sigma_y = 0.1f;
+  p->sigma_z = 0.1f;
+  p->nf_win_y = 4.0f;
+  p->nf_win_z = 4.0f;
+  p->nf_chi2_max = 25.0f;
+  p->min_seed_len = 3;
+  p->chi2_gate = 16.0f;
+  p->max_miss = 10;
+  p->max_sinphi = 0.95f;
+  p->alpha = 6.0f;       // section 3.1
+  p->beta = 1.0f;
+  p->min_clusters = 30;  // section 5
+  p->min_pt = 0.1f;
+  p->prior_sinphi = 1.0f;
+  p->prior_tanl = 1.0f;
+  p->prior_qpt = 100.0f;
+  p->max_tracklets = 0;
+}
+
+const char* tpc_last_error(void) { return g_err.c_str(); }
+
+int tpc_validate(const tpc_event* ev, const tpc_geometry* geo, const tpc_params* params) {
+  return validate(ev, geo, params);
+}
+
+int tpc_ctx_create(int device, size_t hbm_budget_bytes, tpc_ctx** out) {
+  if (!out) return fail(TPC_ERR_INVALID_ARG, "out is null");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+  if (device < 0 || device >= n) return fail(TPC_ERR_INVALID_ARG, "device %d of %d", device, n);
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  tpc_ctx* c = new (std::nothrow) tpc_ctx();
+  if (!c) return fail(TPC_ERR_OOM, "host allocation failed");
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  e = hipHostMalloc((void**)&c->h_counters, sizeof(int32_t) * C_COUNT, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "hipHostMalloc");
+  }
+  *out = c;
+  return TPC_OK;
+}
+
+int tpc_kernel_count(void) { return K_NUM; }
+
+const char* tpc_kernel_name(int i) { return (i >= 0 && i < K_NUM) ? kKernelNames[i] : ""; }
+
+int tpc_ctx_set_timing(tpc_ctx* ctx, uint32_t kernel_mask) {
+  if (!ctx) return fail(TPC_ERR_INVALID_ARG, "ctx is null");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if (kernel_mask && !ctx->timer_ready) {
+    for (int k = 0; k < K_NUM; ++k)
+      for (int j = 0; j < 2; ++j) {
+        e = hipEventCreate(&ctx->timer.ev[k][j]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+      }
+    ctx->timer_ready = true;
+  }
+  ctx->timer.mask = kernel_mask & ((1u << K_NUM) - 1u);
+  return TPC_OK;
+}
+
+int tpc_ctx_get_stats(tpc_ctx* ctx, double* kernel_ms, int64_t* kernel_launches, int64_t* work) {
+  if (!ctx) return fail(TPC_ERR_INVALID_ARG, "ctx is null");
+  for (int k = 0; k < K_NUM; ++k) {
+    if (kernel_ms) kernel_ms[k] = ctx->kernel_ms[k];
+    if (kernel_launches) kernel_launches[k] = ctx->kernel_launches[k];
+  }
+  if (work)
+    for (int i = 0; i < 5; ++i) work[i] = ctx->work[i];
+  return TPC_OK;
+}
+
+int tpc_ctx_reset_stats(tpc_ctx* ctx) {
+  if (!ctx) return fail(TPC_ERR_INVALID_ARG, "ctx is null");
+  for (int k = 0; k < K_NUM; ++k) {
+    ctx->kernel_ms[k] = 0.0;
+    ctx->kernel_launches[k] = 0;
+  }
+  for (int i = 0; i < 5; ++i) ctx->work[i] = 0;
+  return TPC_OK;
+}
+
+void tpc_ctx_destroy(tpc_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  if (ctx->timer_ready)
+    for (int k = 0; k < K_NUM; ++k)
+      for (int j = 0; j < 2; ++j) (void)hipEventDestroy(ctx->timer.ev[k][j]);
+  if (ctx->arena) (void)hipFree(ctx->arena);
+  if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
+  delete ctx;
+}
+
+int tpc_track_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float bz_tesla,
+                    const tpc_params* params, tpc_tracks* out, void* hip_stream) {
+  if (!ctx) return fail(TPC_ERR_INVALID_ARG, "ctx is null");
+  if (!out || !out->n_tracks || !out->n_track_clusters)
+    return fail(TPC_ERR_INVALID_ARG, "out or its size pointers are null");
+  if (out->cap_tracks < 0 || out->cap_track_clusters < 0)
+    return fail(TPC_ERR_INVALID_ARG, "negative capacity");
+  if ((out->cap_tracks > 0 && (!out->track_par || !out->track_meta)) ||
+      (out->cap_track_clusters > 0 && !out->track_cluster))
+    return fail(TPC_ERR_INVALID_ARG, "output array is null");
+  if (ev && ev->n_clusters > 0 && !out->cluster_track)
+    return fail(TPC_ERR_INVALID_ARG, "cluster_track is null");
+  Outputs o{out->cap_tracks, out->cap_track_clusters, out->track_par, out->track_meta,
+            out->track_cluster, out->cluster_track};
+  hipStream_t st = (hipStream_t)hip_stream;
+  int rc = run_event(ctx, ev, geo, bz_tesla, params, o, STAGE_ALL, st, nullptr);
+  if (rc) return rc;
+  const int32_t* c = ctx->h_counters;
+  *out->n_tracks = c[C_TRACKS];
+  *out->n_track_clusters = c[C_TRACK_CLUSTERS];
+  if (c[C_ERR] & E_CAPACITY)
+    return fail(TPC_ERR_CAPACITY, "need %d tracks / %d track clusters, have %d / %d",
+                c[C_TRACKS], c[C_TRACK_CLUSTERS], out->cap_tracks, out->cap_track_clusters);
+  return TPC_OK;
+}
+
+int tpc_debug_links(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo,
+                    const tpc_params* params, int32_t* up, int32_t* dn, int32_t* up2,
+                    int32_t* dn2, void* hip_stream) {
+  if (!ctx) return fail(TPC_ERR_INVALID_ARG, "ctx is null");
+  Outputs o{0, 0, nullptr, nullptr, nullptr, nullptr};
+  hipStream_t st = (hipStream_t)hip_stream;
+  Scratch sc;
+  int rc = run_event(ctx, ev, geo, 0.f, params, o, STAGE_LINKS, st, &sc);
+  if (rc) return rc;
+  const size_t nb = sizeof(int32_t) * (size_t)ev->n_clusters;
+  int32_t* dst[4] = {up, dn, up2, dn2};
+  int32_t* src[4] = {sc.up, sc.dn, sc.up2, sc.dn2};
+  for (int i = 0; i < 4; ++i) {
+    if (!dst[i] || nb == 0) continue;
+    hipError_t e = hipMemcpyAsync(dst[i], src[i], nb, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(links)");
+  }
+  hipError_t e = hipStreamSynchronize(st);
+  return e == hipSuccess ? TPC_OK : hip_fail(e, "hipStreamSynchronize");
+}
+
+int tpc_debug_tracklets(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo,
+                        float bz_tesla, const tpc_params* params, int32_t cap,
+                        int32_t* n_tracklets, int32_t* seeds, int32_t* hits, int32_t* row_lo,
+                        int32_t* row_hi, int32_t* n, int32_t* ndf, float* chi2, float* par,
+                        void* hip_stream) {
+  if (!ctx || !n_tracklets || cap < 0) return fail(TPC_ERR_INVALID_ARG, "bad arguments");
+  Outputs o{0, 0, nullptr, nullptr, nullptr, nullptr};
+  hipStream_t st = (hipStream_t)hip_stream;
+  Scratch sc;
+  int rc = run_event(ctx, ev, geo, bz_tesla, params, o, STAGE_TRACKLETS, st, &sc);
+  if (rc) return rc;
+  const int32_t cnt = ctx->h_counters[C_SEEDS];
+  *n_tracklets = cnt;
+  if (cnt > cap) return fail(TPC_ERR_CAPACITY, "%d tracklets, capacity %d", cnt, cap);
+  if (cnt > 0) {
+    const size_t i4 = sizeof(int32_t) * (size_t)cnt;
+    struct {
+      void* d;
+      const void* s;
+      size_t b;
+    } cp[] = {{seeds, sc.seeds, i4},   {row_lo, sc.row_lo, i4}, {row_hi, sc.row_hi, i4},
+              {n, sc.n, i4},           {ndf, sc.ndf, i4},       {chi2, sc.chi2, i4},
+              {par, sc.par, 6 * i4}};
+    for (auto& x : cp) {
+      if (!x.d) continue;
+      hipError_t e = hipMemcpyAsync(x.d, x.s, x.b, hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(tracklets)");
+    }
+    if (hits) {
+      hipError_t e = hipMemcpy2DAsync(hits, sizeof(int32_t) * geo->n_rows, sc.hits,
+                                      sizeof(int32_t) * kHitStride, sizeof(int32_t) * geo->n_rows,
+                                      cnt, hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) return hip_fail(e, "hipMemcpy2DAsync(hits)");
+    }
+  }
+  hipError_t e = hipStreamSynchronize(st);
+  return e == hipSuccess ? TPC_OK : hip_fail(e, "hipStreamSynchronize");
+}
+
+}  // extern "C"

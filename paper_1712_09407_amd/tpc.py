@@ -1,0 +1,271 @@
+"""Python binding of libtpctrack.so (the C ABI in include/tpc_track.h).
+
+Argument marshalling only: every step of the tracker runs in the library's
+HIP kernels.  PyTorch provides device memory and the stream.  If the library
+is not built, importing this module raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtpctrack.so")
+
+TPC_OK, TPC_ERR_INVALID_ARG, TPC_ERR_CAPACITY, TPC_ERR_OOM, TPC_ERR_DEVICE, \
+    TPC_ERR_OVERFLOW, TPC_ERR_BUSY = range(7)
+TPC_MAX_ROWS = 160
+
+
+class TpcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tpc error {code}: {msg}")
+        self.code = code
+
+
+class Geometry(C.Structure):
+    _fields_ = [("n_rows", C.c_int32), ("row_x", C.POINTER(C.c_float)),
+                ("tan_half_angle", C.c_float), ("z_max", C.c_float)]
+
+
+class Event(C.Structure):
+    _fields_ = [("n_sectors", C.c_int32), ("sector_id", C.c_void_p), ("n_clusters", C.c_int64),
+                ("y", C.c_void_p), ("z", C.c_void_p), ("row_offsets", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("sigma_y", C.c_float), ("sigma_z", C.c_float), ("nf_win_y", C.c_float),
+                ("nf_win_z", C.c_float), ("nf_chi2_max", C.c_float), ("min_seed_len", C.c_int32),
+                ("chi2_gate", C.c_float), ("max_miss", C.c_int32), ("max_sinphi", C.c_float),
+                ("alpha", C.c_float), ("beta", C.c_float), ("min_clusters", C.c_int32),
+                ("min_pt", C.c_float), ("prior_sinphi", C.c_float), ("prior_tanl", C.c_float),
+                ("prior_qpt", C.c_float), ("max_tracklets", C.c_int32)]
+
+
+class Tracks(C.Structure):
+    _fields_ = [("cap_tracks", C.c_int32), ("cap_track_clusters", C.c_int32),
+                ("n_tracks", C.POINTER(C.c_int32)), ("n_track_clusters", C.POINTER(C.c_int32)),
+                ("track_par", C.c_void_p), ("track_meta", C.c_void_p),
+                ("track_cluster", C.c_void_p), ("cluster_track", C.c_void_p)]
+
+
+EXPORTS = ["tpc_params_default", "tpc_validate", "tpc_ctx_create", "tpc_ctx_destroy",
+           "tpc_track_event", "tpc_debug_links", "tpc_debug_tracklets", "tpc_last_error",
+           "tpc_kernel_count", "tpc_kernel_name", "tpc_ctx_set_timing", "tpc_ctx_get_stats",
+           "tpc_ctx_reset_stats"]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    L.tpc_params_default.argtypes = [P(Params)]
+    L.tpc_params_default.restype = None
+    L.tpc_validate.argtypes = [P(Event), P(Geometry), P(Params)]
+    L.tpc_ctx_create.argtypes = [C.c_int, C.c_size_t, P(C.c_void_p)]
+    L.tpc_ctx_destroy.argtypes = [C.c_void_p]
+    L.tpc_ctx_destroy.restype = None
+    L.tpc_track_event.argtypes = [C.c_void_p, P(Event), P(Geometry), C.c_float, P(Params),
+                                  P(Tracks), C.c_void_p]
+    L.tpc_debug_links.argtypes = [C.c_void_p, P(Event), P(Geometry), P(Params), C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.tpc_debug_tracklets.argtypes = [C.c_void_p, P(Event), P(Geometry), C.c_float, P(Params),
+                                      C.c_int32, P(C.c_int32)] + [C.c_void_p] * 9
+    L.tpc_kernel_count.argtypes = []
+    L.tpc_kernel_name.argtypes = [C.c_int]
+    L.tpc_kernel_name.restype = C.c_char_p
+    L.tpc_ctx_set_timing.argtypes = [C.c_void_p, C.c_uint32]
+    L.tpc_ctx_get_stats.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int64), P(C.c_int64)]
+    L.tpc_ctx_reset_stats.argtypes = [C.c_void_p]
+    L.tpc_last_error.argtypes = []
+    L.tpc_last_error.restype = C.c_char_p
+    return L
+
+
+lib = _load()
+
+
+def _check(rc):
+    if rc != TPC_OK:
+        raise TpcError(rc, lib.tpc_last_error().decode())
+
+
+def default_params(**over) -> Params:
+    p = Params()
+    lib.tpc_params_default(C.byref(p))
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def validate(e: Event, geo: Geometry, params: Params = None) -> int:
+    """Host-only argument checks; returns the TPC_* code."""
+    return lib.tpc_validate(C.byref(e), C.byref(geo), C.byref(params or default_params()))
+
+
+def last_error() -> str:
+    return lib.tpc_last_error().decode()
+
+
+def make_geometry(row_x, tan_half_angle, z_max):
+    rx = np.ascontiguousarray(row_x, np.float32)
+    g = Geometry(int(rx.shape[0]), rx.ctypes.data_as(C.POINTER(C.c_float)),
+                 float(tan_half_angle), float(z_max))
+    g._keep = rx
+    return g
+
+
+class DeviceEvent:
+    """An event resident in device memory (torch tensors on the GPU)."""
+
+    def __init__(self, y, z, row_offsets, sector_id):
+        self.y, self.z, self.row_offsets, self.sector_id = y, z, row_offsets, sector_id
+
+    @classmethod
+    def from_host(cls, y, z, row_offsets, sector_id, device="cuda"):
+        import torch
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dt)).to(device)
+        return cls(t(y, np.float32), t(z, np.float32), t(row_offsets, np.int32),
+                   t(sector_id, np.int32))
+
+    @property
+    def n_clusters(self):
+        return int(self.y.shape[0])
+
+    def cstruct(self) -> Event:
+        for a in (self.y, self.z, self.row_offsets, self.sector_id):
+            assert a.is_cuda and a.is_contiguous()
+        return Event(int(self.sector_id.shape[0]), self.sector_id.data_ptr(),
+                     self.n_clusters, self.y.data_ptr(), self.z.data_ptr(),
+                     self.row_offsets.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Tracker:
+    """One library context on one GPU."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        h = C.c_void_p()
+        _check(lib.tpc_ctx_create(int(device), int(hbm_budget_bytes), C.byref(h)))
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.tpc_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def track_event(self, ev: DeviceEvent, geo: Geometry, bz: float, params: Params = None,
+                    cap_tracks: int = None, cap_track_clusters: int = None, stream=None,
+                    out=None):
+        """Run the whole path.  Returns a dict of device tensors trimmed to size.
+        `out` may hold preallocated outputs (track_par, track_meta, track_cluster,
+        cluster_track) to avoid allocation per call."""
+        import torch
+        n = ev.n_clusters
+        dev = ev.y.device
+        if out is None:
+            ct = cap_tracks if cap_tracks is not None else max(16, n // 40)
+            cc = cap_track_clusters if cap_track_clusters is not None else max(16, n)
+            out = dict(track_par=torch.empty((ct, 8), dtype=torch.float32, device=dev),
+                       track_meta=torch.empty((ct, 4), dtype=torch.int32, device=dev),
+                       track_cluster=torch.empty(cc, dtype=torch.int32, device=dev),
+                       cluster_track=torch.empty(max(n, 1), dtype=torch.int32, device=dev))
+        nt, nc = C.c_int32(0), C.c_int32(0)
+        tr = Tracks(int(out["track_par"].shape[0]), int(out["track_cluster"].shape[0]),
+                    C.pointer(nt), C.pointer(nc), out["track_par"].data_ptr(),
+                    out["track_meta"].data_ptr(), out["track_cluster"].data_ptr(),
+                    out["cluster_track"].data_ptr())
+        e = ev.cstruct()
+        rc = lib.tpc_track_event(self._h, C.byref(e), C.byref(geo), float(bz),
+                                 C.byref(params or default_params()), C.byref(tr),
+                                 _stream_handle(stream))
+        if rc == TPC_ERR_CAPACITY and (cap_tracks is None and cap_track_clusters is None):
+            return self.track_event(ev, geo, bz, params, nt.value + 16, nc.value + 16, stream)
+        _check(rc)
+        return dict(n_tracks=nt.value, n_track_clusters=nc.value,
+                    track_par=out["track_par"][:nt.value], track_meta=out["track_meta"][:nt.value],
+                    track_cluster=out["track_cluster"][:nc.value],
+                    cluster_track=out["cluster_track"][:n])
+
+    def set_timing(self, kernels=None):
+        """Time the named kernels (None = all, [] = off) with HIP events."""
+        names = kernel_names()
+        mask = (1 << len(names)) - 1 if kernels is None else \
+            sum(1 << names.index(k) for k in kernels)
+        _check(lib.tpc_ctx_set_timing(self._h, mask))
+
+    def stats(self):
+        nk = lib.tpc_kernel_count()
+        ms = (C.c_double * nk)()
+        cnt = (C.c_int64 * nk)()
+        work = (C.c_int64 * 5)()
+        _check(lib.tpc_ctx_get_stats(self._h, ms, cnt, work))
+        names = kernel_names()
+        return dict(kernel_ms={names[i]: ms[i] for i in range(nk)},
+                    kernel_launches={names[i]: cnt[i] for i in range(nk)},
+                    events=work[0], tracklets=work[1], steps=work[2], updates=work[3],
+                    candidates=work[4])
+
+    def reset_stats(self):
+        _check(lib.tpc_ctx_reset_stats(self._h))
+
+    def track_event_raw(self, e: Event, geo: Geometry, bz: float, params: Params, tr: Tracks,
+                        stream_handle) -> int:
+        """Direct call on prebuilt structs (no allocation), for timing loops."""
+        return lib.tpc_track_event(self._h, C.byref(e), C.byref(geo), float(bz),
+                                   C.byref(params), C.byref(tr), stream_handle)
+
+    def links(self, ev: DeviceEvent, geo: Geometry, params: Params = None, stream=None):
+        import torch
+        n = max(ev.n_clusters, 1)
+        bufs = [torch.empty(n, dtype=torch.int32, device=ev.y.device) for _ in range(4)]
+        e = ev.cstruct()
+        _check(lib.tpc_debug_links(self._h, C.byref(e), C.byref(geo),
+                                   C.byref(params or default_params()),
+                                   *[b.data_ptr() for b in bufs], _stream_handle(stream)))
+        return [b[:ev.n_clusters] for b in bufs]
+
+    def tracklets(self, ev: DeviceEvent, geo: Geometry, bz: float, params: Params = None,
+                  cap: int = None, stream=None):
+        import torch
+        dev = ev.y.device
+        cap = cap if cap is not None else max(64, ev.n_clusters // 8)
+        nr = geo.n_rows
+        i32 = dict(dtype=torch.int32, device=dev)
+        b = dict(seeds=torch.empty(cap, **i32), hits=torch.empty((cap, nr), **i32),
+                 row_lo=torch.empty(cap, **i32), row_hi=torch.empty(cap, **i32),
+                 n=torch.empty(cap, **i32), ndf=torch.empty(cap, **i32),
+                 chi2=torch.empty(cap, dtype=torch.float32, device=dev),
+                 par=torch.empty((cap, 6), dtype=torch.float32, device=dev))
+        cnt = C.c_int32(0)
+        e = ev.cstruct()
+        _check(lib.tpc_debug_tracklets(
+            self._h, C.byref(e), C.byref(geo), float(bz), C.byref(params or default_params()),
+            int(cap), C.byref(cnt),
+            *[b[k].data_ptr() for k in ("seeds", "hits", "row_lo", "row_hi", "n", "ndf", "chi2",
+                                        "par")], _stream_handle(stream)))
+        k = cnt.value
+        return {name: v[:k] for name, v in b.items()}
+
+
+def kernel_names():
+    return [lib.tpc_kernel_name(i).decode() for i in range(lib.tpc_kernel_count())]
+
+
+def to_numpy(res: dict) -> dict:
+    return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in res.items()}
