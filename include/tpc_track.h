@@ -85,6 +85,8 @@ typedef struct {
   float nf_win_y, nf_win_z; /* neighbours finder: |dy|, |dz| window on rows k+-1 */
   float nf_chi2_max;        /* neighbours finder: straight-line chi^2 cut */
   int32_t min_seed_len;     /* shortest chain of one-to-one links used as a seed */
+  int32_t seed_window;      /* the seed circle uses the first, middle and last of the
+                               first min(m, seed_window) chain clusters (>= 2) */
   float chi2_gate;          /* construction: chi^2 condition for collecting a cluster */
   int32_t max_miss;         /* construction: stop after more consecutive empty rows */
   float max_sinphi;         /* construction: |sin phi| limit */

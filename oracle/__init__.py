@@ -32,6 +32,7 @@ class Params(C.Structure):
     _fields_ = [("sigma_y", C.c_double), ("sigma_z", C.c_double),
                 ("nf_win_y", C.c_double), ("nf_win_z", C.c_double),
                 ("nf_chi2_max", C.c_double), ("min_seed_len", C.c_int32),
+                ("seed_window", C.c_int32),
                 ("chi2_gate", C.c_double), ("max_miss", C.c_int32),
                 ("max_sinphi", C.c_double), ("alpha", C.c_double), ("beta", C.c_double),
                 ("min_clusters", C.c_int32), ("min_pt", C.c_double),
@@ -90,7 +91,8 @@ def lib():
         L.orc_construct.argtypes = [P(EventS), P(Geometry), C.c_double, P(Params), P(C.c_int32),
                                     C.c_int64, P(C.c_int32), P(Tracklets)]
         L.orc_select.argtypes = [P(EventS), P(Geometry), C.c_double, P(Params), C.c_int64,
-                                 P(C.c_int32), P(Tracklets), P(C.c_int32), P(C.c_int32)]
+                                 P(C.c_int32), P(Tracklets), P(C.c_double), P(C.c_int32),
+                                 P(C.c_int32)]
         L.orc_propagate.argtypes = [C.c_double, P(C.c_double), P(C.c_double), C.c_double,
                                     C.c_double, C.c_double, P(C.c_double)]
         L.orc_fit_hits.argtypes = [C.c_int32, P(C.c_double), P(C.c_double), P(C.c_double),
@@ -236,8 +238,9 @@ def construct(ev, geo, bz, up2, seeds_arr, params=None):
     return {k: v[:n_tl] for k, v in a.items()}
 
 
-def select(ev, geo, bz, ids, tl: dict, params=None):
-    """tl: dict with hits, row_lo, row_hi, n, chi2, ndf, par (float64 [n,6])."""
+def select(ev, geo, bz, ids, tl: dict, params=None, weights=None):
+    """tl: dict with hits, row_lo, row_hi, n, chi2, ndf, par (float64 [n,6]).
+    weights: optional per-tracklet weights used instead of the computed ones."""
     cx = _ctx(ev, geo)
     ids = np.ascontiguousarray(ids, np.int32)
     n_tl = int(ids.shape[0])
@@ -250,9 +253,11 @@ def select(ev, geo, bz, ids, tl: dict, params=None):
     n = int(cx.y.shape[0])
     owner = np.empty(max(n, 1), np.int32)
     keep = np.empty(max(n_tl, 1), np.int32)
+    w = None if weights is None else np.ascontiguousarray(weights, np.float64)
     rc = lib().orc_select(C.byref(cx.ev), C.byref(cx.geo), float(bz),
                           C.byref(params or default_params()), n_tl, _p(ids, C.c_int32),
-                          C.byref(s), _p(owner, C.c_int32), _p(keep, C.c_int32))
+                          C.byref(s), None if w is None else _p(w, C.c_double),
+                          _p(owner, C.c_int32), _p(keep, C.c_int32))
     if rc:
         raise RuntimeError("orc_select failed")
     return owner[:n], keep[:n_tl]

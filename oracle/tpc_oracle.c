@@ -40,6 +40,7 @@ void orc_params_default(orc_params* p) {
   p->nf_win_z = 4.0;
   p->nf_chi2_max = 25.0;
   p->min_seed_len = 3;
+  p->seed_window = 16;
   p->chi2_gate = 16.0;
   p->max_miss = 10;
   p->max_sinphi = (double)0.95f;
@@ -391,9 +392,10 @@ static void kreset_cov(kstate* s, const orc_params* p) {
 }
 
 /*
- * Seed of a tracklet from three of its clusters a (first), b (middle), e
- * (last): the circle through their (x, y) gives the curvature and the
- * direction at a; tan lambda is the z rise over the arc length a -> e.
+ * Seed of a tracklet from three chain clusters a (first), b (middle), e
+ * (last of the seed window): the circle through their (x, y) gives the
+ * curvature and the direction at a; tan lambda is the z rise over the arc
+ * length a -> e.
  * Positions at a are taken from cluster a.  With Bz = 0 the track is straight.
  */
 static void kseed(kstate* s, double xa, double ya, double za, double xb, double yb,
@@ -425,7 +427,8 @@ static void kseed(kstate* s, double xa, double ya, double za, double xb, double 
  * The paper: fit the tracklet with a Kalman filter, extrapolate to adjacent
  * rows, collect clusters that meet a chi^2 condition, refit, until no more
  * clusters are found.  Reading used:
- *   1. seed from the chain (kseed), then filter outward through the chain
+ *   1. seed from the chain (kseed: first, middle and last of the first
+ *      seed_window chain clusters), then filter outward through all chain
  *      clusters unconditionally;
  *   2. keep going outward row by row: propagate, search the row, take the
  *      cluster with the smallest (chi2, index) if chi2 <= chi2_gate, else
@@ -505,11 +508,15 @@ static void build_tracklet(const sector_ctx* sc, const int32_t* up2, int32_t sta
   int m = 0;
   for (int32_t c = start; c >= 0 && m < 1024; c = up2[c]) chain[m++] = c;
   const int k0 = row_of_cluster(sc, start);
-  const int32_t a = chain[0], b = chain[m / 2], e = chain[m - 1];
+  /* the seed circle uses the first, middle and last of the first
+     min(m, seed_window) chain clusters */
+  int ms = m < p->seed_window ? m : p->seed_window;
+  if (ms < 2) ms = m < 2 ? m : 2;
+  const int32_t a = chain[0], b = chain[ms / 2], e = chain[ms - 1];
 
   /* 1. seed and outward filter through the chain */
   kstate s;
-  kseed(&s, X[k0], Y[a], Z[a], X[k0 + m / 2], Y[b], X[k0 + m - 1], Y[e], Z[e], sc->bz, p);
+  kseed(&s, X[k0], Y[a], Z[a], X[k0 + ms / 2], Y[b], X[k0 + ms - 1], Y[e], Z[e], sc->bz, p);
   if (fabs(s.p[2]) > p->max_sinphi) return; /* dropped */
   hits[k0] = a;
   kstate last = s;
@@ -610,14 +617,14 @@ static double tl_weight(const orc_params* p, int32_t n, double chi2, int32_t ndf
 static void select_core(const orc_params* p, double bz, int32_t nr, int64_t n_tl,
                         const int32_t* ids, const int32_t* hits, const int32_t* row_lo,
                         const int32_t* row_hi, const int32_t* n, const double* chi2,
-                        const int32_t* ndf, const double* par, int64_t cbase, int64_t ncl,
-                        int32_t* owner_l, int32_t* keep) {
+                        const int32_t* ndf, const double* par, const double* weights,
+                        int64_t cbase, int64_t ncl, int32_t* owner_l, int32_t* keep) {
   double* wbest = (double*)malloc(sizeof(double) * (size_t)(ncl > 0 ? ncl : 1));
   for (int64_t c = 0; c < ncl; ++c) owner_l[c] = -1;
   for (int64_t t = 0; t < n_tl; ++t) {
     keep[t] = 0;
     if (!tl_qualifies(p, bz, n[t], par[6 * t + 5])) continue;
-    double w = tl_weight(p, n[t], chi2[t], ndf[t]);
+    double w = weights ? weights[t] : tl_weight(p, n[t], chi2[t], ndf[t]);
     for (int r = row_lo[t]; r <= row_hi[t]; ++r) {
       int32_t c = hits[t * nr + r];
       if (c < 0) continue;
@@ -688,7 +695,7 @@ static void track_sector(const orc_event* ev, const orc_geometry* geo, double bz
   }
   int32_t* owner = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ncl + 1));
   int32_t* keep = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_tl + 1));
-  select_core(prm, bz, nr, n_tl, ids, hits, row_lo, row_hi, nn, chi2, ndf, par, cbase, ncl,
+  select_core(prm, bz, nr, n_tl, ids, hits, row_lo, row_hi, nn, chi2, ndf, par, NULL, cbase, ncl,
               owner, keep);
   /* output: kept tracklets in id order, owned clusters in row order */
   int64_t nt = 0, nc = 0;
@@ -910,11 +917,11 @@ int orc_construct(const orc_event* ev, const orc_geometry* geo, double bz,
 }
 
 int orc_select(const orc_event* ev, const orc_geometry* geo, double bz, const orc_params* prm,
-               int64_t n_tl, const int32_t* ids, const orc_tracklets* tl, int32_t* owner,
-               int32_t* keep) {
+               int64_t n_tl, const int32_t* ids, const orc_tracklets* tl, const double* weights,
+               int32_t* owner, int32_t* keep) {
   if (check_event(ev, geo) || !prm || !tl || !owner || !keep || n_tl < 0) return -1;
   select_core(prm, bz, geo->n_rows, n_tl, ids, tl->hits, tl->row_lo, tl->row_hi, tl->n,
-              tl->chi2, tl->ndf, tl->par, 0, ev->n_clusters, owner, keep);
+              tl->chi2, tl->ndf, tl->par, weights, 0, ev->n_clusters, owner, keep);
   return 0;
 }
 
@@ -939,8 +946,10 @@ int orc_fit_hits(int32_t n, const double* x, const double* y, const double* z, d
   if (n < 3 || !x || !y || !z || !prm || !st || !cov || !chi2 || !ndf) return -1;
   const double sy2 = prm->sigma_y * prm->sigma_y, sz2 = prm->sigma_z * prm->sigma_z;
   kstate s;
-  int b = n / 2, e = n - 1;
-  kseed(&s, x[0], y[0], z[0], x[b], y[b], x[e], y[e], z[e], bz, prm);
+  int ns = n < prm->seed_window ? n : prm->seed_window;
+  if (ns < 2) ns = 2;
+  int b = ns / 2, es = ns - 1, e = n - 1;
+  kseed(&s, x[0], y[0], z[0], x[b], y[b], x[es], y[es], z[es], bz, prm);
   if (fabs(s.p[2]) > prm->max_sinphi) return 1;
   for (int i = 1; i < n; ++i) {
     if (kprop(&s, x[i], bz, prm->max_sinphi, NULL)) return 1;

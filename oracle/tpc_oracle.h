@@ -35,6 +35,7 @@ typedef struct {
   double nf_win_y, nf_win_z;    /* neighbour search window (cm) */
   double nf_chi2_max;           /* straight-line cut of the neighbours finder */
   int32_t min_seed_len;         /* shortest link chain that becomes a tracklet */
+  int32_t seed_window;          /* the seed uses the first min(m, seed_window) chain clusters */
   double chi2_gate;             /* per-cluster chi^2 gate of the extension */
   int32_t max_miss;             /* extension stops after more consecutive misses */
   double max_sinphi;            /* |sin(phi)| limit of the propagation */
@@ -116,11 +117,14 @@ int orc_construct(const orc_event* ev, const orc_geometry* geo, double bz,
                   int64_t n_seeds, const int32_t* seeds, orc_tracklets* tl);
 
 /* Weights, cluster assignment and selection (sections 1 and 3.1).  qpt is
- * tl->par[.][5].  owner[c] = index of the owning tracklet or -1; keep[t] = 1
- * for the tracklets that become tracks. */
+ * tl->par[.][5].  weights (may be NULL) replaces the computed cluster weight
+ * of each tracklet, so that a caller can decide the ownership with weights
+ * evaluated in another precision.  owner[c] = index of the owning tracklet or
+ * -1; keep[t] = 1 for the tracklets that become tracks. */
 int orc_select(const orc_event* ev, const orc_geometry* geo, double bz,
                const orc_params* prm, int64_t n_tl, const int32_t* ids,
-               const orc_tracklets* tl, int32_t* owner, int32_t* keep);
+               const orc_tracklets* tl, const double* weights, int32_t* owner,
+               int32_t* keep);
 
 /* ---- fit pieces on explicit double-precision hits (tests only) ---------- */
 
@@ -132,7 +136,7 @@ int orc_propagate(double x1, double* st, double* cov, double x2, double bz,
 
 /* Fit of a fixed list of hits (x increasing) the way a tracklet made of one
  * link chain covering them is fitted: three-point seed, outward filter,
- * inward refit.  Outputs the state and covariance at x[0], chi^2, ndf.
+ * inward refit (the seed from the first seed_window hits).  Outputs the state and covariance at x[0], chi^2, ndf.
  * Returns 0, or 1 if the propagation left |sin(phi)| <= max_sinphi. */
 int orc_fit_hits(int32_t n, const double* x, const double* y, const double* z,
                  double bz, const orc_params* prm, double* st, double* cov,

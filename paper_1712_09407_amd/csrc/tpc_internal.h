@@ -17,6 +17,7 @@ struct KParams {
   float sigma_y, sigma_z, sy2, sz2;
   float nf_win_y, nf_win_z, nf_chi2_max;
   int32_t min_seed_len;
+  int32_t seed_window;
   float chi2_gate;
   int32_t max_miss;
   float max_sinphi;
@@ -35,6 +36,12 @@ struct DevEvent {
   int32_t n_clusters;
 };
 
+// One cluster in grid order: coordinates and event index in one 16-byte load.
+struct __attribute__((aligned(16))) GridRec {
+  float y, z;
+  int32_t id, pad;
+};
+
 // Per-row search grid: clusters of a row counting-sorted into ny x nz bins.
 struct RowGrid {
   float y0, z0, iby, ibz;
@@ -50,6 +57,7 @@ enum Counter {
   C_STEPS = 5,      // constructor: helix steps taken
   C_UPDATES = 6,    // constructor: Kalman updates
   C_CANDS = 7,      // constructor: candidate clusters tested against the gate
+  C_QUEUE = 8,      // constructor: next tracklet to hand out, one per XCD group (8..15)
   C_COUNT = 16
 };
 enum ErrBits { E_OFFSETS = 1, E_NONFINITE = 2, E_TL_OVERFLOW = 4, E_CAPACITY = 8 };
@@ -61,8 +69,7 @@ struct Scratch {
   int32_t* counters;       // [C_COUNT]
   RowGrid* grid;           // [R]
   int32_t* bins;           // [N + R + 1]
-  float2* g_yz;            // [N] grid order
-  int32_t* g_id;           // [N] grid order -> event index
+  GridRec* g_rec;          // [N] grid order: y, z, event index
   int32_t *up, *dn;        // [N]
   int32_t *up2, *dn2;      // [N]
   uint8_t* start;          // [N]
@@ -72,12 +79,14 @@ struct Scratch {
   int32_t* seeds;          // [T]
   int32_t* seed_rs;        // [T]
   int32_t* hits;           // [T * kHitStride]
+  float2* hit_yz;          // [T * kHitStride] coordinates of collected clusters
   int32_t *row_lo, *row_hi, *n, *ndf;  // [T]
   float* chi2;             // [T]
   float* par;              // [T * 6]
   unsigned long long* key; // [T]
   int32_t *owned, *kept;   // [T]
   int32_t *trk_idx, *trk_off; // [T]
+  int32_t* span_sum;       // [2 * spans]: kept / owned sums per span of tracklets
 };
 
 struct Outputs {
@@ -95,7 +104,7 @@ void scratch_carve(void* base, int64_t n_clusters, int64_t n_rowslots, int64_t c
 // Kernels of one event, in launch order (index into timing tables).
 enum KernelId {
   K_ZERO, K_GRID, K_NF, K_EVO, K_SCAN_ROWS, K_SEED_WRITE, K_CONSTRUCT, K_ASSIGN, K_SELECT,
-  K_SCAN_TL, K_OUTPUT, K_NUM
+  K_TL_REDUCE, K_TL_SCAN, K_OUTPUT, K_NUM
 };
 extern const char* const kKernelNames[K_NUM];
 

@@ -19,11 +19,14 @@
 //                 tracklet id is the start cluster's index, so seeds come out
 //                 sorted)
 //   k_construct   one lane per tracklet: FP32 Kalman filter in registers,
-//                 exact helix steps row by row, grid search with a chi^2 gate
+//                 exact helix steps row by row, grid search with a chi^2 gate;
+//                 all phases in one loop; tracklets of a sector group stay
+//                 on one XCD
 //   k_assign      one lane per tracklet: weight, 64-bit atomicMax owner key
 //                 per cluster (order-free, smaller id wins ties)
 //   k_select      one lane per tracklet: owned clusters, >= min_clusters cut
-//   k_scan_tl     one block: track index and cluster offset of kept tracklets
+//   k_tl_reduce,  track index and cluster offset of kept tracklets (reduce
+//   k_tl_scan     spans of tracklets, then scan them with the span offsets)
 //   k_output      one lane per tracklet: tracks, cluster lists, cluster->track
 //
 // No step depends on the order in which lanes or blocks run: every choice is
@@ -49,7 +52,7 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) {
 
 // Exact decision of |a - b| <= w for finite a, b and w > 0: the rounded
 // difference is corrected by its TwoSum error, so no rounding can flip it.
-__device__ __forceinline__ bool within(float a, float b, float w) {
+__device__ __attribute__((noinline)) bool within_exact(float a, float b, float w) {
   float s = a - b;
   float bb = s - a;
   float err = (a - (s - bb)) + (-b - bb);
@@ -58,6 +61,13 @@ __device__ __forceinline__ bool within(float a, float b, float w) {
   if (as < 0.5f * w || as > 2.0f * w) return as <= w;
   float d = as - w;  // exact (Sterbenz)
   return d <= -ae;
+}
+// The rounded difference is within 2^-24 relative of the exact one, so only
+// values within 1e-5 of the edge need the exact test.
+__device__ __forceinline__ bool within(float a, float b, float w) {
+  const float as = fabsf(a - b);
+  if (fabsf(as - w) > 1e-5f * w) return as <= w;
+  return within_exact(a, b, w);
 }
 
 __device__ __forceinline__ int bin_y(const RowGrid& g, float y) {
@@ -213,23 +223,45 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(DevEvent ev, KParams kp, Sc
     float y = ev.y[i], z = ev.z[i];
     if (!isfinite(y) || !isfinite(z)) continue;
     int pos = atomicAdd(&s_cnt[bin_z(g, z) * ny + bin_y(g, y)], 1);
-    sc.g_yz[b + pos] = make_float2(y, z);
-    sc.g_id[b + pos] = i;
+    GridRec rec;
+    rec.y = y;
+    rec.z = z;
+    rec.id = i;
+    rec.pad = 0;
+    sc.g_rec[b + pos] = rec;
   }
 }
 
 // ------------------------------------------------------------------ k_nf
 
-// Neighbour-row view (LDS or global).
+// Neighbour-row view staged in LDS.
 struct RowView {
   const float2* yz;
   const int32_t* id;
   const int32_t* bins;  // bins of the row, index 0 = first bin
   RowGrid g;
+  __device__ float2 yz_at(int j) const { return yz[j]; }
+  __device__ int id_at(int j) const { return id[j]; }
 };
 
-// Best (chi2, d, u) pair for a cluster at (yc, zc) of row k (section 1).
-__device__ __forceinline__ void nf_search(const RowView& D, const RowView& U, float yc, float zc,
+// Neighbour-row view in global memory (rows too large for the LDS stage).
+struct RowViewG {
+  const GridRec* rec;
+  const int32_t* bins;
+  RowGrid g;
+  __device__ float2 yz_at(int j) const {
+    const GridRec v = rec[j];
+    return make_float2(v.y, v.z);
+  }
+  __device__ int id_at(int j) const { return rec[j].id; }
+};
+
+constexpr int kNfList = 16;  // window candidates per neighbour row kept per lane
+
+// Best (chi2, d, u) pair for a cluster at (yc, zc) of row k (section 1):
+// every pair of window candidates, no lists (used for dense rows).
+template <class V>
+__device__ __forceinline__ void nf_search(const V& D, const V& U, float yc, float zc,
                                           float t, float wy, float wz, float isy2, float isz2,
                                           float inorm, float& best, int& bd, int& bu) {
   const float m = 1e-3f;  // bin ranges are only an accelerator: widen them
@@ -240,16 +272,16 @@ __device__ __forceinline__ void nf_search(const RowView& D, const RowView& U, fl
   for (int iz = dz0; iz <= dz1; ++iz) {
     const int j0 = D.bins[iz * D.g.ny + dy0], j1 = D.bins[iz * D.g.ny + dy1 + 1];
     for (int j = j0; j < j1; ++j) {
-      const float2 pd = D.yz[j];
+      const float2 pd = D.yz_at(j);
       if (!within(pd.x, yc, wy) || !within(pd.y, zc, wz)) continue;
-      const int idd = D.id[j];
+      const int idd = D.id_at(j);
       const float dyd = pd.x - yc, dzd = pd.y - zc;
       for (int kz = uz0; kz <= uz1; ++kz) {
         const int k0 = U.bins[kz * U.g.ny + uy0], k1 = U.bins[kz * U.g.ny + uy1 + 1];
         for (int k = k0; k < k1; ++k) {
-          const float2 pu = U.yz[k];
+          const float2 pu = U.yz_at(k);
           if (!within(pu.x, yc, wy) || !within(pu.y, zc, wz)) continue;
-          const int idu = U.id[k];
+          const int idu = U.id_at(k);
           const float ry = dyd + t * ((pu.x - yc) - dyd);
           const float rz = dzd + t * ((pu.y - zc) - dzd);
           const float chi2 = (ry * ry * isy2 + rz * rz * isz2) * inorm;
@@ -265,10 +297,34 @@ __device__ __forceinline__ void nf_search(const RowView& D, const RowView& U, fl
   }
 }
 
+// Window candidates of one neighbour row: row-local positions into list
+// (column `lane` of a [kNfList][blockDim] LDS array).  Returns the count,
+// which may exceed kNfList (then the list is incomplete).
+__device__ __forceinline__ int nf_collect(const RowView& V, float yc, float zc, float wy, float wz,
+                                          uint16_t (*list)[kGridBlock], int lane) {
+  const float m = 1e-3f;
+  const int y0 = bin_y(V.g, yc - wy - m), y1 = bin_y(V.g, yc + wy + m);
+  const int z0 = bin_z(V.g, zc - wz - m), z1 = bin_z(V.g, zc + wz + m);
+  int cnt = 0;
+  for (int iz = z0; iz <= z1; ++iz) {
+    const int j0 = V.bins[iz * V.g.ny + y0], j1 = V.bins[iz * V.g.ny + y1 + 1];
+    for (int j = j0; j < j1; ++j) {
+      const float2 p = V.yz[j];
+      if (within(p.x, yc, wy) && within(p.y, zc, wz)) {
+        if (cnt < kNfList) list[cnt][lane] = (uint16_t)j;
+        ++cnt;
+      }
+    }
+  }
+  return cnt;
+}
+
 __global__ __launch_bounds__(kGridBlock) void k_nf(DevEvent ev, KParams kp, Scratch sc) {
   __shared__ float2 s_yz[2][kNfLds];
   __shared__ int32_t s_id[2][kNfLds];
   __shared__ int32_t s_bins[2][kNfLds + 1];
+  __shared__ uint16_t s_dl[kNfList][kGridBlock];
+  __shared__ uint16_t s_ul[kNfList][kGridBlock];
   if (event_bad(sc.counters)) return;
   const int rs = blockIdx.x;
   const int r = rs % kp.n_rows;
@@ -288,15 +344,18 @@ __global__ __launch_bounds__(kGridBlock) void k_nf(DevEvent ev, KParams kp, Scra
   const float t = (xc - xd) / (xu - xd);
   const float inorm = 1.f / (1.f + t * t + (1.f - t) * (1.f - t));
   const float isy2 = 1.f / kp.sy2, isz2 = 1.f / kp.sz2;
+  const float wy = kp.nf_win_y, wz = kp.nf_win_z;
   if (stage) {
     const int nbd = gd.ny * gd.nz, nbu = gu.ny * gu.nz;
     for (int i = tid; i < gd.n; i += kGridBlock) {
-      s_yz[0][i] = sc.g_yz[bd_ + i];
-      s_id[0][i] = sc.g_id[bd_ + i];
+      const GridRec v = sc.g_rec[bd_ + i];
+      s_yz[0][i] = make_float2(v.y, v.z);
+      s_id[0][i] = v.id;
     }
     for (int i = tid; i < gu.n; i += kGridBlock) {
-      s_yz[1][i] = sc.g_yz[bu_ + i];
-      s_id[1][i] = sc.g_id[bu_ + i];
+      const GridRec v = sc.g_rec[bu_ + i];
+      s_yz[1][i] = make_float2(v.y, v.z);
+      s_id[1][i] = v.id;
     }
     if (gd.n > 0)
       for (int i = tid; i <= nbd; i += kGridBlock) s_bins[0][i] = sc.bins[gd.bin_base + i];
@@ -304,18 +363,49 @@ __global__ __launch_bounds__(kGridBlock) void k_nf(DevEvent ev, KParams kp, Scra
       for (int i = tid; i <= nbu; i += kGridBlock) s_bins[1][i] = sc.bins[gu.bin_base + i];
     __syncthreads();
   }
-  for (int i = b + tid; i < e; i += kGridBlock) {
-    const float yc = ev.y[i], zc = ev.z[i];
+  // lanes take the row's clusters in grid order: neighbouring lanes sit at
+  // nearby positions and visit similar bins, so a wave diverges less
+  for (int ii = tid; ii < e - b; ii += kGridBlock) {
+    const GridRec me = sc.g_rec[b + ii];
+    const int i = me.id;
+    const float yc = me.y, zc = me.z;
     float best = INFINITY;
     int bd = -1, bu = -1;
     if (gd.n > 0 && gu.n > 0) {
       if (stage) {
-        RowView D{s_yz[0], s_id[0], s_bins[0], gd}, U{s_yz[1], s_id[1], s_bins[1], gu};
-        nf_search(D, U, yc, zc, t, kp.nf_win_y, kp.nf_win_z, isy2, isz2, inorm, best, bd, bu);
+        const RowView D{s_yz[0], s_id[0], s_bins[0], gd}, U{s_yz[1], s_id[1], s_bins[1], gu};
+        // candidates of each neighbour row once, then the pairs: no nested
+        // bin scans, so lanes of a wave stay in step
+        const int nd = nf_collect(D, yc, zc, wy, wz, s_dl, tid);
+        const int nu = nd ? nf_collect(U, yc, zc, wy, wz, s_ul, tid) : 0;
+        if (nd <= kNfList && nu <= kNfList) {
+          for (int p = 0; p < nd; ++p) {
+            const int j = s_dl[p][tid];
+            const float2 pd = s_yz[0][j];
+            const int idd = s_id[0][j];
+            const float dyd = pd.x - yc, dzd = pd.y - zc;
+            for (int q = 0; q < nu; ++q) {
+              const int k = s_ul[q][tid];
+              const float2 pu = s_yz[1][k];
+              const int idu = s_id[1][k];
+              const float ry = dyd + t * ((pu.x - yc) - dyd);
+              const float rz = dzd + t * ((pu.y - zc) - dzd);
+              const float chi2 = (ry * ry * isy2 + rz * rz * isz2) * inorm;
+              if (bd < 0 || chi2 < best ||
+                  (chi2 == best && (idd < bd || (idd == bd && idu < bu)))) {
+                best = chi2;
+                bd = idd;
+                bu = idu;
+              }
+            }
+          }
+        } else {
+          nf_search(D, U, yc, zc, t, wy, wz, isy2, isz2, inorm, best, bd, bu);
+        }
       } else {
-        RowView D{sc.g_yz + bd_, sc.g_id + bd_, sc.bins + gd.bin_base, gd};
-        RowView U{sc.g_yz + bu_, sc.g_id + bu_, sc.bins + gu.bin_base, gu};
-        nf_search(D, U, yc, zc, t, kp.nf_win_y, kp.nf_win_z, isy2, isz2, inorm, best, bd, bu);
+        const RowViewG D{sc.g_rec + bd_, sc.bins + gd.bin_base, gd};
+        const RowViewG U{sc.g_rec + bu_, sc.bins + gu.bin_base, gu};
+        nf_search(D, U, yc, zc, t, wy, wz, isy2, isz2, inorm, best, bd, bu);
       }
     }
     const bool ok = bd >= 0 && best <= kp.nf_chi2_max;
@@ -404,6 +494,12 @@ __global__ __launch_bounds__(kGridBlock) void k_seed_write(DevEvent ev, Scratch 
 
 // ------------------------------------------------------------------ track model
 
+// Hardware reciprocal / square root (about 1 ulp): the FP32 path is compared
+// with the FP64 oracle at 1e-3, far above these rounding differences.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
 // Lower-triangular packed symmetric 5x5 covariance.
 struct Cov {
   float c00, c10, c11, c20, c21, c22, c30, c31, c32, c33, c40, c41, c42, c43, c44;
@@ -427,12 +523,12 @@ __device__ __forceinline__ void reset_cov(Cov& C, const KParams& kp) {
 __device__ __forceinline__ float asinc(float u) {
   const float u2 = u * u;
   if (u2 < 0.01f) return 1.f + u2 * (1.f / 6.f + u2 * (3.f / 40.f + u2 * (5.f / 112.f)));
-  return asinf(u) / u;
+  return asinf(u) * frcp(u);
 }
 __device__ __forceinline__ float asinc_d(float u, float isq) {
   const float u2 = u * u;
   if (u2 < 0.01f) return u * (1.f / 3.f + u2 * (3.f / 10.f + u2 * (15.f / 56.f)));
-  return (u * isq - asinf(u)) / u2;
+  return (u * isq - asinf(u)) * frcp(u2);
 }
 
 // Exact helix step to x2 with the analytic Jacobian (section 1's Kalman fit
@@ -444,18 +540,19 @@ __device__ __forceinline__ bool propagate(KState& s, float x2, const KParams& kp
   const float kap = k * s.qpt;
   const float s1 = s.sp, s2 = s1 - kap * dx;
   if (fabsf(s1) > kp.max_sinphi || fabsf(s2) > kp.max_sinphi) return false;
-  const float c1 = sqrtf((1.f - s1) * (1.f + s1)), c2 = sqrtf((1.f - s2) * (1.f + s2));
-  const float ic1 = 1.f / c1, ic2 = 1.f / c2;
-  const float T = (s1 + s2) / (c1 + c2);
+  const float ic1 = frsq((1.f - s1) * (1.f + s1)), ic2 = frsq((1.f - s2) * (1.f + s2));
+  const float c1 = (1.f - s1) * (1.f + s1) * ic1, c2 = (1.f - s2) * (1.f + s2) * ic2;
+  const float T = (s1 + s2) * frcp(c1 + c2);
   const float Q2 = 1.f + T * T;
-  const float Q = sqrtf(Q2);
+  const float iQ = frsq(Q2);
+  const float Q = Q2 * iQ;
   const float u = 0.5f * kap * dx * Q;
-  const float isq = 1.f / sqrtf(1.f - u * u);
+  const float isq = frsq(1.f - u * u);
   const float h = asinc(u);
   const float ds = dx * Q * h;
   const float dT_ds1 = 0.5f * Q2 * (ic1 + ic2);
   const float dT_dk = -0.5f * Q2 * dx * ic2;
-  const float TQ = T / Q;
+  const float TQ = T * iQ;
   const float dds_ds1 = dx * TQ * dT_ds1 * isq;
   const float dds_dk = dx * (TQ * dT_dk * isq + 0.5f * Q2 * dx * asinc_d(u, isq));
   const float a = dx * dT_ds1;        // dy/dsinphi
@@ -507,7 +604,7 @@ __device__ __forceinline__ bool propagate(KState& s, float x2, const KParams& kp
 __device__ __forceinline__ float kf_update(KState& s, float my, float mz, const KParams& kp) {
   Cov& C = s.C;
   const float S00 = C.c00 + kp.sy2, S01 = C.c10, S11 = C.c11 + kp.sz2;
-  const float idet = 1.f / (S00 * S11 - S01 * S01);
+  const float idet = frcp(S00 * S11 - S01 * S01);
   const float i00 = S11 * idet, i01 = -S01 * idet, i11 = S00 * idet;
   const float ry = my - s.y, rz = mz - s.z;
   const float chi2 = ry * ry * i00 + 2.f * ry * rz * i01 + rz * rz * i11;
@@ -543,9 +640,9 @@ __device__ __forceinline__ float kf_update(KState& s, float my, float mz, const 
   return chi2;
 }
 
-// Seed from clusters a (first), b (middle), e (last) of the chain: the circle
-// through them in (x, y) gives curvature and direction at a; tan lambda is
-// the z rise over the arc a -> e.
+// Seed from chain clusters a (first), b (middle) and e (last of the seed
+// window): the circle through them in (x, y) gives curvature and direction at
+// a; tan lambda is the z rise over the arc a -> e.
 __device__ __forceinline__ void seed3(KState& s, float xa, float ya, float za, float xb, float yb,
                                       float xe, float ye, float ze, const KParams& kp) {
   const float d1x = xb - xa, d1y = yb - ya, d2x = xe - xa, d2y = ye - ya;
@@ -573,15 +670,16 @@ struct Work {
   int steps = 0, updates = 0, cands = 0;
 };
 
-// Best cluster of a row inside the chi^2 gate (smallest (chi2, index)).
+// Best cluster of a row inside the chi^2 gate (smallest (chi2, index)); its
+// coordinates come back with it, so no reload is needed.
 __device__ __forceinline__ int search_row(const Scratch& sc, const RowGrid& g, int rb,
-                                          const KState& s, const KParams& kp, float& chi2_out,
-                                          Work& wk) {
+                                          const KState& s, const KParams& kp, float& by,
+                                          float& bz_, Work& wk) {
   if (g.n == 0) return -1;
   const float S00 = s.C.c00 + kp.sy2, S01 = s.C.c10, S11 = s.C.c11 + kp.sz2;
-  const float idet = 1.f / (S00 * S11 - S01 * S01);
-  const float wy = sqrtf(kp.chi2_gate * S00) * 1.0001f + 1e-4f;
-  const float wz = sqrtf(kp.chi2_gate * S11) * 1.0001f + 1e-4f;
+  const float idet = frcp(S00 * S11 - S01 * S01);
+  const float wy = fsqrt(kp.chi2_gate * S00) * 1.001f + 1e-4f;
+  const float wz = fsqrt(kp.chi2_gate * S11) * 1.001f + 1e-4f;
   const int iy0 = bin_y(g, s.y - wy), iy1 = bin_y(g, s.y + wy);
   const int iz0 = bin_z(g, s.z - wz), iz1 = bin_z(g, s.z + wz);
   float best = INFINITY;
@@ -591,41 +689,31 @@ __device__ __forceinline__ int search_row(const Scratch& sc, const RowGrid& g, i
     const int j1 = sc.bins[g.bin_base + iz * g.ny + iy1 + 1];
     wk.cands += j1 - j0;
     for (int j = j0; j < j1; ++j) {
-      const float2 v = sc.g_yz[rb + j];
-      const float ry = v.x - s.y, rz = v.y - s.z;
+      const GridRec v = sc.g_rec[rb + j];
+      const float ry = v.y - s.y, rz = v.z - s.z;
       const float chi2 = (ry * ry * S11 - 2.f * ry * rz * S01 + rz * rz * S00) * idet;
-      if (chi2 <= kp.chi2_gate) {
-        const int id = sc.g_id[rb + j];
-        if (chi2 < best || (chi2 == best && id < bid)) {
-          best = chi2;
-          bid = id;
-        }
+      if (chi2 <= kp.chi2_gate && (chi2 < best || (chi2 == best && v.id < bid))) {
+        best = chi2;
+        bid = v.id;
+        by = v.y;
+        bz_ = v.z;
       }
     }
   }
-  chi2_out = best;
   return bid;
 }
 
-// One extension row: 0 = cluster collected, 1 = miss, 2 = stop.
-__device__ __forceinline__ int extend_step(const DevEvent& ev, const Scratch& sc, const KParams& kp,
-                                           const float* s_x, int rsb, int r, KState& s, int& hit,
-                                           float& chi2, Work& wk) {
-  if (!propagate(s, s_x[r], kp)) return 2;
-  ++wk.steps;
-  if (fabsf(s.z) > kp.z_max) return 2;
-  if (fabsf(s.y) > s_x[r] * kp.tan_half) return 1;
-  const RowGrid g = sc.grid[rsb + r];
-  float c2;
-  const int j = search_row(sc, g, ev.ro[rsb + r], s, kp, c2, wk);
-  if (j < 0) return 1;
-  chi2 = kf_update(s, ev.y[j], ev.z[j], kp);
-  ++wk.updates;
-  hit = j;
-  return 0;
-}
-
 // ------------------------------------------------------------------ k_construct
+//
+// One lane per tracklet, all phases of the construction in ONE loop of row
+// steps, so that lanes of a wave stay in step whatever phase each is in:
+//   P_CHAIN  outward through the chain, clusters taken unconditionally
+//   P_UP     outward extension: search the row, chi^2 gate
+//   P_REFIT  inward from the outermost cluster with a fresh covariance
+//   P_DOWN   inward extension below the innermost cluster
+// A lane that finishes takes the next tracklet from a queue counter.
+
+enum Phase { P_CHAIN = 0, P_UP = 1, P_REFIT = 2, P_DOWN = 3 };
 
 __global__ __launch_bounds__(kTlBlock) void k_construct(DevEvent ev, KParams kp, Scratch sc) {
   __shared__ float s_x[TPC_MAX_ROWS];
@@ -635,129 +723,219 @@ __global__ __launch_bounds__(kTlBlock) void k_construct(DevEvent ev, KParams kp,
   const int n_tl = min(sc.counters[C_SEEDS], sc.cap_tl);
   const int nr = kp.n_rows;
   Work wk;
-  for (int t = blockIdx.x * kTlBlock + threadIdx.x; t < n_tl; t += gridDim.x * kTlBlock) {
-    const int start = sc.seeds[t];
-    const int rs0 = sc.seed_rs[t];
-    const int k0 = rs0 % nr;
-    const int rsb = rs0 - k0;
-    int32_t* H = sc.hits + (size_t)t * kHitStride;
-    // the chain of one-to-one links
-    int m = 0, last = start;
-    for (int c = start; c >= 0 && k0 + m < nr; c = sc.up2[c]) {
+
+  // XCD-aware mapping: workgroups are spread round-robin over the 8 XCDs,
+  // each with its own L2.  Blocks b = g (mod 8) take the tracklets of the
+  // sectors s = g (mod 8), so one XCD reads the grids of only a few sectors.
+  // Any mapping gives the same results; this one keeps the grids in L2.
+  const int grp = blockIdx.x & 7;
+  const int blocks_g = ((int)gridDim.x - grp + 7) >> 3;
+  const int lanes_g = blocks_g * kTlBlock;
+  int total_g = 0;
+  for (int sct = grp; sct < ev.n_sectors; sct += 8)
+    total_g += sc.row_cnt[(sct + 1) * nr] - sc.row_cnt[sct * nr];
+  // k-th tracklet of this group -> tracklet index (sectors are contiguous)
+  auto group_tracklet = [&](int k) {
+    for (int sct = grp; sct < ev.n_sectors; sct += 8) {
+      const int o = sc.row_cnt[sct * nr], c = sc.row_cnt[(sct + 1) * nr] - o;
+      if (k < c) return min(o + k, n_tl);
+      k -= c;
+    }
+    return n_tl;
+  };
+  int kg = (blockIdx.x >> 3) * kTlBlock + threadIdx.x;  // first: static
+  int t = kg < total_g ? group_tracklet(kg) : n_tl;
+  // lane state
+  KState s;
+  int phase = 0, r = 0, k0 = 0, rsb = 0, last_row = 0, misses = 0, n = 0, inner = 0;
+  int cn = -1, cnn = -1;            // chain: cluster of row r and the one after
+  float cy = 0.f, cz = 0.f;         // coordinates of cn / of the prefetched refit hit
+  int hc = -1;                      // refit: cluster of row r
+  float l_sp = 0.f, l_tl = 0.f, l_q = 0.f, l_y = 0.f, l_z = 0.f;  // state at last hit
+  float chi2 = 0.f;
+  float o0 = 0.f, o1 = 0.f, o2 = 0.f, o3 = 0.f, o4 = 0.f, o5 = 0.f;  // output state
+  bool dropped = false;
+  int32_t* H = nullptr;
+  float2* HY = nullptr;
+
+  // Set up tracklet t: walk the seed window of its chain, fit the seed.
+  auto begin = [&](int tt) {
+    const int start = sc.seeds[tt];
+    const int rs0 = sc.seed_rs[tt];
+    k0 = rs0 % nr;
+    rsb = rs0 - k0;
+    H = sc.hits + (size_t)tt * kHitStride;
+    HY = sc.hit_yz + (size_t)tt * kHitStride;
+    int m = 0, c = start, last = start, c1 = -1, c2 = -1;
+    while (c >= 0 && m < kp.seed_window && k0 + m < nr) {
       H[k0 + m] = c;
       last = c;
+      if (m == 1) c1 = c;
+      if (m == 2) c2 = c;
       ++m;
+      c = sc.up2[c];
     }
+    if (m == 2) c2 = c;  // the chain may continue past a 2-cluster window
     const int bmid = H[k0 + m / 2];
-    KState s;
     seed3(s, s_x[k0], ev.y[start], ev.z[start], s_x[k0 + m / 2], ev.y[bmid], s_x[k0 + m - 1],
           ev.y[last], ev.z[last], kp);
-    bool dropped = fabsf(s.sp) > kp.max_sinphi;
-    int last_row = k0;
-    float l_sp = s.sp, l_tl = s.tl, l_q = s.qpt;
-    // outward filter through the chain, unconditionally
-    for (int j = 1; j < m && !dropped; ++j) {
-      if (!propagate(s, s_x[k0 + j], kp)) {
-        dropped = true;
-        break;
-      }
-      const int c = H[k0 + j];
-      kf_update(s, ev.y[c], ev.z[c], kp);
-      wk.steps += 1;
-      wk.updates += 1;
-      last_row = k0 + j;
-      l_sp = s.sp;
-      l_tl = s.tl;
-      l_q = s.qpt;
+    dropped = fabsf(s.sp) > kp.max_sinphi;
+    last_row = k0;
+    l_sp = s.sp; l_tl = s.tl; l_q = s.qpt; l_y = s.y; l_z = s.z;
+    HY[k0] = make_float2(s.y, s.z);
+    phase = P_CHAIN;
+    r = k0 + 1;
+    cn = c1;
+    cnn = c2;
+    if (cn >= 0) {
+      cy = ev.y[cn];
+      cz = ev.z[cn];
     }
-    // outward extension
-    if (!dropped) {
-      int misses = 0;
-      for (int r = k0 + m; r < nr; ++r) {
-        int h = -1;
-        float c2;
-        const int st = extend_step(ev, sc, kp, s_x, rsb, r, s, h, c2, wk);
-        if (st == 2) break;
-        H[r] = h;
-        if (st == 0) {
-          last_row = r;
-          l_sp = s.sp;
-          l_tl = s.tl;
-          l_q = s.qpt;
-          misses = 0;
-        } else if (++misses > kp.max_miss) {
-          break;
-        }
+    misses = 0;
+    n = 0;
+    chi2 = 0.f;
+  };
+  // Inward refit set-up from the outermost collected cluster.
+  auto begin_refit = [&]() {
+    s.x = s_x[last_row];
+    s.y = l_y;
+    s.z = l_z;
+    s.sp = l_sp;
+    s.tl = l_tl;
+    s.qpt = l_q;
+    reset_cov(s.C, kp);
+    n = 1;
+    inner = last_row;
+    chi2 = 0.f;
+    o0 = s.x; o1 = s.y; o2 = s.z; o3 = s.sp; o4 = s.tl; o5 = s.qpt;
+    phase = P_REFIT;
+    r = last_row - 1;
+    if (r >= k0) {
+      hc = H[r];
+      if (hc >= 0) {
+        const float2 v = HY[r];
+        cy = v.x;
+        cz = v.y;
       }
     }
-    // inward refit from the outermost collected cluster with a fresh covariance
-    int n = 0, inner = 0, ndf = 0;
-    float chi2 = 0.f;
-    float ox = 0.f, oy = 0.f, oz = 0.f, osp = 0.f, otl = 0.f, oq = 0.f;
-    if (!dropped) {
-      const int ho = H[last_row];
-      KState w;
-      w.x = s_x[last_row];
-      w.y = ev.y[ho];
-      w.z = ev.z[ho];
-      w.sp = l_sp;
-      w.tl = l_tl;
-      w.qpt = l_q;
-      reset_cov(w.C, kp);
-      n = 1;
-      inner = last_row;
-      ox = w.x; oy = w.y; oz = w.z; osp = w.sp; otl = w.tl; oq = w.qpt;
-      for (int r = last_row - 1; r >= k0; --r) {
-        if (!propagate(w, s_x[r], kp)) {
-          dropped = true;
-          break;
-        }
-        ++wk.steps;
-        const int c = H[r];
-        if (c >= 0) {
-          ++wk.updates;
-          chi2 += kf_update(w, ev.y[c], ev.z[c], kp);
-          ++n;
-          inner = r;
-          ox = w.x; oy = w.y; oz = w.z; osp = w.sp; otl = w.tl; oq = w.qpt;
-        }
-      }
-      if (!dropped) {
-        int misses = 0;
-        for (int r = k0 - 1; r >= 0; --r) {
-          int h = -1;
-          float c2 = 0.f;
-          const int st = extend_step(ev, sc, kp, s_x, rsb, r, w, h, c2, wk);
-          if (st == 2) break;
-          H[r] = h;
-          if (st == 0) {
-            chi2 += c2;
-            ++n;
-            inner = r;
-            ox = w.x; oy = w.y; oz = w.z; osp = w.sp; otl = w.tl; oq = w.qpt;
-            misses = 0;
-          } else if (++misses > kp.max_miss) {
-            break;
+  };
+
+  RowGrid gn;  // grid header of the next extension row, loaded one step early
+  if (t < n_tl) begin(t);
+  while (t < n_tl) {
+    bool finish = dropped;
+    if (!finish) {
+      const RowGrid g = gn;
+      const bool ext = phase == P_UP || phase == P_DOWN;
+      // 1. one helix step for every lane, whatever its phase
+      const bool ok = propagate(s, s_x[r], kp);
+      if (ok) ++wk.steps;
+      // 2. the measurement of this row: known (chain, refit) or searched
+      int st = 2;  // 0 = cluster, 1 = no cluster (miss), 2 = stop
+      int hit = -1;
+      float my = cy, mz = cz;
+      if (ok) {
+        if (phase == P_CHAIN) {
+          st = 0;
+          hit = cn;
+        } else if (phase == P_REFIT) {
+          st = hc >= 0 ? 0 : 1;
+          hit = hc;
+        } else if (!(fabsf(s.z) > kp.z_max)) {
+          st = 1;
+          if (!(fabsf(s.y) > s_x[r] * kp.tan_half)) {
+            hit = search_row(sc, g, g.bin_base - (rsb + r), s, kp, my, mz, wk);
+            if (hit >= 0) st = 0;
           }
         }
       }
-      ndf = 2 * n - 5;
+      // 3. one Kalman update for every lane that has a cluster
+      float c2 = 0.f;
+      if (st == 0) {
+        c2 = kf_update(s, my, mz, kp);
+        ++wk.updates;
+      }
+      // 4. bookkeeping of the phase
+      if (st == 2 && !ext) {
+        dropped = finish = true;  // a step through known clusters failed
+      } else if (phase == P_CHAIN || phase == P_UP) {
+        if (st == 0) {
+          last_row = r;
+          l_sp = s.sp; l_tl = s.tl; l_q = s.qpt; l_y = my; l_z = mz;
+          HY[r] = make_float2(my, mz);
+        }
+        if (st != 2) H[r] = hit;
+        if (phase == P_CHAIN) {
+          cn = cnn;
+          ++r;
+          if (cn >= 0 && r < nr) {
+            cy = ev.y[cn];
+            cz = ev.z[cn];
+            cnn = sc.up2[cn];
+          } else {
+            phase = P_UP;
+            misses = 0;
+            if (r >= nr) begin_refit();
+          }
+        } else {
+          misses = st == 0 ? 0 : misses + 1;
+          ++r;
+          if (st == 2 || misses > kp.max_miss || r >= nr) begin_refit();
+        }
+      } else {  // P_REFIT or P_DOWN: collected clusters enter the final fit
+        if (st == 0) {
+          chi2 += c2;
+          ++n;
+          inner = r;
+          o0 = s.x; o1 = s.y; o2 = s.z; o3 = s.sp; o4 = s.tl; o5 = s.qpt;
+        }
+        if (phase == P_DOWN) {
+          if (st != 2) H[r] = hit;
+          misses = st == 0 ? 0 : misses + 1;
+          --r;
+          if (st == 2 || misses > kp.max_miss || r < 0) finish = true;
+        } else {
+          --r;
+          if (r >= k0) {
+            hc = H[r];
+            if (hc >= 0) {
+              const float2 v = HY[r];
+              cy = v.x;
+              cz = v.y;
+            }
+          }
+        }
+      }
+      // a refit that reaches (or starts) below the chain start continues as P_DOWN
+      if (!finish && phase == P_REFIT && r < k0) {
+        phase = P_DOWN;
+        misses = 0;
+        if (r < 0) finish = true;
+      }
+      if (!finish && (phase == P_UP || phase == P_DOWN)) gn = sc.grid[rsb + r];
     }
-    if (dropped) {
-      n = 0;
-      ndf = 0;
-      chi2 = 0.f;
-      sc.row_lo[t] = 0;
-      sc.row_hi[t] = -1;
-    } else {
-      sc.row_lo[t] = inner;
-      sc.row_hi[t] = last_row;
+    if (finish) {
+      if (dropped) {
+        sc.row_lo[t] = 0;
+        sc.row_hi[t] = -1;
+        sc.n[t] = 0;
+        sc.ndf[t] = 0;
+        sc.chi2[t] = 0.f;
+      } else {
+        sc.row_lo[t] = inner;
+        sc.row_hi[t] = last_row;
+        sc.n[t] = n;
+        sc.ndf[t] = 2 * n - 5;
+        sc.chi2[t] = chi2;
+      }
+      float* P = sc.par + (size_t)t * 6;
+      P[0] = dropped ? 0.f : o0; P[1] = dropped ? 0.f : o1; P[2] = dropped ? 0.f : o2;
+      P[3] = dropped ? 0.f : o3; P[4] = dropped ? 0.f : o4; P[5] = dropped ? 0.f : o5;
+      // refill from this group's queue (only when it has more tracklets than lanes)
+      kg = lanes_g < total_g ? lanes_g + atomicAdd(&sc.counters[C_QUEUE + grp], 1) : total_g;
+      t = kg < total_g ? group_tracklet(kg) : n_tl;
+      if (t < n_tl) begin(t);
     }
-    sc.n[t] = n;
-    sc.ndf[t] = ndf;
-    sc.chi2[t] = chi2;
-    float* P = sc.par + (size_t)t * 6;
-    P[0] = ox; P[1] = oy; P[2] = oz; P[3] = osp; P[4] = otl; P[5] = oq;
   }
   // one atomic per wave and counter
   int st = wk.steps, up = wk.updates, ca = wk.cands;
@@ -774,16 +952,20 @@ __global__ __launch_bounds__(kTlBlock) void k_construct(DevEvent ev, KParams kp,
 }
 
 // ------------------------------------------------------------------ selection
+//
+// One wave per tracklet: the wave's lanes cover the tracklet's rows.
 
 __device__ __forceinline__ unsigned int order_bits(float w) {
   const unsigned int u = __float_as_uint(w + 0.f);  // -0 -> +0
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-__global__ __launch_bounds__(kTlBlock) void k_assign(KParams kp, Scratch sc) {
+__global__ __launch_bounds__(kGridBlock) void k_assign(KParams kp, Scratch sc) {
   if (event_bad(sc.counters)) return;
   const int n_tl = min(sc.counters[C_SEEDS], sc.cap_tl);
-  for (int t = blockIdx.x * kTlBlock + threadIdx.x; t < n_tl; t += gridDim.x * kTlBlock) {
+  const int lane = threadIdx.x & 63;
+  const int wpb = kGridBlock / 64;
+  for (int t = blockIdx.x * wpb + (threadIdx.x >> 6); t < n_tl; t += gridDim.x * wpb) {
     const int n = sc.n[t];
     const float qpt = sc.par[(size_t)t * 6 + 5];
     unsigned long long key = 0ull;
@@ -792,95 +974,162 @@ __global__ __launch_bounds__(kTlBlock) void k_assign(KParams kp, Scratch sc) {
       key = ((unsigned long long)order_bits(w) << 32) |
             (unsigned long long)(0xFFFFFFFFu - (unsigned int)sc.seeds[t]);
       const int32_t* H = sc.hits + (size_t)t * kHitStride;
-      for (int r = sc.row_lo[t]; r <= sc.row_hi[t]; ++r) {
+      const int lo = sc.row_lo[t], hi = sc.row_hi[t];
+      for (int r = lo + lane; r <= hi; r += 64) {
         const int c = H[r];
         if (c >= 0) atomicMax(&sc.own[c], key);
       }
     }
-    sc.key[t] = key;
+    if (lane == 0) sc.key[t] = key;
   }
 }
 
-__global__ __launch_bounds__(kTlBlock) void k_select(KParams kp, Scratch sc) {
+__global__ __launch_bounds__(kGridBlock) void k_select(KParams kp, Scratch sc) {
   if (event_bad(sc.counters)) return;
   const int n_tl = min(sc.counters[C_SEEDS], sc.cap_tl);
-  for (int t = blockIdx.x * kTlBlock + threadIdx.x; t < n_tl; t += gridDim.x * kTlBlock) {
+  const int lane = threadIdx.x & 63;
+  const int wpb = kGridBlock / 64;
+  for (int t = blockIdx.x * wpb + (threadIdx.x >> 6); t < n_tl; t += gridDim.x * wpb) {
     const unsigned long long key = sc.key[t];
     int owned = 0;
     if (key != 0ull) {
       const int32_t* H = sc.hits + (size_t)t * kHitStride;
-      for (int r = sc.row_lo[t]; r <= sc.row_hi[t]; ++r) {
+      const int lo = sc.row_lo[t], hi = sc.row_hi[t];
+      for (int r = lo + lane; r <= hi; r += 64) {
         const int c = H[r];
         owned += (c >= 0 && sc.own[c] == key) ? 1 : 0;
       }
+      for (int d = 32; d >= 1; d >>= 1) owned += __shfl_xor(owned, d, 64);
     }
-    const bool kept = owned >= kp.min_clusters;
-    sc.kept[t] = kept ? 1 : 0;
-    sc.owned[t] = kept ? owned : 0;
+    if (lane == 0) {
+      const bool kept = owned >= kp.min_clusters;
+      sc.kept[t] = kept ? 1 : 0;
+      sc.owned[t] = kept ? owned : 0;
+    }
   }
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_tl(Scratch sc, int cap_tracks,
+// Track index and cluster offset of every kept tracklet, in two passes over
+// spans of kSpan tracklets: k_tl_reduce sums each span, k_tl_scan adds the
+// sums of the spans before it to a scan of its own span.
+constexpr int kSpanPer = 4;
+constexpr int kSpan = kScanBlock * kSpanPer;
+
+__global__ __launch_bounds__(kScanBlock) void k_tl_reduce(Scratch sc) {
+  __shared__ int s_w[kScanBlock / 64];
+  if (event_bad(sc.counters)) return;
+  const int n_tl = min(sc.counters[C_SEEDS], sc.cap_tl);
+  const int base = blockIdx.x * kSpan + threadIdx.x * kSpanPer;
+  int st = 0, so = 0;
+#pragma unroll
+  for (int q = 0; q < kSpanPer; ++q) {
+    const int i = base + q;
+    if (i < n_tl) {
+      st += sc.kept[i];
+      so += sc.owned[i];
+    }
+  }
+  int tt, to;
+  block_excl_scan<kScanBlock>(st, s_w, &tt);
+  block_excl_scan<kScanBlock>(so, s_w, &to);
+  if (threadIdx.x == 0) {
+    sc.span_sum[2 * blockIdx.x] = tt;
+    sc.span_sum[2 * blockIdx.x + 1] = to;
+  }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_tl_scan(Scratch sc, int cap_tracks,
                                                         int cap_track_clusters) {
   __shared__ int s_w[kScanBlock / 64];
   if (event_bad(sc.counters)) return;
   const int n_tl = min(sc.counters[C_SEEDS], sc.cap_tl);
   const int tid = threadIdx.x;
-  int carry_t = 0, carry_c = 0;
-  for (int base = 0; base < n_tl; base += kScanBlock) {
-    const int i = base + tid;
-    const int k = i < n_tl ? sc.kept[i] : 0;
-    const int o = i < n_tl ? sc.owned[i] : 0;
-    int tt, tc;
-    const int et = block_excl_scan<kScanBlock>(k, s_w, &tt);
-    const int ec = block_excl_scan<kScanBlock>(o, s_w, &tc);
-    if (i < n_tl) {
-      sc.trk_idx[i] = carry_t + et;
-      sc.trk_off[i] = carry_c + ec;
-    }
-    carry_t += tt;
-    carry_c += tc;
+  // offsets of this span: sums of the spans before it
+  int pt = 0, po = 0;
+  for (int j = tid; j < (int)blockIdx.x; j += kScanBlock) {
+    pt += sc.span_sum[2 * j];
+    po += sc.span_sum[2 * j + 1];
   }
-  if (tid == 0) {
-    sc.counters[C_TRACKS] = carry_t;
-    sc.counters[C_TRACK_CLUSTERS] = carry_c;
-    if (carry_t > cap_tracks || carry_c > cap_track_clusters)
-      atomicOr(&sc.counters[C_ERR], E_CAPACITY);
+  int off_t, off_o;
+  block_excl_scan<kScanBlock>(pt, s_w, &off_t);
+  block_excl_scan<kScanBlock>(po, s_w, &off_o);
+  const int base = blockIdx.x * kSpan + tid * kSpanPer;
+  int kv[kSpanPer], ov[kSpanPer];
+  int st = 0, so = 0;
+#pragma unroll
+  for (int q = 0; q < kSpanPer; ++q) {
+    const int i = base + q;
+    kv[q] = i < n_tl ? sc.kept[i] : 0;
+    ov[q] = i < n_tl ? sc.owned[i] : 0;
+    st += kv[q];
+    so += ov[q];
+  }
+  int tt, to;
+  int et = block_excl_scan<kScanBlock>(st, s_w, &tt) + off_t;
+  int eo = block_excl_scan<kScanBlock>(so, s_w, &to) + off_o;
+#pragma unroll
+  for (int q = 0; q < kSpanPer; ++q) {
+    const int i = base + q;
+    if (i < n_tl) {
+      sc.trk_idx[i] = et;
+      sc.trk_off[i] = eo;
+    }
+    et += kv[q];
+    eo += ov[q];
+  }
+  if (blockIdx.x == gridDim.x - 1 && tid == 0) {
+    const int nt = off_t + tt, nc = off_o + to;
+    sc.counters[C_TRACKS] = nt;
+    sc.counters[C_TRACK_CLUSTERS] = nc;
+    if (nt > cap_tracks || nc > cap_track_clusters) atomicOr(&sc.counters[C_ERR], E_CAPACITY);
   }
 }
 
-__global__ __launch_bounds__(kTlBlock) void k_output(DevEvent ev, KParams kp, Scratch sc,
-                                                     Outputs out) {
+__global__ __launch_bounds__(kGridBlock) void k_output(DevEvent ev, KParams kp, Scratch sc,
+                                                       Outputs out) {
   if (__builtin_nontemporal_load(&sc.counters[C_ERR]) != 0) {
     // bad input, capacity exceeded or tracklet overflow: nothing is written
     return;
   }
   const int n_tl = min(sc.counters[C_SEEDS], sc.cap_tl);
-  for (int t = blockIdx.x * kTlBlock + threadIdx.x; t < n_tl; t += gridDim.x * kTlBlock) {
-    if (!sc.kept[t]) continue;
+  const int lane = threadIdx.x & 63;
+  const int wpb = kGridBlock / 64;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  for (int t = blockIdx.x * wpb + (threadIdx.x >> 6); t < n_tl; t += gridDim.x * wpb) {
+    if (!sc.kept[t]) continue;  // wave-uniform
     const int i = sc.trk_idx[t];
-    const int off = sc.trk_off[t];
+    int off = sc.trk_off[t];
     const unsigned long long key = sc.key[t];
     const int32_t* H = sc.hits + (size_t)t * kHitStride;
-    int k = 0;
-    for (int r = sc.row_lo[t]; r <= sc.row_hi[t]; ++r) {
-      const int c = H[r];
-      if (c >= 0 && sc.own[c] == key) {
+    const int lo = sc.row_lo[t], hi = sc.row_hi[t];
+    for (int r0 = lo; r0 <= hi; r0 += 64) {  // wave-uniform trip count
+      const int r = r0 + lane;
+      const int c = r <= hi ? H[r] : -1;
+      const bool mine = c >= 0 && sc.own[c] == key;
+      const unsigned long long m = __ballot(mine);
+      if (mine) {
+        const int k = __popcll(m & lt);
         out.track_cluster[off + k] = c;
         out.cluster_track[c] = i;
-        ++k;
       }
+      off += __popcll(m);
     }
-    const float* P = sc.par + (size_t)t * 6;
-    float* O = out.track_par + (size_t)i * 8;
-    O[0] = P[0]; O[1] = P[1]; O[2] = P[2]; O[3] = P[3]; O[4] = P[4]; O[5] = P[5];
-    O[6] = sc.chi2[t];
-    O[7] = (float)sc.ndf[t];
-    int32_t* M = out.track_meta + (size_t)i * 4;
-    M[0] = ev.sector_id[sc.seed_rs[t] / kp.n_rows];
-    M[1] = k;
-    M[2] = off;
-    M[3] = sc.seeds[t];
+    if (lane < 8) {
+      const float* P = sc.par + (size_t)t * 6;
+      float v;
+      if (lane < 6) v = P[lane];
+      else if (lane == 6) v = sc.chi2[t];
+      else v = (float)sc.ndf[t];
+      out.track_par[(size_t)i * 8 + lane] = v;
+    } else if (lane < 12) {
+      int v;
+      const int q = lane - 8;
+      if (q == 0) v = ev.sector_id[sc.seed_rs[t] / kp.n_rows];
+      else if (q == 1) v = sc.owned[t];
+      else if (q == 2) v = sc.trk_off[t];
+      else v = sc.seeds[t];
+      out.track_meta[(size_t)i * 4 + q] = v;
+    }
   }
 }
 
@@ -893,17 +1142,19 @@ size_t scratch_bytes(int64_t N, int64_t R, int64_t T) {
   b += align_up(sizeof(int32_t) * C_COUNT);
   b += align_up(sizeof(RowGrid) * R);
   b += align_up(sizeof(int32_t) * (N + R + 1));
-  b += align_up(sizeof(float2) * N);
-  b += align_up(sizeof(int32_t) * N) * 6;  // g_id, up, dn, up2, dn2 + start (bytes, padded)
+  b += align_up(sizeof(GridRec) * N);
+  b += align_up(sizeof(int32_t) * N) * 5;  // up, dn, up2, dn2 + start (bytes, padded)
   b += align_up(sizeof(unsigned long long) * N);
   b += align_up(sizeof(int32_t) * (R + 1));
   b += align_up(sizeof(int32_t) * T) * 2;
   b += align_up(sizeof(int32_t) * T * kHitStride);
+  b += align_up(sizeof(float2) * T * kHitStride);
   b += align_up(sizeof(int32_t) * T) * 4;
   b += align_up(sizeof(float) * T);
   b += align_up(sizeof(float) * T * 6);
   b += align_up(sizeof(unsigned long long) * T);
   b += align_up(sizeof(int32_t) * T) * 4;
+  b += align_up(sizeof(int32_t) * (2 * ((T + kSpan - 1) / kSpan) + 2));
   return b;
 }
 
@@ -917,8 +1168,7 @@ void scratch_carve(void* base, int64_t N, int64_t R, int64_t T, Scratch* sc) {
   sc->counters = (int32_t*)take(sizeof(int32_t) * C_COUNT);
   sc->grid = (RowGrid*)take(sizeof(RowGrid) * R);
   sc->bins = (int32_t*)take(sizeof(int32_t) * (N + R + 1));
-  sc->g_yz = (float2*)take(sizeof(float2) * N);
-  sc->g_id = (int32_t*)take(sizeof(int32_t) * N);
+  sc->g_rec = (GridRec*)take(sizeof(GridRec) * N);
   sc->up = (int32_t*)take(sizeof(int32_t) * N);
   sc->dn = (int32_t*)take(sizeof(int32_t) * N);
   sc->up2 = (int32_t*)take(sizeof(int32_t) * N);
@@ -930,6 +1180,7 @@ void scratch_carve(void* base, int64_t N, int64_t R, int64_t T, Scratch* sc) {
   sc->seeds = (int32_t*)take(sizeof(int32_t) * T);
   sc->seed_rs = (int32_t*)take(sizeof(int32_t) * T);
   sc->hits = (int32_t*)take(sizeof(int32_t) * T * kHitStride);
+  sc->hit_yz = (float2*)take(sizeof(float2) * T * kHitStride);
   sc->row_lo = (int32_t*)take(sizeof(int32_t) * T);
   sc->row_hi = (int32_t*)take(sizeof(int32_t) * T);
   sc->n = (int32_t*)take(sizeof(int32_t) * T);
@@ -941,19 +1192,26 @@ void scratch_carve(void* base, int64_t N, int64_t R, int64_t T, Scratch* sc) {
   sc->kept = (int32_t*)take(sizeof(int32_t) * T);
   sc->trk_idx = (int32_t*)take(sizeof(int32_t) * T);
   sc->trk_off = (int32_t*)take(sizeof(int32_t) * T);
+  sc->span_sum = (int32_t*)take(sizeof(int32_t) * (2 * ((T + kSpan - 1) / kSpan) + 2));
 }
 
-// Per-tracklet kernels: enough waves for every tracklet of a large event,
-// lanes stride over the rest.
+// Constructor: one lane per tracklet of the reservation, refills from the
+// queue when the reservation exceeds the launch.  Per-tracklet kernels: one
+// wave per tracklet.
 static inline int tl_blocks(int64_t T) {
   int64_t b = (T + kTlBlock - 1) / kTlBlock;
-  if (b > 8192) b = 8192;
+  if (b > 16384) b = 16384;
+  return (int)(b < 1 ? 1 : b);
+}
+static inline int wave_blocks(int64_t T) {
+  int64_t b = (T + kGridBlock / 64 - 1) / (kGridBlock / 64);
+  if (b > 65536) b = 65536;
   return (int)(b < 1 ? 1 : b);
 }
 
 const char* const kKernelNames[K_NUM] = {
     "k_zero", "k_grid", "k_nf", "k_evo", "k_scan_rows", "k_seed_write", "k_construct",
-    "k_assign", "k_select", "k_scan_tl", "k_output"};
+    "k_assign", "k_select", "k_tl_reduce", "k_tl_scan", "k_output"};
 
 hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& sc,
                          const Outputs& out, int upto, hipStream_t st, const KernelTimer* tm) {
@@ -989,18 +1247,23 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
   hipLaunchKernelGGL(k_construct, dim3(nb), dim3(kTlBlock), 0, st, ev, kp, sc);
   post(K_CONSTRUCT);
   if (upto <= STAGE_TRACKLETS) return hipGetLastError();
+  const int wb = wave_blocks(sc.cap_tl);
   pre(K_ASSIGN);
-  hipLaunchKernelGGL(k_assign, dim3(nb), dim3(kTlBlock), 0, st, kp, sc);
+  hipLaunchKernelGGL(k_assign, dim3(wb), dim3(kGridBlock), 0, st, kp, sc);
   post(K_ASSIGN);
   pre(K_SELECT);
-  hipLaunchKernelGGL(k_select, dim3(nb), dim3(kTlBlock), 0, st, kp, sc);
+  hipLaunchKernelGGL(k_select, dim3(wb), dim3(kGridBlock), 0, st, kp, sc);
   post(K_SELECT);
-  pre(K_SCAN_TL);
-  hipLaunchKernelGGL(k_scan_tl, dim3(1), dim3(kScanBlock), 0, st, sc, out.cap_tracks,
+  const int spans = (int)((sc.cap_tl + kSpan - 1) / kSpan);
+  pre(K_TL_REDUCE);
+  hipLaunchKernelGGL(k_tl_reduce, dim3(spans), dim3(kScanBlock), 0, st, sc);
+  post(K_TL_REDUCE);
+  pre(K_TL_SCAN);
+  hipLaunchKernelGGL(k_tl_scan, dim3(spans), dim3(kScanBlock), 0, st, sc, out.cap_tracks,
                      out.cap_track_clusters);
-  post(K_SCAN_TL);
+  post(K_TL_SCAN);
   pre(K_OUTPUT);
-  hipLaunchKernelGGL(k_output, dim3(nb), dim3(kTlBlock), 0, st, ev, kp, sc, out);
+  hipLaunchKernelGGL(k_output, dim3(wb), dim3(kGridBlock), 0, st, ev, kp, sc, out);
   post(K_OUTPUT);
   return hipGetLastError();
 }

@@ -81,6 +81,7 @@ int validate(const tpc_event* ev, const tpc_geometry* geo, const tpc_params* p) 
   if (!(p->nf_chi2_max >= 0.f)) return fail(TPC_ERR_INVALID_ARG, "nf_chi2_max must be >= 0");
   if (p->min_seed_len < 2 || p->min_seed_len > geo->n_rows)
     return fail(TPC_ERR_INVALID_ARG, "min_seed_len must be in [2, n_rows]");
+  if (p->seed_window < 2) return fail(TPC_ERR_INVALID_ARG, "seed_window must be >= 2");
   if (!pos(p->chi2_gate)) return fail(TPC_ERR_INVALID_ARG, "chi2_gate must be > 0");
   if (p->max_miss < 0) return fail(TPC_ERR_INVALID_ARG, "max_miss must be >= 0");
   if (!(p->max_sinphi > 0.f && p->max_sinphi < 1.f))
@@ -112,6 +113,7 @@ KParams make_kparams(const tpc_geometry* geo, float bz, const tpc_params* p) {
   k.nf_win_z = p->nf_win_z;
   k.nf_chi2_max = p->nf_chi2_max;
   k.min_seed_len = p->min_seed_len;
+  k.seed_window = p->seed_window;
   k.chi2_gate = p->chi2_gate;
   k.max_miss = p->max_miss;
   k.max_sinphi = p->max_sinphi;
@@ -250,6 +252,7 @@ void tpc_params_default(tpc_params* p) {
   p->nf_win_z = 4.0f;
   p->nf_chi2_max = 25.0f;
   p->min_seed_len = 3;
+  p->seed_window = 16;
   p->chi2_gate = 16.0f;
   p->max_miss = 10;
   p->max_sinphi = 0.95f;

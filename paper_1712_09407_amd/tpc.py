@@ -38,6 +38,7 @@ class Event(C.Structure):
 class Params(C.Structure):
     _fields_ = [("sigma_y", C.c_float), ("sigma_z", C.c_float), ("nf_win_y", C.c_float),
                 ("nf_win_z", C.c_float), ("nf_chi2_max", C.c_float), ("min_seed_len", C.c_int32),
+                ("seed_window", C.c_int32),
                 ("chi2_gate", C.c_float), ("max_miss", C.c_int32), ("max_sinphi", C.c_float),
                 ("alpha", C.c_float), ("beta", C.c_float), ("min_clusters", C.c_int32),
                 ("min_pt", C.c_float), ("prior_sinphi", C.c_float), ("prior_tanl", C.c_float),

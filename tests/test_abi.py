@@ -72,7 +72,7 @@ def test_validation_accepts_a_valid_call():
 @pytest.mark.parametrize("case", [
     "rows_small", "rows_big", "rows_not_increasing", "sectors_zero", "clusters_negative",
     "y_null", "offsets_null", "sigma_zero", "gate_zero", "sinphi_one", "beta_zero",
-    "min_clusters_small", "seed_len_one", "min_pt_zero", "prior_zero", "nan_window",
+    "min_clusters_small", "seed_len_one", "seed_window_one", "min_pt_zero", "prior_zero", "nan_window",
     "tan_half_zero", "max_tracklets_negative"])
 def test_validation_rejects(case):
     tpc, geo, ev = _valid_host_structs()
@@ -105,6 +105,8 @@ def test_validation_rejects(case):
         p.min_clusters = 2
     elif case == "seed_len_one":
         p.min_seed_len = 1
+    elif case == "seed_window_one":
+        p.seed_window = 1
     elif case == "min_pt_zero":
         p.min_pt = 0.0
     elif case == "prior_zero":
