@@ -79,6 +79,89 @@ def cpu_baseline(ev_host, geo_t, bz, gpu_res, n_clusters, seconds):
     return base, conc
 
 
+def _gen_batch_event(seed):
+    from paper_1712_09407_amd import synth
+    e = synth.batch_event(seed)
+    return e.y, e.z, e.row_offsets, e.sector_id
+
+
+def batched_section(tr, tpc, synth, geo, prm, n_events, steps, log_):
+    """Many events of very different multiplicity in one launch sequence
+    (graph replay, autotuned), against the plain per-event loop on the same
+    events."""
+    import concurrent.futures as cf
+    import torch
+    from paper_1712_09407_amd import tune
+    seeds = [3000 + i for i in range(n_events)]
+    workers = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                         else (os.cpu_count() or 1)))
+    log_(f"generating {n_events} batch events with {workers} processes")
+    with cf.ProcessPoolExecutor(workers) as ex:
+        host = list(ex.map(_gen_batch_event, seeds))
+    devs = [tpc.DeviceEvent.from_host(*h) for h in host]
+    n_cl = sum(d.n_clusters for d in devs)
+    # plain per-event loop over the same events
+    tr.set_tuning(use_graph=0)
+    for d in devs[:4]:
+        tr.track_event(d, geo, 0.5, prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d in devs:
+        tr.track_event(d, geo, 0.5, prm)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    # autotune, then time graph replays of the whole batch
+    name = torch.cuda.get_device_name(0)
+    rec = tune.autotune(tr, devs, geo, 0.5, prm, reps=1, device_name=name, use_cache=False,
+                        log=log_)
+    outs = None
+    res = tr.track_batch(devs, geo, 0.5, prm)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        tr.track_batch(devs, geo, 0.5, prm)
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    tr.set_tuning()
+    batched_section.host_events = host
+    return dict(workload=f"{n_events} events, multiplicity log-uniform 100-8000 tracks "
+                         f"(seeds 3000+), {n_cl} clusters", events=n_events, clusters=n_cl,
+                events_per_s=round(n_events * steps / el, 2),
+                clusters_per_s=round(n_cl * steps / el, 1),
+                ms_per_batch=round(el / steps * 1e3, 3),
+                plain_loop_events_per_s=round(n_events / plain_s, 2),
+                speedup_vs_plain=round((n_events * steps / el) / (n_events / plain_s), 3),
+                tuned=rec["best"], graph=True,
+                tracks=int(sum(r["n_tracks"] for r in res)))
+
+
+def serving_section(tpc, synth, geo, prm, host, rates, n_events, log_):
+    """Poisson arrivals of events with log-uniform multiplicity: the
+    continuous-batching server against the one-at-a-time path, same GPU."""
+    from paper_1712_09407_amd import serve
+    pool = [tpc.HostEvent(*h) for h in host]
+    out = dict(workload=f"Poisson arrivals, {len(pool)} distinct events of multiplicity "
+                        f"log-uniform 100-8000 tracks, {n_events} events per rate",
+               rates={})
+    for rate in rates:
+        row = {}
+        for name, cfg in (("continuous_batching", dict(max_batch=64, n_workers=2, use_graph=1)),
+                          ("one_at_a_time", dict(max_batch=1, n_workers=1, use_graph=0))):
+            srv = tpc.Server(geo, 0.5, prm, keep_results=0, **cfg)
+            serve.run(srv, pool, rate_hz=rate, n_events=min(64, n_events), seed=99)  # warm
+            res, _ = serve.run(srv, pool, rate_hz=rate, n_events=n_events, seed=4)
+            srv.close()
+            row[name] = {k: res[k] for k in ("p50_ms", "p99_ms", "mean_ms",
+                                              "sustained_events_per_s", "offered_events_per_s")}
+            row[name]["batches"] = res["stats"]["batches"]
+            log_(f"serve {rate} Hz {name}: {row[name]}")
+        out["rates"][str(int(rate))] = row
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +174,11 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 256 MiB device copy first (counter scale for rocprofv3)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--batch-events", type=int, default=64,
+                    help="events in the batched-path measurement (0 = skip)")
+    ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--serve-events", type=int, default=1000,
+                    help="events per arrival rate in the serving measurement (0 = skip)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -208,6 +296,15 @@ def main():
                                     updates=st["updates"] / ev_n,
                                     candidates=st["candidates"] / ev_n),
                 roofline=roof)
+    if args.batch_events > 0:
+        log("batched path ...")
+        line["batched"] = batched_section(tr, tpc, synth, geo, prm, args.batch_events,
+                                          args.batch_steps, log)
+        log("batched:", line["batched"])
+    if args.serve_events > 0 and args.batch_events > 0:
+        log("serving ...")
+        line["serving"] = serving_section(tpc, synth, geo, prm, batched_section.host_events,
+                                          (200.0, 500.0, 1000.0), args.serve_events, log)
     if not args.no_cpu_baseline:
         log("oracle baseline on the host cores ...")
         ev_host = dict(y=e.y, z=e.z, row_offsets=e.row_offsets, sector_id=e.sector_id)

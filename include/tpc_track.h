@@ -135,6 +135,18 @@ void tpc_ctx_destroy(tpc_ctx* ctx);
 int tpc_track_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float bz_tesla,
                     const tpc_params* params, tpc_tracks* out, void* hip_stream);
 
+/* Track n_events events in one launch sequence (sections 1, 3.1, 3.2): the
+ * events' sectors are tracked side by side and each event's tracks, cluster
+ * lists and cluster->track map are written to its own outputs[i], exactly as
+ * tpc_track_event would write them for that event alone (indices are the
+ * event's own).  events[i] and outputs[i] follow the rules of
+ * tpc_track_event.  Returns TPC_ERR_CAPACITY if any event's outputs are too
+ * small (every event's sizes are written; contents of those events are
+ * unspecified), TPC_ERR_INVALID_ARG if any event is invalid. */
+int tpc_track_batch(tpc_ctx* ctx, const tpc_event* events, int n_events, const tpc_geometry* geo,
+                    float bz_tesla, const tpc_params* params, tpc_tracks* outputs,
+                    void* hip_stream);
+
 /* Stage-by-stage access for checks (same kernels as tpc_track_event).
  * Runs the neighbours finder and the evolution step and copies the link
  * arrays into DEVICE buffers of n_clusters int32 each (any may be NULL):
@@ -155,6 +167,24 @@ int tpc_debug_tracklets(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* g
                         int32_t* row_hi, int32_t* n, int32_t* ndf, float* chi2, float* par,
                         void* hip_stream);
 
+/* ---- tuning --------------------------------------------------------------
+ * Knobs that change speed, never results (every setting gives bitwise the
+ * same outputs). */
+typedef struct {
+  int32_t use_graph;        /* tpc_track_batch captures its launch sequence in a HIP
+                               graph and replays it for later batches of the same
+                               shape (number of events, sector slots, capacity) */
+  int32_t construct_blocks; /* tracklet-construction grid in workgroups of 64 lanes;
+                               0 = one lane per reserved tracklet, fewer = persistent
+                               lanes that take tracklets from a queue */
+  float bin_occupancy;      /* target clusters per bin of the per-row search grids
+                               (1 .. 64; a row never gets more bins than clusters) */
+} tpc_tuning;
+void tpc_tuning_default(tpc_tuning* t);
+int tpc_ctx_set_tuning(tpc_ctx* ctx, const tpc_tuning* t);
+/* Number of HIP-graph replays done by this context (for checks). */
+int tpc_ctx_graph_launches(tpc_ctx* ctx, int64_t* n);
+
 /* ---- measurement -------------------------------------------------------
  * Kernels of one event are numbered 0 .. tpc_kernel_count()-1 in launch
  * order; tpc_kernel_name(i) names them.  With a non-zero mask, later calls
@@ -168,6 +198,50 @@ int tpc_ctx_set_timing(tpc_ctx* ctx, uint32_t kernel_mask);
  * candidate clusters tested (any pointer may be NULL). */
 int tpc_ctx_get_stats(tpc_ctx* ctx, double* kernel_ms, int64_t* kernel_launches, int64_t* work);
 int tpc_ctx_reset_stats(tpc_ctx* ctx);
+
+/* ---- serving -------------------------------------------------------------
+ * Continuous batching.  Events arrive one by one in HOST memory; an event is
+ * admitted when its device footprint (about 160 B per cluster) fits the
+ * budget still free, is staged and uploaded at once, and is tracked by the
+ * next free worker together with every other uploaded event (at most
+ * max_batch).  n_workers workers, each with its own context and stream, keep
+ * that many batches in flight, so uploads, tracking and downloads of
+ * different events overlap.  Each event's tracks are exactly those
+ * tpc_track_event gives it alone.  One worker with max_batch = 1 is the
+ * plain one-event-at-a-time path. */
+typedef struct tpc_server tpc_server;
+typedef struct {
+  int32_t device;
+  size_t hbm_budget_bytes;  /* admission budget for resident events */
+  int32_t max_batch;        /* events per launch sequence (>= 1) */
+  int32_t n_workers;        /* launch sequences in flight (1 .. 16) */
+  int32_t use_graph;        /* replay captured launch sequences */
+  int32_t keep_results;     /* copy tracks back for tpc_server_fetch */
+} tpc_server_config;
+typedef struct {
+  uint64_t tag;
+  int32_t status;           /* TPC_OK or the error of the event's batch */
+  int32_t n_tracks, n_track_clusters;
+  double t_submit, t_done;  /* tpc_server_now() clock: submit entry, results on host */
+} tpc_server_done;
+void tpc_server_config_default(tpc_server_config* cfg);
+int tpc_server_create(const tpc_server_config* cfg, const tpc_geometry* geo, float bz_tesla,
+                      const tpc_params* params, tpc_server** out);
+/* host_event: the fields of tpc_event, all HOST pointers (copied before return).
+ * TPC_ERR_BUSY: not admitted now (try again after completions). */
+int tpc_server_submit(tpc_server* srv, const tpc_event* host_event, uint64_t tag);
+/* Up to max finished events (waits up to timeout_ms for the first one). */
+int tpc_server_poll(tpc_server* srv, tpc_server_done* done, int max, int* n_done,
+                    int timeout_ms);
+/* Copies a polled event's results into HOST buffers sized by its counts
+ * (track_par [n][8], track_meta [n][4], track_cluster, cluster_track
+ * [n_clusters]; any may be NULL) and releases them. */
+int tpc_server_fetch(tpc_server* srv, uint64_t tag, float* track_par, int32_t* track_meta,
+                     int32_t* track_cluster, int32_t* cluster_track);
+int tpc_server_stats(tpc_server* srv, int64_t* batches, int64_t* events, size_t* resident_bytes);
+double tpc_server_now(void);
+const char* tpc_server_last_error(void);
+void tpc_server_destroy(tpc_server* srv);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* tpc_last_error(void);

@@ -10,7 +10,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtpctrack.so")
-SOURCES = ["tpc_kernels.hip", "tpc_runtime.cpp"]
+SOURCES = ["tpc_kernels.hip", "tpc_runtime.cpp", "tpc_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # packed FP32 instructions stay off (see the design notes)
@@ -21,7 +21,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 def build() -> str:
     """Compile every HIP source into libtpctrack.so (always rebuilds)."""
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+    cmd = [HIPCC, *FLAGS, *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp, "-lpthread"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

@@ -25,6 +25,8 @@ struct KParams {
   int32_t min_clusters;
   float max_qpt;  // 1 / min_pt
   float prior_sinphi, prior_tanl, prior_qpt;
+  float bin_occupancy;     // target clusters per search-grid bin
+  int32_t construct_blocks;  // constructor grid (0 = one lane per tracklet)
 };
 
 struct DevEvent {
@@ -34,6 +36,7 @@ struct DevEvent {
   const int32_t* sector_id;
   int32_t n_sectors;
   int32_t n_clusters;
+  const int32_t* n_dev;  // if set, the cluster count is read here (graph replays)
 };
 
 // One cluster in grid order: coordinates and event index in one 16-byte load.
@@ -97,6 +100,44 @@ struct Outputs {
   int32_t* cluster_track;
 };
 
+// One event of a batch: the caller's device arrays and outputs, and where the
+// event sits in the concatenated batch.
+struct BatchEventDesc {
+  const float* y;
+  const float* z;
+  const int32_t* ro;
+  const int32_t* sector_id;
+  int32_t n_clusters, n_sectors;
+  int32_t cbase, sbase;  // first cluster / first sector slot of the event in the batch
+  float* track_par;
+  int32_t* track_meta;
+  int32_t* track_cluster;
+  int32_t* cluster_track;
+  int32_t cap_tracks, cap_track_clusters;
+};
+
+// Device buffers of a batch: the concatenated event and its outputs.
+struct BatchBuffers {
+  float* y;
+  float* z;
+  int32_t* ro;          // [S*n_rows + 1]
+  int32_t* sector_id;   // [S]
+  float* par;           // [cap_tracks][8]
+  int32_t* meta;        // [cap_tracks][4]
+  int32_t* tcl;         // [N]
+  int32_t* ctr;         // [N]
+  int32_t cap_tracks;
+  int32_t* ev_counts;   // [E][2]: tracks, track clusters of each event
+  BatchEventDesc* desc; // [E]
+  int32_t* hdr;         // [4]: total clusters of the batch (read by graph replays)
+};
+
+// Clears the counters, then gathers the events (so that it can flag bad offsets).
+hipError_t enqueue_batch_gather(const BatchBuffers& bb, const Scratch& sc, int n_events,
+                                int n_rows, int n_total, int s_total, hipStream_t st);
+hipError_t enqueue_batch_scatter(const BatchBuffers& bb, const Scratch& sc, int n_events,
+                                 hipStream_t st);
+
 size_t scratch_bytes(int64_t n_clusters, int64_t n_rowslots, int64_t cap_tl);
 void scratch_carve(void* base, int64_t n_clusters, int64_t n_rowslots, int64_t cap_tl,
                    Scratch* sc);
@@ -118,6 +159,6 @@ struct KernelTimer {
 enum Stage { STAGE_LINKS = 1, STAGE_SEEDS = 2, STAGE_TRACKLETS = 3, STAGE_ALL = 4 };
 hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& sc,
                          const Outputs& out, int upto, hipStream_t st,
-                         const KernelTimer* timer = nullptr);
+                         const KernelTimer* timer = nullptr, bool zero_counters = true);
 
 }  // namespace tpc

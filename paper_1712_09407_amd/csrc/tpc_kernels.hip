@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(DevEvent ev, KParams kp, Sc
   __shared__ int s_w[kGridBlock / 64];
   const int rs = blockIdx.x;
   const int R = ev.n_sectors * kp.n_rows;
-  const int N = ev.n_clusters;
+  const int N = ev.n_dev ? *ev.n_dev : ev.n_clusters;
   const int tid = threadIdx.x;
   int b = ev.ro[rs], e = ev.ro[rs + 1];
   bool bad = b < 0 || e < b || e > N || (rs == 0 && b != 0) || (rs == R - 1 && e != N);
@@ -180,7 +180,11 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(DevEvent ev, KParams kp, Sc
   float wz = zmax - zmin;
   if (!(wz > 1e-3f)) wz = 1e-3f;
   g.z0 = (n > 0 && isfinite(zmin)) ? zmin : 0.f;
-  int nbt = n < 1 ? 1 : (n > kMaxBins ? kMaxBins : n);
+  // a row owns n + 1 bin slots (bins[] is laid out per row at b + rs): never
+  // more bins than clusters, whatever the occupancy asks for
+  int nbt = (int)((float)n / kp.bin_occupancy);
+  nbt = min(nbt, min(n, kMaxBins));
+  nbt = nbt < 1 ? 1 : nbt;
   int ny = clampi((int)(sqrtf((float)nbt * wy / wz) + 0.5f), 1, nbt);
   int nz = clampi(nbt / ny, 1, nbt);
   g.ny = ny;
@@ -1133,6 +1137,101 @@ __global__ __launch_bounds__(kGridBlock) void k_output(DevEvent ev, KParams kp, 
   }
 }
 
+// ------------------------------------------------------------------ batches
+//
+// A batch is tracked as one event whose sector slots are those of all its
+// events side by side: sectors never interact, and every tie is broken by
+// comparing cluster indices that keep their order within an event, so each
+// event's tracks are exactly those it gets alone.
+
+__global__ __launch_bounds__(kGridBlock) void k_batch_gather(BatchBuffers bb, int32_t* counters,
+                                                             int n_rows, int n_total,
+                                                             int s_total) {
+  const BatchEventDesc d = bb.desc[blockIdx.y];
+  const int stride = gridDim.x * kGridBlock;
+  {  // each event's own offsets must be a partition of [0, n_clusters]
+    const int nro_ = d.n_sectors * n_rows;
+    for (int r = blockIdx.x * kGridBlock + threadIdx.x; r <= nro_; r += stride) {
+      const int v = d.ro[r];
+      bool bad = v < 0 || v > d.n_clusters || (r < nro_ && d.ro[r + 1] < v) ||
+                 (r == 0 && v != 0) || (r == nro_ && v != d.n_clusters);
+      if (bad) atomicOr(&counters[C_ERR], E_OFFSETS);
+    }
+  }
+  for (int i = blockIdx.x * kGridBlock + threadIdx.x; i < d.n_clusters; i += stride) {
+    bb.y[d.cbase + i] = d.y[i];
+    bb.z[d.cbase + i] = d.z[i];
+  }
+  const int nro = d.n_sectors * n_rows;
+  for (int r = blockIdx.x * kGridBlock + threadIdx.x; r < nro; r += stride)
+    bb.ro[d.sbase * n_rows + r] = d.ro[r] + d.cbase;
+  for (int q = blockIdx.x * kGridBlock + threadIdx.x; q < d.n_sectors; q += stride)
+    bb.sector_id[d.sbase + q] = d.sector_id[q];
+  if (blockIdx.y == gridDim.y - 1 && blockIdx.x == 0 && threadIdx.x == 0)
+    bb.ro[s_total * n_rows] = d.ro[nro] + d.cbase;  // == n_total when offsets are valid
+}
+
+// First track whose seed (an event-global index of the batch) is >= c.
+__device__ __forceinline__ int first_track_from(const int32_t* meta, int n_tracks, int c) {
+  int lo = 0, hi = n_tracks;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (meta[(size_t)mid * 4 + 3] < c)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kGridBlock) void k_batch_scatter(BatchBuffers bb, Scratch sc) {
+  if (__builtin_nontemporal_load(&sc.counters[C_ERR]) != 0) return;
+  const int e = blockIdx.y;
+  const BatchEventDesc d = bb.desc[e];
+  const int nt_all = sc.counters[C_TRACKS];
+  const int nc_all = sc.counters[C_TRACK_CLUSTERS];
+  const int t0 = first_track_from(bb.meta, nt_all, d.cbase);
+  const int t1 = first_track_from(bb.meta, nt_all, d.cbase + d.n_clusters);
+  const int o0 = t0 < nt_all ? bb.meta[(size_t)t0 * 4 + 2] : nc_all;
+  const int o1 = t1 < nt_all ? bb.meta[(size_t)t1 * 4 + 2] : nc_all;
+  const int nt = t1 - t0, nc = o1 - o0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    bb.ev_counts[2 * e] = nt;
+    bb.ev_counts[2 * e + 1] = nc;
+  }
+  if (nt > d.cap_tracks || nc > d.cap_track_clusters) return;  // reported, nothing written
+  const int stride = gridDim.x * kGridBlock;
+  const int tid = blockIdx.x * kGridBlock + threadIdx.x;
+  for (int j = tid; j < nt * 8; j += stride) d.track_par[j] = bb.par[(size_t)t0 * 8 + j];
+  for (int j = tid; j < nt; j += stride) {
+    const int32_t* m = bb.meta + (size_t)(t0 + j) * 4;
+    int32_t* o = d.track_meta + (size_t)j * 4;
+    o[0] = m[0];
+    o[1] = m[1];
+    o[2] = m[2] - o0;
+    o[3] = m[3] - d.cbase;
+  }
+  for (int j = tid; j < nc; j += stride) d.track_cluster[j] = bb.tcl[o0 + j] - d.cbase;
+  for (int i = tid; i < d.n_clusters; i += stride) {
+    const int v = bb.ctr[d.cbase + i];
+    d.cluster_track[i] = v < 0 ? -1 : v - t0;
+  }
+}
+
+hipError_t enqueue_batch_gather(const BatchBuffers& bb, const Scratch& sc, int n_events,
+                                int n_rows, int n_total, int s_total, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, sc.counters);
+  hipLaunchKernelGGL(k_batch_gather, dim3(64, n_events), dim3(kGridBlock), 0, st, bb,
+                     sc.counters, n_rows, n_total, s_total);
+  return hipGetLastError();
+}
+
+hipError_t enqueue_batch_scatter(const BatchBuffers& bb, const Scratch& sc, int n_events,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_scatter, dim3(64, n_events), dim3(kGridBlock), 0, st, bb, sc);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ host side
 
 static inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -1214,7 +1313,8 @@ const char* const kKernelNames[K_NUM] = {
     "k_assign", "k_select", "k_tl_reduce", "k_tl_scan", "k_output"};
 
 hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& sc,
-                         const Outputs& out, int upto, hipStream_t st, const KernelTimer* tm) {
+                         const Outputs& out, int upto, hipStream_t st, const KernelTimer* tm,
+                         bool zero_counters) {
   const int R = ev.n_sectors * kp.n_rows;
   auto pre = [&](int k) {
     if (tm && (tm->mask >> k & 1u)) (void)hipEventRecord(tm->ev[k][0], st);
@@ -1223,7 +1323,7 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
     if (tm && (tm->mask >> k & 1u)) (void)hipEventRecord(tm->ev[k][1], st);
   };
   pre(K_ZERO);
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, sc.counters);
+  if (zero_counters) hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, sc.counters);
   post(K_ZERO);
   pre(K_GRID);
   hipLaunchKernelGGL(k_grid, dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc, out.cluster_track);
@@ -1242,7 +1342,7 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
   hipLaunchKernelGGL(k_seed_write, dim3(R), dim3(kGridBlock), 0, st, ev, sc);
   post(K_SEED_WRITE);
   if (upto <= STAGE_SEEDS) return hipGetLastError();
-  const int nb = tl_blocks(sc.cap_tl);
+  const int nb = kp.construct_blocks > 0 ? kp.construct_blocks : tl_blocks(sc.cap_tl);
   pre(K_CONSTRUCT);
   hipLaunchKernelGGL(k_construct, dim3(nb), dim3(kTlBlock), 0, st, ev, kp, sc);
   post(K_CONSTRUCT);

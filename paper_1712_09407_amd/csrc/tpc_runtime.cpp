@@ -44,6 +44,20 @@ struct tpc_ctx {
   double kernel_ms[tpc::K_NUM] = {};
   int64_t kernel_launches[tpc::K_NUM] = {};
   int64_t work[5] = {};     // events, tracklets, helix steps, updates, candidates
+  // batches
+  void* batch_arena = nullptr;
+  size_t batch_bytes = 0;
+  void* h_batch = nullptr;  // pinned: descriptors out, per-event counts back
+  size_t h_batch_bytes = 0;
+  tpc_tuning tuning{1, 0, 1.0f};
+  // captured batch launch sequence and what it was captured for
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  uint64_t graph_key = 0;
+  int64_t graph_ncap = 0;
+  int64_t graph_launches = 0;
+  hipStream_t graph_stream = nullptr;  // capture is not allowed on the legacy default stream
+  hipEvent_t graph_dep = nullptr;
 };
 
 namespace tpc {
@@ -124,7 +138,15 @@ KParams make_kparams(const tpc_geometry* geo, float bz, const tpc_params* p) {
   k.prior_sinphi = p->prior_sinphi;
   k.prior_tanl = p->prior_tanl;
   k.prior_qpt = p->prior_qpt;
+  k.bin_occupancy = 1.0f;
+  k.construct_blocks = 0;
   return k;
+}
+
+uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* p = (const unsigned char*)data;
+  for (size_t i = 0; i < n; ++i) h = (h ^ p[i]) * 1099511628211ull;
+  return h;
 }
 
 DevEvent make_devevent(const tpc_event* ev) {
@@ -135,6 +157,7 @@ DevEvent make_devevent(const tpc_event* ev) {
   d.sector_id = ev->sector_id;
   d.n_sectors = ev->n_sectors;
   d.n_clusters = (int32_t)ev->n_clusters;
+  d.n_dev = nullptr;
   return d;
 }
 
@@ -183,7 +206,9 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   const int64_t N = ev->n_clusters, R = (int64_t)ev->n_sectors * geo->n_rows;
-  const KParams kp = make_kparams(geo, bz, p);
+  KParams kp = make_kparams(geo, bz, p);
+  kp.bin_occupancy = ctx->tuning.bin_occupancy;
+  kp.construct_blocks = ctx->tuning.construct_blocks;
   const DevEvent dev = make_devevent(ev);
   int64_t T = default_tracklets(ctx, N, p);
   for (int attempt = 0; attempt < 2; ++attempt) {
@@ -233,6 +258,270 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
     ctx->work[3] += (uint32_t)c[C_UPDATES];
     ctx->work[4] += (uint32_t)c[C_CANDS];
     if (sc_out) *sc_out = sc;
+    return TPC_OK;
+  }
+  return fail(TPC_ERR_OVERFLOW, "tracklet reservation retry failed");
+}
+
+
+int ensure_batch(tpc_ctx* ctx, int64_t N, int64_t S, int n_rows, int E, int64_t cap_tracks,
+                 BatchBuffers* bb, BatchEventDesc** h_desc, int32_t** h_counts,
+                 hipStream_t st) {
+  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t need = al(4 * (size_t)N) * 2 + al(4 * ((size_t)S * n_rows + 1)) + al(4 * (size_t)S) +
+                      al(32 * (size_t)cap_tracks) + al(16 * (size_t)cap_tracks) +
+                      al(4 * (size_t)N) * 2 + al(8 * (size_t)E) + al(sizeof(BatchEventDesc) * E) +
+                      al(16);
+  hipError_t e;
+  if (need > ctx->batch_bytes) {
+    if (ctx->budget && need + ctx->arena_bytes > ctx->budget)
+      return fail(TPC_ERR_OOM, "batch buffers of %zu bytes exceed the context budget", need);
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (ctx->batch_arena) (void)hipFree(ctx->batch_arena);
+    ctx->batch_arena = nullptr;
+    ctx->batch_bytes = 0;
+    e = hipMalloc(&ctx->batch_arena, need + need / 4);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(TPC_ERR_OOM, "hipMalloc(%zu) failed for the batch", need + need / 4);
+    }
+    ctx->batch_bytes = need + need / 4;
+  }
+  const size_t hneed = al(sizeof(BatchEventDesc) * E) + al(16) + 8 * (size_t)E + 64;
+  if (hneed > ctx->h_batch_bytes) {
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (ctx->h_batch) (void)hipHostFree(ctx->h_batch);
+    ctx->h_batch = nullptr;
+    ctx->h_batch_bytes = 0;
+    e = hipHostMalloc(&ctx->h_batch, 2 * hneed, hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(e, "hipHostMalloc(batch)");
+    ctx->h_batch_bytes = 2 * hneed;
+  }
+  char* p = (char*)ctx->batch_arena;
+  auto take = [&](size_t b) {
+    void* q = p;
+    p += al(b);
+    return q;
+  };
+  bb->y = (float*)take(4 * (size_t)N);
+  bb->z = (float*)take(4 * (size_t)N);
+  bb->ro = (int32_t*)take(4 * ((size_t)S * n_rows + 1));
+  bb->sector_id = (int32_t*)take(4 * (size_t)S);
+  bb->par = (float*)take(32 * (size_t)cap_tracks);
+  bb->meta = (int32_t*)take(16 * (size_t)cap_tracks);
+  bb->tcl = (int32_t*)take(4 * (size_t)N);
+  bb->ctr = (int32_t*)take(4 * (size_t)N);
+  bb->ev_counts = (int32_t*)take(8 * (size_t)E);
+  bb->desc = (BatchEventDesc*)take(sizeof(BatchEventDesc) * E);
+  bb->hdr = (int32_t*)take(16);
+  bb->cap_tracks = (int32_t)cap_tracks;
+  *h_desc = (BatchEventDesc*)ctx->h_batch;
+  *h_counts = (int32_t*)((char*)ctx->h_batch + al(sizeof(BatchEventDesc) * E) + al(16));
+  return TPC_OK;
+}
+
+int check_outputs(const tpc_event* ev, const tpc_tracks* out) {
+  if (!out || !out->n_tracks || !out->n_track_clusters)
+    return fail(TPC_ERR_INVALID_ARG, "out or its size pointers are null");
+  if (out->cap_tracks < 0 || out->cap_track_clusters < 0)
+    return fail(TPC_ERR_INVALID_ARG, "negative capacity");
+  if ((out->cap_tracks > 0 && (!out->track_par || !out->track_meta)) ||
+      (out->cap_track_clusters > 0 && !out->track_cluster))
+    return fail(TPC_ERR_INVALID_ARG, "output array is null");
+  if (ev && ev->n_clusters > 0 && !out->cluster_track)
+    return fail(TPC_ERR_INVALID_ARG, "cluster_track is null");
+  return TPC_OK;
+}
+
+int run_batch(tpc_ctx* ctx, const tpc_event* evs, int E, const tpc_geometry* geo, float bz,
+              const tpc_params* p, tpc_tracks* outs, hipStream_t st) {
+  if (!evs || !outs || E < 1) return fail(TPC_ERR_INVALID_ARG, "need at least one event");
+  int64_t N = 0, S = 0;
+  for (int e = 0; e < E; ++e) {
+    int rc = validate(&evs[e], geo, p);
+    if (rc) return fail(rc, "event %d: %s", e, g_err.c_str());
+    rc = check_outputs(&evs[e], &outs[e]);
+    if (rc) return fail(rc, "event %d: %s", e, g_err.c_str());
+    N += evs[e].n_clusters;
+    S += evs[e].n_sectors;
+  }
+  if (!std::isfinite(bz)) return fail(TPC_ERR_INVALID_ARG, "bz must be finite");
+  if (S * geo->n_rows + N + 1 > 0x7fffffffLL || S > 0x7fffffffLL / geo->n_rows)
+    return fail(TPC_ERR_INVALID_ARG, "batch too large for int32 indexing");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  const int64_t R = S * geo->n_rows;
+  const bool use_graph = ctx->tuning.use_graph != 0;
+  if (use_graph) {
+    // graph work runs on the context's own stream, after the caller's stream
+    if (!ctx->graph_stream) {
+      e = hipStreamCreateWithFlags(&ctx->graph_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+      e = hipEventCreateWithFlags(&ctx->graph_dep, hipEventDisableTiming);
+      if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
+    }
+    e = hipEventRecord(ctx->graph_dep, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->graph_stream, ctx->graph_dep, 0);
+    if (e != hipSuccess) return hip_fail(e, "stream ordering");
+    st = ctx->graph_stream;
+  }
+  // With a graph, buffers are laid out for a capacity that later batches of
+  // the same shape reuse; without, for this batch.
+  int64_t ncap = N;
+  if (use_graph) {
+    ncap = ctx->graph_ncap > N ? ctx->graph_ncap : ((N + (1 << 20) - 1) >> 20) << 20;
+    if (ncap < 1) ncap = 1;
+  }
+  const int64_t cap_tracks = ncap / p->min_clusters + 1;  // tracks own >= min_clusters clusters
+  BatchBuffers bb;
+  BatchEventDesc* hd;
+  int32_t* hc;
+  int rc = ensure_batch(ctx, ncap, S, geo->n_rows, E, cap_tracks, &bb, &hd, &hc, st);
+  if (rc) return rc;
+  int64_t cb = 0, sb = 0;
+  for (int i = 0; i < E; ++i) {
+    BatchEventDesc& d = hd[i];
+    d.y = evs[i].y;
+    d.z = evs[i].z;
+    d.ro = evs[i].row_offsets;
+    d.sector_id = evs[i].sector_id;
+    d.n_clusters = (int32_t)evs[i].n_clusters;
+    d.n_sectors = evs[i].n_sectors;
+    d.cbase = (int32_t)cb;
+    d.sbase = (int32_t)sb;
+    d.track_par = outs[i].track_par;
+    d.track_meta = outs[i].track_meta;
+    d.track_cluster = outs[i].track_cluster;
+    d.cluster_track = outs[i].cluster_track;
+    d.cap_tracks = outs[i].cap_tracks;
+    d.cap_track_clusters = outs[i].cap_track_clusters;
+    cb += evs[i].n_clusters;
+    sb += evs[i].n_sectors;
+  }
+  int32_t* hh = (int32_t*)(hd + E);
+  hh = (int32_t*)(((uintptr_t)hh + 255) & ~(uintptr_t)255);
+  hh[0] = (int32_t)N;
+  e = hipMemcpyAsync(bb.desc, hd, sizeof(BatchEventDesc) * E, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(bb.hdr, hh, 16, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(batch descriptors)");
+  tpc_event bev;
+  bev.n_sectors = (int32_t)S;
+  bev.sector_id = bb.sector_id;
+  bev.n_clusters = N;
+  bev.y = bb.y;
+  bev.z = bb.z;
+  bev.row_offsets = bb.ro;
+  KParams kp = make_kparams(geo, bz, p);
+  kp.bin_occupancy = ctx->tuning.bin_occupancy;
+  kp.construct_blocks = ctx->tuning.construct_blocks;
+  DevEvent dev = make_devevent(&bev);
+  if (use_graph) {
+    dev.n_clusters = (int32_t)ncap;
+    dev.n_dev = bb.hdr;
+  }
+  const Outputs o{(int32_t)cap_tracks, (int32_t)ncap, bb.par, bb.meta, bb.tcl, bb.ctr};
+  int64_t T = default_tracklets(ctx, ncap, p);
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    rc = ensure_arena(ctx, ncap, R, T, st);
+    if (rc) return rc;
+    Scratch sc;
+    scratch_carve(ctx->arena, ncap, R, T, &sc);
+    const bool graph_now = use_graph && attempt == 0;
+    const bool timed = ctx->timer.mask != 0 && !graph_now;
+    if (graph_now) {
+      uint64_t key = fnv1a(&kp, sizeof(kp));
+      const int64_t shape[6] = {E, S, ncap, T, (int64_t)(uintptr_t)ctx->arena,
+                                (int64_t)(uintptr_t)ctx->batch_arena};
+      key = fnv1a(shape, sizeof(shape), key);
+      key = fnv1a(&st, sizeof(st), key);
+      if (!ctx->graph_exec || key != ctx->graph_key) {
+        if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+        if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+        ctx->graph_exec = nullptr;
+        ctx->graph = nullptr;
+        e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        hipError_t e1 = enqueue_batch_gather(bb, sc, E, geo->n_rows, (int)ncap, (int)S, st);
+        hipError_t e2 = enqueue_event(dev, kp, sc, o, STAGE_ALL, st, nullptr, false);
+        hipError_t e3 = enqueue_batch_scatter(bb, sc, E, st);
+        e = hipStreamEndCapture(st, &ctx->graph);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e != hipSuccess) {
+          (void)hipGetLastError();
+          return hip_fail(e != hipSuccess ? e : hipErrorUnknown, "graph capture");
+        }
+        e = hipGraphInstantiate(&ctx->graph_exec, ctx->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        ctx->graph_key = key;
+        ctx->graph_ncap = ncap;
+      }
+      e = hipGraphLaunch(ctx->graph_exec, st);
+      if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+      ctx->graph_launches += 1;
+    } else {
+      e = enqueue_batch_gather(bb, sc, E, geo->n_rows, (int)ncap, (int)S, st);
+      if (e == hipSuccess)
+        e = enqueue_event(dev, kp, sc, o, STAGE_ALL, st, timed ? &ctx->timer : nullptr, false);
+      if (e == hipSuccess) e = enqueue_batch_scatter(bb, sc, E, st);
+      if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    }
+    e = hipMemcpyAsync(ctx->h_counters, sc.counters, sizeof(int32_t) * C_COUNT,
+                       hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hc, bb.ev_counts, 8 * (size_t)E, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(counts)");
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    const int32_t* c = ctx->h_counters;
+    if (c[C_ERR] & E_OFFSETS)
+      return fail(TPC_ERR_INVALID_ARG, "row_offsets of an event are not a valid partition");
+    if (graph_now && (c[C_ERR] & E_TL_OVERFLOW)) {
+      // the replay's reservation was too small: drop the graph, re-run eagerly
+      const int64_t need = c[C_SEEDS];
+      T = need + need / 8 + 64;
+      if (T > ctx->learned_tl) ctx->learned_tl = T;
+      if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+      if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+      ctx->graph_exec = nullptr;
+      ctx->graph = nullptr;
+      continue;
+    }
+    if (c[C_ERR] & E_NONFINITE)
+      return fail(TPC_ERR_INVALID_ARG, "%d clusters have non-finite coordinates", c[C_NONFINITE]);
+    if (c[C_ERR] & E_TL_OVERFLOW) {
+      const int64_t need = c[C_SEEDS];
+      if (p->max_tracklets > 0 || attempt == 1)
+        return fail(TPC_ERR_OVERFLOW, "%lld tracklets exceed the reservation of %lld",
+                    (long long)need, (long long)T);
+      T = need + need / 8 + 64;
+      if (T > ctx->learned_tl) ctx->learned_tl = T;
+      continue;
+    }
+    if (c[C_ERR] & E_CAPACITY) return fail(TPC_ERR_DEVICE, "internal batch output overflow");
+    if (timed) {
+      for (int k = 0; k < K_NUM; ++k) {
+        if (!(ctx->timer.mask >> k & 1u)) continue;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ctx->timer.ev[k][0], ctx->timer.ev[k][1]) == hipSuccess) {
+          ctx->kernel_ms[k] += ms;
+          ctx->kernel_launches[k] += 1;
+        }
+      }
+    }
+    ctx->work[0] += E;
+    ctx->work[1] += c[C_SEEDS];
+    ctx->work[2] += (uint32_t)c[C_STEPS];
+    ctx->work[3] += (uint32_t)c[C_UPDATES];
+    ctx->work[4] += (uint32_t)c[C_CANDS];
+    int status = TPC_OK;
+    for (int i = 0; i < E; ++i) {
+      *outs[i].n_tracks = hc[2 * i];
+      *outs[i].n_track_clusters = hc[2 * i + 1];
+      if (hc[2 * i] > outs[i].cap_tracks || hc[2 * i + 1] > outs[i].cap_track_clusters)
+        status = TPC_ERR_CAPACITY;
+    }
+    if (status) return fail(status, "outputs of at least one event are too small");
     return TPC_OK;
   }
   return fail(TPC_ERR_OVERFLOW, "tracklet reservation retry failed");
@@ -298,6 +587,29 @@ int tpc_kernel_count(void) { return K_NUM; }
 
 const char* tpc_kernel_name(int i) { return (i >= 0 && i < K_NUM) ? kKernelNames[i] : ""; }
 
+void tpc_tuning_default(tpc_tuning* t) {
+  if (!t) return;
+  t->use_graph = 1;
+  t->construct_blocks = 0;
+  t->bin_occupancy = 1.0f;
+}
+
+int tpc_ctx_set_tuning(tpc_ctx* ctx, const tpc_tuning* t) {
+  if (!ctx || !t) return fail(TPC_ERR_INVALID_ARG, "ctx or tuning is null");
+  if (t->construct_blocks < 0 || t->construct_blocks > (1 << 20))
+    return fail(TPC_ERR_INVALID_ARG, "construct_blocks outside [0, 2^20]");
+  if (!(t->bin_occupancy >= 1.0f && t->bin_occupancy <= 64.f))
+    return fail(TPC_ERR_INVALID_ARG, "bin_occupancy outside [1, 64]");
+  ctx->tuning = *t;
+  return TPC_OK;
+}
+
+int tpc_ctx_graph_launches(tpc_ctx* ctx, int64_t* n) {
+  if (!ctx || !n) return fail(TPC_ERR_INVALID_ARG, "ctx or n is null");
+  *n = ctx->graph_launches;
+  return TPC_OK;
+}
+
 int tpc_ctx_set_timing(tpc_ctx* ctx, uint32_t kernel_mask) {
   if (!ctx) return fail(TPC_ERR_INVALID_ARG, "ctx is null");
   hipError_t e = hipSetDevice(ctx->device);
@@ -339,26 +651,25 @@ void tpc_ctx_destroy(tpc_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  if (ctx->graph_stream) (void)hipStreamDestroy(ctx->graph_stream);
+  if (ctx->graph_dep) (void)hipEventDestroy(ctx->graph_dep);
   if (ctx->timer_ready)
     for (int k = 0; k < K_NUM; ++k)
       for (int j = 0; j < 2; ++j) (void)hipEventDestroy(ctx->timer.ev[k][j]);
   if (ctx->arena) (void)hipFree(ctx->arena);
+  if (ctx->batch_arena) (void)hipFree(ctx->batch_arena);
   if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
+  if (ctx->h_batch) (void)hipHostFree(ctx->h_batch);
   delete ctx;
 }
 
 int tpc_track_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float bz_tesla,
                     const tpc_params* params, tpc_tracks* out, void* hip_stream) {
   if (!ctx) return fail(TPC_ERR_INVALID_ARG, "ctx is null");
-  if (!out || !out->n_tracks || !out->n_track_clusters)
-    return fail(TPC_ERR_INVALID_ARG, "out or its size pointers are null");
-  if (out->cap_tracks < 0 || out->cap_track_clusters < 0)
-    return fail(TPC_ERR_INVALID_ARG, "negative capacity");
-  if ((out->cap_tracks > 0 && (!out->track_par || !out->track_meta)) ||
-      (out->cap_track_clusters > 0 && !out->track_cluster))
-    return fail(TPC_ERR_INVALID_ARG, "output array is null");
-  if (ev && ev->n_clusters > 0 && !out->cluster_track)
-    return fail(TPC_ERR_INVALID_ARG, "cluster_track is null");
+  int rc0 = check_outputs(ev, out);
+  if (rc0) return rc0;
   Outputs o{out->cap_tracks, out->cap_track_clusters, out->track_par, out->track_meta,
             out->track_cluster, out->cluster_track};
   hipStream_t st = (hipStream_t)hip_stream;
@@ -371,6 +682,13 @@ int tpc_track_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, 
     return fail(TPC_ERR_CAPACITY, "need %d tracks / %d track clusters, have %d / %d",
                 c[C_TRACKS], c[C_TRACK_CLUSTERS], out->cap_tracks, out->cap_track_clusters);
   return TPC_OK;
+}
+
+int tpc_track_batch(tpc_ctx* ctx, const tpc_event* events, int n_events,
+                    const tpc_geometry* geo, float bz_tesla, const tpc_params* params,
+                    tpc_tracks* outs, void* hip_stream) {
+  if (!ctx) return fail(TPC_ERR_INVALID_ARG, "ctx is null");
+  return run_batch(ctx, events, n_events, geo, bz_tesla, params, outs, (hipStream_t)hip_stream);
 }
 
 int tpc_debug_links(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo,

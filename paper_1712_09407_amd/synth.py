@@ -168,6 +168,8 @@ def _crossings(x_r, alpha, pt, q, tanl, phi0, z0, bz, theta_max):
         yl = -X * sa + Y * ca
         zz = z0[idx][ti] + tanl[idx][ti] * sg
         out.append((idx[ti], ri, yl, zz, np.sin(phi0[idx][ti] - alpha)))
+    if not out:
+        return [np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(0), np.zeros(0), np.zeros(0)]
     cat = [np.concatenate([o[k] for o in out]) for k in range(5)]
     return cat
 

@@ -45,6 +45,23 @@ class Params(C.Structure):
                 ("prior_qpt", C.c_float), ("max_tracklets", C.c_int32)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("use_graph", C.c_int32), ("construct_blocks", C.c_int32),
+                ("bin_occupancy", C.c_float)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("device", C.c_int32), ("hbm_budget_bytes", C.c_size_t),
+                ("max_batch", C.c_int32), ("n_workers", C.c_int32), ("use_graph", C.c_int32),
+                ("keep_results", C.c_int32)]
+
+
+class ServerDone(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("status", C.c_int32), ("n_tracks", C.c_int32),
+                ("n_track_clusters", C.c_int32), ("t_submit", C.c_double),
+                ("t_done", C.c_double)]
+
+
 class Tracks(C.Structure):
     _fields_ = [("cap_tracks", C.c_int32), ("cap_track_clusters", C.c_int32),
                 ("n_tracks", C.POINTER(C.c_int32)), ("n_track_clusters", C.POINTER(C.c_int32)),
@@ -53,9 +70,12 @@ class Tracks(C.Structure):
 
 
 EXPORTS = ["tpc_params_default", "tpc_validate", "tpc_ctx_create", "tpc_ctx_destroy",
-           "tpc_track_event", "tpc_debug_links", "tpc_debug_tracklets", "tpc_last_error",
+           "tpc_track_event", "tpc_track_batch", "tpc_debug_links", "tpc_debug_tracklets", "tpc_last_error",
            "tpc_kernel_count", "tpc_kernel_name", "tpc_ctx_set_timing", "tpc_ctx_get_stats",
-           "tpc_ctx_reset_stats"]
+           "tpc_ctx_reset_stats", "tpc_tuning_default", "tpc_ctx_set_tuning",
+           "tpc_ctx_graph_launches", "tpc_server_config_default", "tpc_server_create",
+           "tpc_server_submit", "tpc_server_poll", "tpc_server_fetch", "tpc_server_stats",
+           "tpc_server_now", "tpc_server_last_error", "tpc_server_destroy"]
 
 
 def _load():
@@ -71,6 +91,8 @@ def _load():
     L.tpc_ctx_destroy.restype = None
     L.tpc_track_event.argtypes = [C.c_void_p, P(Event), P(Geometry), C.c_float, P(Params),
                                   P(Tracks), C.c_void_p]
+    L.tpc_track_batch.argtypes = [C.c_void_p, P(Event), C.c_int, P(Geometry), C.c_float,
+                                  P(Params), P(Tracks), C.c_void_p]
     L.tpc_debug_links.argtypes = [C.c_void_p, P(Event), P(Geometry), P(Params), C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.tpc_debug_tracklets.argtypes = [C.c_void_p, P(Event), P(Geometry), C.c_float, P(Params),
@@ -81,6 +103,25 @@ def _load():
     L.tpc_ctx_set_timing.argtypes = [C.c_void_p, C.c_uint32]
     L.tpc_ctx_get_stats.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int64), P(C.c_int64)]
     L.tpc_ctx_reset_stats.argtypes = [C.c_void_p]
+    L.tpc_tuning_default.argtypes = [P(Tuning)]
+    L.tpc_tuning_default.restype = None
+    L.tpc_ctx_set_tuning.argtypes = [C.c_void_p, P(Tuning)]
+    L.tpc_ctx_graph_launches.argtypes = [C.c_void_p, P(C.c_int64)]
+    L.tpc_server_config_default.argtypes = [P(ServerConfig)]
+    L.tpc_server_config_default.restype = None
+    L.tpc_server_create.argtypes = [P(ServerConfig), P(Geometry), C.c_float, P(Params),
+                                    P(C.c_void_p)]
+    L.tpc_server_submit.argtypes = [C.c_void_p, P(Event), C.c_uint64]
+    L.tpc_server_poll.argtypes = [C.c_void_p, P(ServerDone), C.c_int, P(C.c_int), C.c_int]
+    L.tpc_server_fetch.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p]
+    L.tpc_server_stats.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int64), P(C.c_size_t)]
+    L.tpc_server_now.argtypes = []
+    L.tpc_server_now.restype = C.c_double
+    L.tpc_server_last_error.argtypes = []
+    L.tpc_server_last_error.restype = C.c_char_p
+    L.tpc_server_destroy.argtypes = [C.c_void_p]
+    L.tpc_server_destroy.restype = None
     L.tpc_last_error.argtypes = []
     L.tpc_last_error.restype = C.c_char_p
     return L
@@ -203,6 +244,21 @@ class Tracker:
                     track_cluster=out["track_cluster"][:nc.value],
                     cluster_track=out["cluster_track"][:n])
 
+    def set_tuning(self, **kw):
+        """Speed knobs (results never change): use_graph, construct_blocks,
+        bin_occupancy.  Unnamed knobs keep their defaults."""
+        tu = Tuning()
+        lib.tpc_tuning_default(C.byref(tu))
+        for k, v in kw.items():
+            setattr(tu, k, v)
+        _check(lib.tpc_ctx_set_tuning(self._h, C.byref(tu)))
+        return {k: getattr(tu, k) for k, _ in Tuning._fields_}
+
+    def graph_launches(self) -> int:
+        n = C.c_int64(0)
+        _check(lib.tpc_ctx_graph_launches(self._h, C.byref(n)))
+        return n.value
+
     def set_timing(self, kernels=None):
         """Time the named kernels (None = all, [] = off) with HIP events."""
         names = kernel_names()
@@ -224,6 +280,47 @@ class Tracker:
 
     def reset_stats(self):
         _check(lib.tpc_ctx_reset_stats(self._h))
+
+    def track_batch(self, evs, geo: Geometry, bz: float, params: Params = None, outs=None,
+                    stream=None):
+        """Track several device events in one launch sequence.  Returns one
+        dict per event, like track_event.  `outs` may hold preallocated
+        outputs (one dict per event)."""
+        import torch
+        E = len(evs)
+        if outs is None:
+            outs = []
+            for ev in evs:
+                n = ev.n_clusters
+                dev = ev.y.device
+                ct = max(16, n // 30 + 1)
+                outs.append(dict(
+                    track_par=torch.empty((ct, 8), dtype=torch.float32, device=dev),
+                    track_meta=torch.empty((ct, 4), dtype=torch.int32, device=dev),
+                    track_cluster=torch.empty(max(16, n), dtype=torch.int32, device=dev),
+                    cluster_track=torch.empty(max(n, 1), dtype=torch.int32, device=dev)))
+        sizes = [(C.c_int32(0), C.c_int32(0)) for _ in range(E)]
+        trs = (Tracks * E)(*[Tracks(int(o["track_par"].shape[0]), int(o["track_cluster"].shape[0]),
+                                    C.pointer(a), C.pointer(b), o["track_par"].data_ptr(),
+                                    o["track_meta"].data_ptr(), o["track_cluster"].data_ptr(),
+                                    o["cluster_track"].data_ptr())
+                             for o, (a, b) in zip(outs, sizes)])
+        es = (Event * E)(*[ev.cstruct() for ev in evs])
+        rc = lib.tpc_track_batch(self._h, es, E, C.byref(geo), float(bz),
+                                 C.byref(params or default_params()), trs, _stream_handle(stream))
+        _check(rc)
+        res = []
+        for ev, o, (a, b) in zip(evs, outs, sizes):
+            res.append(dict(n_tracks=a.value, n_track_clusters=b.value,
+                            track_par=o["track_par"][:a.value], track_meta=o["track_meta"][:a.value],
+                            track_cluster=o["track_cluster"][:b.value],
+                            cluster_track=o["cluster_track"][:ev.n_clusters]))
+        return res
+
+    def track_batch_raw(self, es, E, geo, bz, params, trs, stream_handle) -> int:
+        """Direct call on prebuilt ctypes arrays (no allocation), for timing loops."""
+        return lib.tpc_track_batch(self._h, es, E, C.byref(geo), float(bz), C.byref(params), trs,
+                                   stream_handle)
 
     def track_event_raw(self, e: Event, geo: Geometry, bz: float, params: Params, tr: Tracks,
                         stream_handle) -> int:
@@ -270,3 +367,84 @@ def kernel_names():
 
 def to_numpy(res: dict) -> dict:
     return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in res.items()}
+
+
+class HostEvent:
+    """An event in host memory (numpy), as a server takes it."""
+
+    def __init__(self, y, z, row_offsets, sector_id):
+        self.y = np.ascontiguousarray(y, np.float32)
+        self.z = np.ascontiguousarray(z, np.float32)
+        self.row_offsets = np.ascontiguousarray(row_offsets, np.int32)
+        self.sector_id = np.ascontiguousarray(sector_id, np.int32)
+        self.c = Event(int(self.sector_id.shape[0]), self.sector_id.ctypes.data,
+                       int(self.y.shape[0]), self.y.ctypes.data, self.z.ctypes.data,
+                       self.row_offsets.ctypes.data)
+
+    @property
+    def n_clusters(self):
+        return int(self.y.shape[0])
+
+
+class Server:
+    """Continuous-batching server (tpc_server_*)."""
+
+    def __init__(self, geo: Geometry, bz: float, params: Params = None, **cfg):
+        c = ServerConfig()
+        lib.tpc_server_config_default(C.byref(c))
+        for k, v in cfg.items():
+            setattr(c, k, v)
+        h = C.c_void_p()
+        rc = lib.tpc_server_create(C.byref(c), C.byref(geo), float(bz),
+                                   C.byref(params or default_params()), C.byref(h))
+        if rc:
+            raise TpcError(rc, lib.tpc_server_last_error().decode())
+        self._h, self.cfg, self._geo = h, c, geo
+        self._buf = (ServerDone * 1024)()
+
+    def submit(self, ev: HostEvent, tag: int) -> int:
+        """TPC_OK, or TPC_ERR_BUSY when the event is not admitted now."""
+        rc = lib.tpc_server_submit(self._h, C.byref(ev.c), int(tag))
+        if rc not in (TPC_OK, TPC_ERR_BUSY):
+            raise TpcError(rc, lib.tpc_server_last_error().decode())
+        return rc
+
+    def poll(self, timeout_ms: int = 0):
+        n = C.c_int(0)
+        _rc = lib.tpc_server_poll(self._h, self._buf, 1024, C.byref(n), int(timeout_ms))
+        return [dict(tag=d.tag, status=d.status, n_tracks=d.n_tracks,
+                     n_track_clusters=d.n_track_clusters, t_submit=d.t_submit, t_done=d.t_done)
+                for d in self._buf[:n.value]]
+
+    def fetch(self, done: dict, n_clusters: int):
+        nt, nc = done["n_tracks"], done["n_track_clusters"]
+        par = np.empty((nt, 8), np.float32)
+        meta = np.empty((nt, 4), np.int32)
+        tcl = np.empty(nc, np.int32)
+        ctr = np.empty(max(n_clusters, 1), np.int32)
+        rc = lib.tpc_server_fetch(self._h, int(done["tag"]), par.ctypes.data, meta.ctypes.data,
+                                  tcl.ctypes.data, ctr.ctypes.data)
+        if rc:
+            raise TpcError(rc, lib.tpc_server_last_error().decode())
+        return dict(n_tracks=nt, n_track_clusters=nc, track_par=par, track_meta=meta,
+                    track_cluster=tcl, cluster_track=ctr[:n_clusters])
+
+    def stats(self):
+        b, e, r = C.c_int64(0), C.c_int64(0), C.c_size_t(0)
+        _check(lib.tpc_server_stats(self._h, C.byref(b), C.byref(e), C.byref(r)))
+        return dict(batches=b.value, events=e.value, resident_bytes=r.value)
+
+    @staticmethod
+    def now() -> float:
+        return lib.tpc_server_now()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.tpc_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -230,7 +230,7 @@ def test_dense_rows_use_the_global_memory_path(orc, tracker, geo):
     """Rows with more clusters than the LDS stage holds (noise flood, as in the
     paper's section 6 incident) must give the same links."""
     cfg = synth.EventConfig(n_tracks=150, sectors=(0,), phi_range_deg=(0, 20),
-                            ignore_membrane=True, noise_frac=12.0)
+                            ignore_membrane=True, noise_frac=20.0)
     e = synth.make_event(cfg, 31)
     assert np.diff(e.row_offsets).max() > 1024
     pg, po = params_pair(orc)
