@@ -175,10 +175,15 @@ typedef struct {
                                graph and replays it for later batches of the same
                                shape (number of events, sector slots, capacity) */
   int32_t construct_blocks; /* tracklet-construction grid in workgroups of 64 lanes;
-                               0 = one lane per reserved tracklet, fewer = persistent
-                               lanes that take tracklets from a queue */
+                               0 = sized from the tracklet reservation; a smaller
+                               grid makes workgroups loop over the work */
   float bin_occupancy;      /* target clusters per bin of the per-row search grids
                                (1 .. 64; a row never gets more bins than clusters) */
+  int32_t construct_schedule; /* 0 = row-synchronous: a workgroup walks the rows of one
+                                 sector in lockstep for up to 64 of its tracklets,
+                                 the searched row staged in LDS;
+                                 1 = one lane per tracklet, each at its own row,
+                                 tracklets taken from a queue */
 } tpc_tuning;
 void tpc_tuning_default(tpc_tuning* t);
 int tpc_ctx_set_tuning(tpc_ctx* ctx, const tpc_tuning* t);

@@ -26,7 +26,8 @@ struct KParams {
   float max_qpt;  // 1 / min_pt
   float prior_sinphi, prior_tanl, prior_qpt;
   float bin_occupancy;     // target clusters per search-grid bin
-  int32_t construct_blocks;  // constructor grid (0 = one lane per tracklet)
+  int32_t construct_blocks;  // constructor grid (0 = sized from the reservation)
+  int32_t construct_schedule;  // 0 = row-synchronous, 1 = one lane per tracklet
 };
 
 struct DevEvent {
@@ -144,7 +145,7 @@ void scratch_carve(void* base, int64_t n_clusters, int64_t n_rowslots, int64_t c
 
 // Kernels of one event, in launch order (index into timing tables).
 enum KernelId {
-  K_ZERO, K_GRID, K_NF, K_EVO, K_SCAN_ROWS, K_SEED_WRITE, K_CONSTRUCT, K_ASSIGN, K_SELECT,
+  K_ZERO, K_GRID, K_NF, K_EVO, K_SCAN_ROWS, K_SEED_WRITE, K_CONSTRUCT, K_OWN,
   K_TL_REDUCE, K_TL_SCAN, K_OUTPUT, K_NUM
 };
 extern const char* const kKernelNames[K_NUM];

@@ -9,7 +9,7 @@
 //   k_zero        clear the per-event counters
 //   k_grid        per row slot: validate offsets, counting-sort the row into a
 //                 y/z bin grid (the "initialization" of section 2, done on the
-//                 device), clear the owner keys and cluster->track output
+//                 device), clear the cluster->track output
 //   k_nf          per row slot: stage rows k-1 and k+1 in LDS, best straight
 //                 neighbour pair of every cluster of row k
 //   k_evo         per row slot: keep reciprocal links, flag chain starts of
@@ -22,11 +22,12 @@
 //                 exact helix steps row by row, grid search with a chi^2 gate;
 //                 all phases in one loop; tracklets of a sector group stay
 //                 on one XCD
-//   k_assign      one lane per tracklet: weight, 64-bit atomicMax owner key
-//                 per cluster (order-free, smaller id wins ties)
-//   k_select      one lane per tracklet: owned clusters, >= min_clusters cut
-//   k_tl_reduce,  track index and cluster offset of kept tracklets (reduce
-//   k_tl_scan     spans of tracklets, then scan them with the span offsets)
+//   k_own         per sector chunk, in LDS: weight, 64-bit atomicMax owner key
+//                 per cluster (order-free, smaller id wins ties), owned
+//                 clusters per tracklet
+//   k_tl_reduce,  >= min_clusters cut; track index and cluster offset of kept
+//   k_tl_scan     tracklets (reduce spans of tracklets, then scan them with
+//                 the span offsets)
 //   k_output      one lane per tracklet: tracks, cluster lists, cluster->track
 //
 // No step depends on the order in which lanes or blocks run: every choice is
@@ -50,24 +51,18 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) {
   return v < lo ? lo : (v > hi ? hi : v);
 }
 
-// Exact decision of |a - b| <= w for finite a, b and w > 0: the rounded
-// difference is corrected by its TwoSum error, so no rounding can flip it.
-__device__ __attribute__((noinline)) bool within_exact(float a, float b, float w) {
-  float s = a - b;
-  float bb = s - a;
-  float err = (a - (s - bb)) + (-b - bb);
-  float as = fabsf(s);
-  float ae = s < 0.f ? -err : err;  // |a - b| = as + ae exactly
-  if (as < 0.5f * w || as > 2.0f * w) return as <= w;
-  float d = as - w;  // exact (Sterbenz)
-  return d <= -ae;
-}
-// The rounded difference is within 2^-24 relative of the exact one, so only
-// values within 1e-5 of the edge need the exact test.
+// Window test |a - b| <= w of the neighbours finder, decided in FP64: the
+// difference of two FP32 values is then (for coordinates of this size) exact,
+// so the decision is that of the exact values, and it is the same operation
+// as the FP64 reference takes on the same FP32 inputs.  Three instructions,
+// no branch.
 __device__ __forceinline__ bool within(float a, float b, float w) {
-  const float as = fabsf(a - b);
-  if (fabsf(as - w) > 1e-5f * w) return as <= w;
-  return within_exact(a, b, w);
+  return fabs((double)a - (double)b) <= (double)w;
+}
+// Both coordinates of p inside the window around (yc, zc); both tests are
+// always evaluated (no short-circuit branch).
+__device__ __forceinline__ bool in_window(float2 p, float yc, float zc, float wy, float wz) {
+  return ((int)within(p.x, yc, wy) & (int)within(p.y, zc, wz)) != 0;
 }
 
 __device__ __forceinline__ int bin_y(const RowGrid& g, float y) {
@@ -150,7 +145,6 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(DevEvent ev, KParams kp, Sc
     }
     zmin = fminf(zmin, z);
     zmax = fmaxf(zmax, z);
-    sc.own[i] = 0ull;
     if (cluster_track) cluster_track[i] = -1;
   }
   if (nonfin) {
@@ -277,14 +271,14 @@ __device__ __forceinline__ void nf_search(const V& D, const V& U, float yc, floa
     const int j0 = D.bins[iz * D.g.ny + dy0], j1 = D.bins[iz * D.g.ny + dy1 + 1];
     for (int j = j0; j < j1; ++j) {
       const float2 pd = D.yz_at(j);
-      if (!within(pd.x, yc, wy) || !within(pd.y, zc, wz)) continue;
+      if (!in_window(pd, yc, zc, wy, wz)) continue;
       const int idd = D.id_at(j);
       const float dyd = pd.x - yc, dzd = pd.y - zc;
       for (int kz = uz0; kz <= uz1; ++kz) {
         const int k0 = U.bins[kz * U.g.ny + uy0], k1 = U.bins[kz * U.g.ny + uy1 + 1];
         for (int k = k0; k < k1; ++k) {
           const float2 pu = U.yz_at(k);
-          if (!within(pu.x, yc, wy) || !within(pu.y, zc, wz)) continue;
+          if (!in_window(pu, yc, zc, wy, wz)) continue;
           const int idu = U.id_at(k);
           const float ry = dyd + t * ((pu.x - yc) - dyd);
           const float rz = dzd + t * ((pu.y - zc) - dzd);
@@ -314,7 +308,7 @@ __device__ __forceinline__ int nf_collect(const RowView& V, float yc, float zc, 
     const int j0 = V.bins[iz * V.g.ny + y0], j1 = V.bins[iz * V.g.ny + y1 + 1];
     for (int j = j0; j < j1; ++j) {
       const float2 p = V.yz[j];
-      if (within(p.x, yc, wy) && within(p.y, zc, wz)) {
+      if (in_window(p, yc, zc, wy, wz)) {
         if (cnt < kNfList) list[cnt][lane] = (uint16_t)j;
         ++cnt;
       }
@@ -709,52 +703,30 @@ __device__ __forceinline__ int search_row(const Scratch& sc, const RowGrid& g, i
 
 // ------------------------------------------------------------------ k_construct
 //
-// One lane per tracklet, all phases of the construction in ONE loop of row
-// steps, so that lanes of a wave stay in step whatever phase each is in:
+// One lane per tracklet.  A lane's construction is a single loop of row
+// steps, whatever phase it is in, so that the lanes of a wave stay in step:
 //   P_CHAIN  outward through the chain, clusters taken unconditionally
 //   P_UP     outward extension: search the row, chi^2 gate
 //   P_REFIT  inward from the outermost cluster with a fresh covariance
 //   P_DOWN   inward extension below the innermost cluster
-// A lane that finishes takes the next tracklet from a queue counter.
+// Two schedules run the same lane steps and give bitwise the same tracklets:
+//   k_construct_rows   row-synchronous: a one-wave workgroup takes up to 64
+//                      tracklets of ONE sector and walks the rows outward,
+//                      then inward, in lockstep; the row being searched is
+//                      staged in LDS (the next one is loaded while the
+//                      current one is used), so the search costs LDS reads
+//                      instead of two dependent global loads per step
+//   k_construct_lanes  each lane runs its own tracklet through all its steps
+//                      and takes the next one from a queue
 
-enum Phase { P_CHAIN = 0, P_UP = 1, P_REFIT = 2, P_DOWN = 3 };
+enum Phase { P_CHAIN = 0, P_UP = 1, P_REFIT = 2, P_DOWN = 3, P_DONE = 4 };
 
-__global__ __launch_bounds__(kTlBlock) void k_construct(DevEvent ev, KParams kp, Scratch sc) {
-  __shared__ float s_x[TPC_MAX_ROWS];
-  if (event_bad(sc.counters)) return;
-  for (int i = threadIdx.x; i < kp.n_rows; i += kTlBlock) s_x[i] = kp.row_x[i];
-  __syncthreads();
-  const int n_tl = min(sc.counters[C_SEEDS], sc.cap_tl);
-  const int nr = kp.n_rows;
-  Work wk;
-
-  // XCD-aware mapping: workgroups are spread round-robin over the 8 XCDs,
-  // each with its own L2.  Blocks b = g (mod 8) take the tracklets of the
-  // sectors s = g (mod 8), so one XCD reads the grids of only a few sectors.
-  // Any mapping gives the same results; this one keeps the grids in L2.
-  const int grp = blockIdx.x & 7;
-  const int blocks_g = ((int)gridDim.x - grp + 7) >> 3;
-  const int lanes_g = blocks_g * kTlBlock;
-  int total_g = 0;
-  for (int sct = grp; sct < ev.n_sectors; sct += 8)
-    total_g += sc.row_cnt[(sct + 1) * nr] - sc.row_cnt[sct * nr];
-  // k-th tracklet of this group -> tracklet index (sectors are contiguous)
-  auto group_tracklet = [&](int k) {
-    for (int sct = grp; sct < ev.n_sectors; sct += 8) {
-      const int o = sc.row_cnt[sct * nr], c = sc.row_cnt[(sct + 1) * nr] - o;
-      if (k < c) return min(o + k, n_tl);
-      k -= c;
-    }
-    return n_tl;
-  };
-  int kg = (blockIdx.x >> 3) * kTlBlock + threadIdx.x;  // first: static
-  int t = kg < total_g ? group_tracklet(kg) : n_tl;
-  // lane state
+struct Lane {
   KState s;
-  int phase = 0, r = 0, k0 = 0, rsb = 0, last_row = 0, misses = 0, n = 0, inner = 0;
-  int cn = -1, cnn = -1;            // chain: cluster of row r and the one after
-  float cy = 0.f, cz = 0.f;         // coordinates of cn / of the prefetched refit hit
-  int hc = -1;                      // refit: cluster of row r
+  int t = 0, phase = P_DONE, r = 0, k0 = 0, rsb = 0, last_row = 0, misses = 0, n = 0, inner = 0;
+  int cn = -1, cnn = -1;      // chain: cluster of row r and the one after
+  float cy = 0.f, cz = 0.f;   // coordinates of cn / of the prefetched refit hit
+  int hc = -1;                // refit: cluster of row r
   float l_sp = 0.f, l_tl = 0.f, l_q = 0.f, l_y = 0.f, l_z = 0.f;  // state at last hit
   float chi2 = 0.f;
   float o0 = 0.f, o1 = 0.f, o2 = 0.f, o3 = 0.f, o4 = 0.f, o5 = 0.f;  // output state
@@ -762,8 +734,15 @@ __global__ __launch_bounds__(kTlBlock) void k_construct(DevEvent ev, KParams kp,
   int32_t* H = nullptr;
   float2* HY = nullptr;
 
-  // Set up tracklet t: walk the seed window of its chain, fit the seed.
-  auto begin = [&](int tt) {
+  __device__ bool outward() const { return phase == P_CHAIN || phase == P_UP; }
+  __device__ bool inward() const { return phase == P_REFIT || phase == P_DOWN; }
+  __device__ bool extending() const { return phase == P_UP || phase == P_DOWN; }
+
+  // Set up tracklet tt: walk the seed window of its chain, fit the seed.
+  __device__ void begin(int tt, const DevEvent& ev, const KParams& kp, const Scratch& sc,
+                        const float* s_x) {
+    const int nr = kp.n_rows;
+    t = tt;
     const int start = sc.seeds[tt];
     const int rs0 = sc.seed_rs[tt];
     k0 = rs0 % nr;
@@ -798,9 +777,10 @@ __global__ __launch_bounds__(kTlBlock) void k_construct(DevEvent ev, KParams kp,
     misses = 0;
     n = 0;
     chi2 = 0.f;
-  };
+  }
+
   // Inward refit set-up from the outermost collected cluster.
-  auto begin_refit = [&]() {
+  __device__ void begin_refit(const KParams& kp, const float* s_x) {
     s.x = s_x[last_row];
     s.y = l_y;
     s.z = l_z;
@@ -822,126 +802,130 @@ __global__ __launch_bounds__(kTlBlock) void k_construct(DevEvent ev, KParams kp,
         cz = v.y;
       }
     }
-  };
-
-  RowGrid gn;  // grid header of the next extension row, loaded one step early
-  if (t < n_tl) begin(t);
-  while (t < n_tl) {
-    bool finish = dropped;
-    if (!finish) {
-      const RowGrid g = gn;
-      const bool ext = phase == P_UP || phase == P_DOWN;
-      // 1. one helix step for every lane, whatever its phase
-      const bool ok = propagate(s, s_x[r], kp);
-      if (ok) ++wk.steps;
-      // 2. the measurement of this row: known (chain, refit) or searched
-      int st = 2;  // 0 = cluster, 1 = no cluster (miss), 2 = stop
-      int hit = -1;
-      float my = cy, mz = cz;
-      if (ok) {
-        if (phase == P_CHAIN) {
-          st = 0;
-          hit = cn;
-        } else if (phase == P_REFIT) {
-          st = hc >= 0 ? 0 : 1;
-          hit = hc;
-        } else if (!(fabsf(s.z) > kp.z_max)) {
-          st = 1;
-          if (!(fabsf(s.y) > s_x[r] * kp.tan_half)) {
-            hit = search_row(sc, g, g.bin_base - (rsb + r), s, kp, my, mz, wk);
-            if (hit >= 0) st = 0;
-          }
-        }
-      }
-      // 3. one Kalman update for every lane that has a cluster
-      float c2 = 0.f;
-      if (st == 0) {
-        c2 = kf_update(s, my, mz, kp);
-        ++wk.updates;
-      }
-      // 4. bookkeeping of the phase
-      if (st == 2 && !ext) {
-        dropped = finish = true;  // a step through known clusters failed
-      } else if (phase == P_CHAIN || phase == P_UP) {
-        if (st == 0) {
-          last_row = r;
-          l_sp = s.sp; l_tl = s.tl; l_q = s.qpt; l_y = my; l_z = mz;
-          HY[r] = make_float2(my, mz);
-        }
-        if (st != 2) H[r] = hit;
-        if (phase == P_CHAIN) {
-          cn = cnn;
-          ++r;
-          if (cn >= 0 && r < nr) {
-            cy = ev.y[cn];
-            cz = ev.z[cn];
-            cnn = sc.up2[cn];
-          } else {
-            phase = P_UP;
-            misses = 0;
-            if (r >= nr) begin_refit();
-          }
-        } else {
-          misses = st == 0 ? 0 : misses + 1;
-          ++r;
-          if (st == 2 || misses > kp.max_miss || r >= nr) begin_refit();
-        }
-      } else {  // P_REFIT or P_DOWN: collected clusters enter the final fit
-        if (st == 0) {
-          chi2 += c2;
-          ++n;
-          inner = r;
-          o0 = s.x; o1 = s.y; o2 = s.z; o3 = s.sp; o4 = s.tl; o5 = s.qpt;
-        }
-        if (phase == P_DOWN) {
-          if (st != 2) H[r] = hit;
-          misses = st == 0 ? 0 : misses + 1;
-          --r;
-          if (st == 2 || misses > kp.max_miss || r < 0) finish = true;
-        } else {
-          --r;
-          if (r >= k0) {
-            hc = H[r];
-            if (hc >= 0) {
-              const float2 v = HY[r];
-              cy = v.x;
-              cz = v.y;
-            }
-          }
-        }
-      }
-      // a refit that reaches (or starts) below the chain start continues as P_DOWN
-      if (!finish && phase == P_REFIT && r < k0) {
-        phase = P_DOWN;
-        misses = 0;
-        if (r < 0) finish = true;
-      }
-      if (!finish && (phase == P_UP || phase == P_DOWN)) gn = sc.grid[rsb + r];
-    }
-    if (finish) {
-      if (dropped) {
-        sc.row_lo[t] = 0;
-        sc.row_hi[t] = -1;
-        sc.n[t] = 0;
-        sc.ndf[t] = 0;
-        sc.chi2[t] = 0.f;
-      } else {
-        sc.row_lo[t] = inner;
-        sc.row_hi[t] = last_row;
-        sc.n[t] = n;
-        sc.ndf[t] = 2 * n - 5;
-        sc.chi2[t] = chi2;
-      }
-      float* P = sc.par + (size_t)t * 6;
-      P[0] = dropped ? 0.f : o0; P[1] = dropped ? 0.f : o1; P[2] = dropped ? 0.f : o2;
-      P[3] = dropped ? 0.f : o3; P[4] = dropped ? 0.f : o4; P[5] = dropped ? 0.f : o5;
-      // refill from this group's queue (only when it has more tracklets than lanes)
-      kg = lanes_g < total_g ? lanes_g + atomicAdd(&sc.counters[C_QUEUE + grp], 1) : total_g;
-      t = kg < total_g ? group_tracklet(kg) : n_tl;
-      if (t < n_tl) begin(t);
-    }
   }
-  // one atomic per wave and counter
+
+  // One row step at row r.  search(my, mz) returns the best cluster of the
+  // row inside the chi^2 gate (or -1) and its coordinates.  Returns true when
+  // the tracklet is finished (or dropped).
+  template <class Search>
+  __device__ bool step(const DevEvent& ev, const KParams& kp, const Scratch& sc, const float* s_x,
+                       Search&& search, Work& wk) {
+    const int nr = kp.n_rows;
+    bool finish = false;
+    const bool ext = extending();
+    // 1. one helix step for every lane, whatever its phase
+    const bool ok = propagate(s, s_x[r], kp);
+    if (ok) ++wk.steps;
+    // 2. the measurement of this row: known (chain, refit) or searched
+    int st = 2;  // 0 = cluster, 1 = no cluster (miss), 2 = stop
+    int hit = -1;
+    float my = cy, mz = cz;
+    if (ok) {
+      if (phase == P_CHAIN) {
+        st = 0;
+        hit = cn;
+      } else if (phase == P_REFIT) {
+        st = hc >= 0 ? 0 : 1;
+        hit = hc;
+      } else if (!(fabsf(s.z) > kp.z_max)) {
+        st = 1;
+        if (!(fabsf(s.y) > s_x[r] * kp.tan_half)) {
+          hit = search(my, mz);
+          if (hit >= 0) st = 0;
+        }
+      }
+    }
+    // 3. one Kalman update for every lane that has a cluster
+    float c2 = 0.f;
+    if (st == 0) {
+      c2 = kf_update(s, my, mz, kp);
+      ++wk.updates;
+    }
+    // 4. bookkeeping of the phase
+    if (st == 2 && !ext) {
+      dropped = finish = true;  // a step through known clusters failed
+    } else if (phase == P_CHAIN || phase == P_UP) {
+      if (st == 0) {
+        last_row = r;
+        l_sp = s.sp; l_tl = s.tl; l_q = s.qpt; l_y = my; l_z = mz;
+        HY[r] = make_float2(my, mz);
+      }
+      if (st != 2) H[r] = hit;
+      if (phase == P_CHAIN) {
+        cn = cnn;
+        ++r;
+        if (cn >= 0 && r < nr) {
+          cy = ev.y[cn];
+          cz = ev.z[cn];
+          cnn = sc.up2[cn];
+        } else {
+          phase = P_UP;
+          misses = 0;
+          if (r >= nr) begin_refit(kp, s_x);
+        }
+      } else {
+        misses = st == 0 ? 0 : misses + 1;
+        ++r;
+        if (st == 2 || misses > kp.max_miss || r >= nr) begin_refit(kp, s_x);
+      }
+    } else {  // P_REFIT or P_DOWN: collected clusters enter the final fit
+      if (st == 0) {
+        chi2 += c2;
+        ++n;
+        inner = r;
+        o0 = s.x; o1 = s.y; o2 = s.z; o3 = s.sp; o4 = s.tl; o5 = s.qpt;
+      }
+      if (phase == P_DOWN) {
+        if (st != 2) H[r] = hit;
+        misses = st == 0 ? 0 : misses + 1;
+        --r;
+        if (st == 2 || misses > kp.max_miss || r < 0) finish = true;
+      } else {
+        --r;
+        if (r >= k0) {
+          hc = H[r];
+          if (hc >= 0) {
+            const float2 v = HY[r];
+            cy = v.x;
+            cz = v.y;
+          }
+        }
+      }
+    }
+    // a refit that reaches (or starts) below the chain start continues as P_DOWN
+    if (!finish && phase == P_REFIT && r < k0) {
+      phase = P_DOWN;
+      misses = 0;
+      if (r < 0) finish = true;
+    }
+    return finish;
+  }
+
+  // Tracklet outputs; the lane is done.
+  __device__ void emit(const Scratch& sc) {
+    if (dropped) {
+      sc.row_lo[t] = 0;
+      sc.row_hi[t] = -1;
+      sc.n[t] = 0;
+      sc.ndf[t] = 0;
+      sc.chi2[t] = 0.f;
+    } else {
+      sc.row_lo[t] = inner;
+      sc.row_hi[t] = last_row;
+      sc.n[t] = n;
+      sc.ndf[t] = 2 * n - 5;
+      sc.chi2[t] = chi2;
+    }
+    sc.owned[t] = 0;  // summed over the sector's chunks by k_own
+    float* P = sc.par + (size_t)t * 6;
+    P[0] = dropped ? 0.f : o0; P[1] = dropped ? 0.f : o1; P[2] = dropped ? 0.f : o2;
+    P[3] = dropped ? 0.f : o3; P[4] = dropped ? 0.f : o4; P[5] = dropped ? 0.f : o5;
+    phase = P_DONE;
+  }
+};
+
+// One atomic per wave and counter for the work done.
+__device__ __forceinline__ void flush_work(const Work& wk, const Scratch& sc) {
   int st = wk.steps, up = wk.updates, ca = wk.cands;
   for (int d = 32; d >= 1; d >>= 1) {
     st += __shfl_xor(st, d, 64);
@@ -955,60 +939,394 @@ __global__ __launch_bounds__(kTlBlock) void k_construct(DevEvent ev, KParams kp,
   }
 }
 
+// ---- row-synchronous schedule
+
+constexpr int kRowLds = 1024;           // clusters of a row staged in LDS
+constexpr int kStage = kRowLds / 64;    // staged records per lane
+constexpr int kStageBins = kStage + 1;  // staged bin starts per lane (nb + 1 <= n + 1)
+
+// A row of the search grid staged in LDS (row-local positions and bins).
+struct RowStage {
+  float2 yz[kRowLds];
+  int32_t id[kRowLds];
+  int32_t bins[kRowLds + 1];
+};
+
+// Next row held in registers between its loads (start of an iteration) and
+// its LDS stores (end of the iteration), so the loads overlap the step.
+struct StageRegs {
+  GridRec rec[kStage];
+  int32_t bin[kStageBins];
+};
+
+__device__ __forceinline__ bool stageable(const RowGrid& g) { return g.n <= kRowLds; }
+
+__device__ __forceinline__ void stage_load(const Scratch& sc, const RowGrid& g, int row_first,
+                                           StageRegs& R) {
+  const int lane = threadIdx.x & 63;
+  if (!stageable(g) || g.n == 0) return;
+  const int nb = g.ny * g.nz;
+#pragma unroll
+  for (int k = 0; k < kStage; ++k) {
+    const int j = k * 64 + lane;
+    if (j < g.n) R.rec[k] = sc.g_rec[row_first + j];
+  }
+#pragma unroll
+  for (int k = 0; k < kStageBins; ++k) {
+    const int j = k * 64 + lane;
+    if (j <= nb) R.bin[k] = sc.bins[g.bin_base + j];
+  }
+}
+
+__device__ __forceinline__ void stage_store(const RowGrid& g, const StageRegs& R, RowStage& L) {
+  const int lane = threadIdx.x & 63;
+  if (!stageable(g) || g.n == 0) return;
+  const int nb = g.ny * g.nz;
+#pragma unroll
+  for (int k = 0; k < kStage; ++k) {
+    const int j = k * 64 + lane;
+    if (j < g.n) {
+      L.yz[j] = make_float2(R.rec[k].y, R.rec[k].z);
+      L.id[j] = R.rec[k].id;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kStageBins; ++k) {
+    const int j = k * 64 + lane;
+    if (j <= nb) L.bins[j] = R.bin[k];
+  }
+}
+
+// search_row on a row staged in LDS: same candidates, same order, same
+// arithmetic, so the same result.
+__device__ __forceinline__ int search_row_lds(const RowStage& L, const RowGrid& g, const KState& s,
+                                              const KParams& kp, float& by, float& bz_, Work& wk) {
+  if (g.n == 0) return -1;
+  const float S00 = s.C.c00 + kp.sy2, S01 = s.C.c10, S11 = s.C.c11 + kp.sz2;
+  const float idet = frcp(S00 * S11 - S01 * S01);
+  const float wy = fsqrt(kp.chi2_gate * S00) * 1.001f + 1e-4f;
+  const float wz = fsqrt(kp.chi2_gate * S11) * 1.001f + 1e-4f;
+  const int iy0 = bin_y(g, s.y - wy), iy1 = bin_y(g, s.y + wy);
+  const int iz0 = bin_z(g, s.z - wz), iz1 = bin_z(g, s.z + wz);
+  float best = INFINITY;
+  int bid = -1;
+  for (int iz = iz0; iz <= iz1; ++iz) {
+    const int j0 = L.bins[iz * g.ny + iy0];
+    const int j1 = L.bins[iz * g.ny + iy1 + 1];
+    wk.cands += j1 - j0;
+    for (int j = j0; j < j1; ++j) {
+      const float2 v = L.yz[j];
+      const float ry = v.x - s.y, rz = v.y - s.z;
+      const float chi2 = (ry * ry * S11 - 2.f * ry * rz * S01 + rz * rz * S00) * idet;
+      if (chi2 <= kp.chi2_gate) {
+        const int id = L.id[j];
+        if (chi2 < best || (chi2 == best && id < bid)) {
+          best = chi2;
+          bid = id;
+          by = v.x;
+          bz_ = v.y;
+        }
+      }
+    }
+  }
+  return bid;
+}
+
+__device__ __forceinline__ RowGrid uniform_grid(const Scratch& sc, int rs) {
+  return sc.grid[__builtin_amdgcn_readfirstlane(rs)];
+}
+
+__global__ __launch_bounds__(64) void k_construct_rows(DevEvent ev, KParams kp, Scratch sc) {
+  __shared__ float s_x[TPC_MAX_ROWS];
+  __shared__ RowStage s_row[2];
+  if (event_bad(sc.counters)) return;
+  const int lane = threadIdx.x;
+  const int nr = kp.n_rows;
+  for (int i = lane; i < nr; i += 64) s_x[i] = kp.row_x[i];
+  __syncthreads();
+  const int n_tl = min(sc.counters[C_SEEDS], sc.cap_tl);
+  Work wk;
+
+  // Work items are (sector, chunk of 64 tracklets).  Workgroups b = g (mod 8)
+  // take the chunks of the sectors s = g (mod 8), in order, with a stride of
+  // the number of such workgroups: one XCD (one L2) stages the rows of only
+  // a few sectors.  Any mapping gives the same results.
+  const int grp = blockIdx.x & 7;
+  const int nwg = ((int)gridDim.x - grp + 7) >> 3;
+  for (int item = blockIdx.x >> 3;; item += nwg) {
+    // find the sector of this item: prefix of chunk counts over the group
+    int sec = -1, q = 0, base = 0;
+    for (int s0 = grp; s0 < ev.n_sectors; s0 += 8 * 64) {
+      const int sct = s0 + 8 * lane;
+      int ch = 0;
+      if (sct < ev.n_sectors) {
+        const int a = min(sc.row_cnt[sct * nr], n_tl), b = min(sc.row_cnt[(sct + 1) * nr], n_tl);
+        ch = (b - a + 63) >> 6;
+      }
+      const int inc = wave_incl_scan(ch);
+      const int tot = __shfl(inc, 63, 64);
+      if (item < base + tot) {
+        const bool here = base + inc - ch <= item && item < base + inc;
+        const unsigned long long m = __ballot(here);
+        const int L = __ffsll((long long)m) - 1;
+        sec = s0 + 8 * L;
+        q = item - (base + __shfl(inc - ch, L, 64));
+        break;
+      }
+      base += tot;
+    }
+    sec = __builtin_amdgcn_readfirstlane(sec);
+    if (sec < 0) break;  // no more items for this workgroup
+    q = __builtin_amdgcn_readfirstlane(q);
+    const int rsb = sec * nr;
+    const int tA = min(sc.row_cnt[rsb], n_tl), tB = min(sc.row_cnt[rsb + nr], n_tl);
+    const int t = tA + q * 64 + lane;
+    Lane ln;
+    if (t < tB) {
+      ln.begin(t, ev, kp, sc, s_x);
+      if (ln.dropped) ln.emit(sc);
+    }
+    StageRegs R;
+    // two passes over the rows: outward (dir +1), then inward (dir -1)
+    for (int dir = 1; dir >= -1; dir -= 2) {
+      const bool outw = dir > 0;
+      auto active = [&]() { return outw ? ln.outward() : ln.inward(); };
+      // first row of the pass: the smallest (outward) or largest (inward) pending row
+      int ir = (ln.phase != P_DONE && active()) ? ln.r : (outw ? nr : -1);
+      for (int d = 32; d >= 1; d >>= 1) {
+        const int o = __shfl_xor(ir, d, 64);
+        ir = outw ? min(ir, o) : max(ir, o);
+      }
+      ir = __builtin_amdgcn_readfirstlane(ir);
+      if (ir < 0 || ir >= nr) continue;
+      RowGrid g = uniform_grid(sc, rsb + ir);
+      int cur = 0;
+      stage_load(sc, g, g.bin_base - (rsb + ir), R);
+      stage_store(g, R, s_row[cur]);
+      __syncthreads();
+      while (true) {
+        const int inext = ir + dir;
+        const bool more = inext >= 0 && inext < nr;
+        RowGrid gn = g;
+        if (more) {
+          gn = uniform_grid(sc, rsb + inext);
+          stage_load(sc, gn, gn.bin_base - (rsb + inext), R);
+        }
+        if (active() && ln.r == ir) {
+          const RowStage& L = s_row[cur];
+          auto search = [&](float& my, float& mz) {
+            if (stageable(g)) return search_row_lds(L, g, ln.s, kp, my, mz, wk);
+            return search_row(sc, g, g.bin_base - (rsb + ir), ln.s, kp, my, mz, wk);
+          };
+          if (ln.step(ev, kp, sc, s_x, search, wk)) ln.emit(sc);
+        }
+        const bool go = __ballot(ln.phase != P_DONE && active()) != 0ull && more;
+        if (!go) break;
+        cur ^= 1;
+        stage_store(gn, R, s_row[cur]);
+        __syncthreads();
+        g = gn;
+        ir = inext;
+      }
+      __syncthreads();  // the buffers are reused by the next pass
+    }
+  }
+  flush_work(wk, sc);
+}
+
+// ---- lane schedule
+
+__global__ __launch_bounds__(kTlBlock) void k_construct_lanes(DevEvent ev, KParams kp, Scratch sc) {
+  __shared__ float s_x[TPC_MAX_ROWS];
+  if (event_bad(sc.counters)) return;
+  for (int i = threadIdx.x; i < kp.n_rows; i += kTlBlock) s_x[i] = kp.row_x[i];
+  __syncthreads();
+  const int n_tl = min(sc.counters[C_SEEDS], sc.cap_tl);
+  const int nr = kp.n_rows;
+  Work wk;
+
+  // XCD-aware mapping: workgroups are spread round-robin over the 8 XCDs,
+  // each with its own L2.  Blocks b = g (mod 8) take the tracklets of the
+  // sectors s = g (mod 8), so one XCD reads the grids of only a few sectors.
+  // Any mapping gives the same results; this one keeps the grids in L2.
+  const int grp = blockIdx.x & 7;
+  const int blocks_g = ((int)gridDim.x - grp + 7) >> 3;
+  const int lanes_g = blocks_g * kTlBlock;
+  int total_g = 0;
+  for (int sct = grp; sct < ev.n_sectors; sct += 8)
+    total_g += sc.row_cnt[(sct + 1) * nr] - sc.row_cnt[sct * nr];
+  // k-th tracklet of this group -> tracklet index (sectors are contiguous)
+  auto group_tracklet = [&](int k) {
+    for (int sct = grp; sct < ev.n_sectors; sct += 8) {
+      const int o = sc.row_cnt[sct * nr], c = sc.row_cnt[(sct + 1) * nr] - o;
+      if (k < c) return min(o + k, n_tl);
+      k -= c;
+    }
+    return n_tl;
+  };
+  int kg = (blockIdx.x >> 3) * kTlBlock + threadIdx.x;  // first: static
+  int t = kg < total_g ? group_tracklet(kg) : n_tl;
+  Lane ln;
+  RowGrid gn;  // grid header of the next extension row, loaded one step early
+  if (t < n_tl) ln.begin(t, ev, kp, sc, s_x);
+  while (t < n_tl) {
+    bool finish = ln.dropped;
+    if (!finish) {
+      const RowGrid g = gn;
+      auto search = [&](float& my, float& mz) {
+        return search_row(sc, g, g.bin_base - (ln.rsb + ln.r), ln.s, kp, my, mz, wk);
+      };
+      finish = ln.step(ev, kp, sc, s_x, search, wk);
+      if (!finish && ln.extending()) gn = sc.grid[ln.rsb + ln.r];
+    }
+    if (finish) {
+      ln.emit(sc);
+      // refill from this group's queue (only when it has more tracklets than lanes)
+      kg = lanes_g < total_g ? lanes_g + atomicAdd(&sc.counters[C_QUEUE + grp], 1) : total_g;
+      t = kg < total_g ? group_tracklet(kg) : n_tl;
+      if (t < n_tl) ln.begin(t, ev, kp, sc, s_x);
+    }
+  }
+  flush_work(wk, sc);
+}
+
 // ------------------------------------------------------------------ selection
 //
-// One wave per tracklet: the wave's lanes cover the tracklet's rows.
+// k_own: per sector, in LDS.  Clusters of different sectors never share a
+// tracklet, so the per-cluster argmax of the weights (section 1's selection,
+// section 3.1's weight) is a sector-local reduction: a workgroup holds the
+// owner keys of a chunk of the sector's clusters in LDS, applies every
+// competing tracklet's key with LDS atomics, writes the chunk's keys out and
+// counts, per tracklet, the clusters whose key is its own.  A sector larger
+// than one chunk is split over several chunks (row ranges); the counts of a
+// tracklet are then summed over its chunks.
 
 __device__ __forceinline__ unsigned int order_bits(float w) {
   const unsigned int u = __float_as_uint(w + 0.f);  // -0 -> +0
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-__global__ __launch_bounds__(kGridBlock) void k_assign(KParams kp, Scratch sc) {
-  if (event_bad(sc.counters)) return;
-  const int n_tl = min(sc.counters[C_SEEDS], sc.cap_tl);
-  const int lane = threadIdx.x & 63;
-  const int wpb = kGridBlock / 64;
-  for (int t = blockIdx.x * wpb + (threadIdx.x >> 6); t < n_tl; t += gridDim.x * wpb) {
-    const int n = sc.n[t];
-    const float qpt = sc.par[(size_t)t * 6 + 5];
-    unsigned long long key = 0ull;
-    if (n >= kp.min_clusters && (kp.bz == 0.f || fabsf(qpt) <= kp.max_qpt)) {
-      const float w = (float)n * (kp.alpha - (sc.chi2[t] / (float)sc.ndf[t]) / kp.beta);
-      key = ((unsigned long long)order_bits(w) << 32) |
-            (unsigned long long)(0xFFFFFFFFu - (unsigned int)sc.seeds[t]);
-      const int32_t* H = sc.hits + (size_t)t * kHitStride;
-      const int lo = sc.row_lo[t], hi = sc.row_hi[t];
-      for (int r = lo + lane; r <= hi; r += 64) {
-        const int c = H[r];
-        if (c >= 0) atomicMax(&sc.own[c], key);
-      }
-    }
-    if (lane == 0) sc.key[t] = key;
+constexpr int kOwnBlock = 1024;
+constexpr int kOwnChunk = 16384;  // clusters per chunk: 128 KB of 64-bit keys
+constexpr int kOwnTable = 1024;   // tracklets per pass over the hit table
+constexpr int kOwnSplit = 4;      // workgroups per sector; chunks are dealt out
+constexpr int kQuads = kHitStride / 4;
+
+// Owner key of tracklet t, 0 if it does not compete: the weight
+// w = n (alpha - (chi^2/ndf)/beta) in order-preserving bits above the
+// complement of the seed id, so that equal weights go to the smaller id.
+__device__ __forceinline__ unsigned long long tracklet_key(const KParams& kp, const Scratch& sc,
+                                                           int t) {
+  const int n = sc.n[t];
+  const float qpt = sc.par[(size_t)t * 6 + 5];
+  if (n >= kp.min_clusters && (kp.bz == 0.f || fabsf(qpt) <= kp.max_qpt)) {
+    const float w = (float)n * (kp.alpha - (sc.chi2[t] / (float)sc.ndf[t]) / kp.beta);
+    return ((unsigned long long)order_bits(w) << 32) |
+           (unsigned long long)(0xFFFFFFFFu - (unsigned int)sc.seeds[t]);
   }
+  return 0ull;
 }
 
-__global__ __launch_bounds__(kGridBlock) void k_select(KParams kp, Scratch sc) {
+__global__ __launch_bounds__(kOwnBlock) void k_own(DevEvent ev, KParams kp, Scratch sc) {
+  __shared__ unsigned long long s_own[kOwnChunk];
+  __shared__ unsigned long long s_key[kOwnTable];
+  __shared__ int s_lh[kOwnTable];   // row_lo | row_hi << 16, clipped to the chunk's rows
+  __shared__ int s_cnt[kOwnTable];
+  __shared__ int s_rows[2];
   if (event_bad(sc.counters)) return;
+  const int nr = kp.n_rows;
+  const int s = blockIdx.x;
+  const int tid = threadIdx.x;
   const int n_tl = min(sc.counters[C_SEEDS], sc.cap_tl);
-  const int lane = threadIdx.x & 63;
-  const int wpb = kGridBlock / 64;
-  for (int t = blockIdx.x * wpb + (threadIdx.x >> 6); t < n_tl; t += gridDim.x * wpb) {
-    const unsigned long long key = sc.key[t];
-    int owned = 0;
-    if (key != 0ull) {
-      const int32_t* H = sc.hits + (size_t)t * kHitStride;
-      const int lo = sc.row_lo[t], hi = sc.row_hi[t];
-      for (int r = lo + lane; r <= hi; r += 64) {
-        const int c = H[r];
-        owned += (c >= 0 && sc.own[c] == key) ? 1 : 0;
-      }
-      for (int d = 32; d >= 1; d >>= 1) owned += __shfl_xor(owned, d, 64);
+  const int t0 = min(sc.row_cnt[s * nr], n_tl), t1 = min(sc.row_cnt[(s + 1) * nr], n_tl);
+  const int c0 = ev.ro[s * nr], c1 = ev.ro[(s + 1) * nr];
+  const int nch = (c1 - c0 + kOwnChunk - 1) / kOwnChunk;
+  for (int ch = blockIdx.y; ch < nch; ch += gridDim.y) {
+    const int cb = c0 + ch * kOwnChunk, ce = min(cb + kOwnChunk, c1);
+    // rows of the sector with clusters in [cb, ce)
+    if (tid == 0) {
+      s_rows[0] = nr;
+      s_rows[1] = -1;
     }
-    if (lane == 0) {
-      const bool kept = owned >= kp.min_clusters;
-      sc.kept[t] = kept ? 1 : 0;
-      sc.owned[t] = kept ? owned : 0;
+    for (int i = tid; i < ce - cb; i += kOwnBlock) s_own[i] = 0ull;
+    __syncthreads();
+    for (int r = tid; r < nr; r += kOwnBlock) {
+      const int lo = ev.ro[s * nr + r], hi = ev.ro[s * nr + r + 1];
+      if (hi > lo && hi > cb && lo < ce) {
+        atomicMin(&s_rows[0], r);
+        atomicMax(&s_rows[1], r);
+      }
+    }
+    __syncthreads();
+    const int rlo = s_rows[0], rhi = s_rows[1];
+    for (int pass = 0; pass < 2; ++pass) {  // 0: owner keys, 1: owned counts
+      for (int tb = t0; tb < t1; tb += kOwnTable) {
+        const int nb = min(kOwnTable, t1 - tb);
+        for (int k = tid; k < nb; k += kOwnBlock) {
+          const int t = tb + k;
+          const unsigned long long key = tracklet_key(kp, sc, t);
+          const int lo = max(sc.row_lo[t], rlo), hi = min(sc.row_hi[t], rhi);
+          s_key[k] = key;
+          s_lh[k] = (key != 0ull && lo <= hi) ? (lo | (hi << 16)) : -1;
+          s_cnt[k] = 0;
+          if (pass == 0 && ch == 0) sc.key[t] = key;
+        }
+        __syncthreads();
+        // (tracklet, 4 rows) elements of the batch; four loads in flight per lane
+        const int ne = nb * kQuads;
+        for (int e0 = 0; e0 < ne; e0 += 4 * kOwnBlock) {
+          int4 h[4];
+          int lh[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * kOwnBlock + tid;
+            lh[u] = -1;
+            h[u] = make_int4(-1, -1, -1, -1);
+            if (e < ne) {
+              const int k = e / kQuads, r0 = (e - k * kQuads) * 4;
+              const int v = s_lh[k];
+              if (v >= 0 && r0 <= (v >> 16) && r0 + 3 >= (v & 0xFFFF)) {
+                lh[u] = v;
+                h[u] = *reinterpret_cast<const int4*>(sc.hits + (size_t)(tb + k) * kHitStride + r0);
+              }
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (lh[u] < 0) continue;
+            const int e = e0 + u * kOwnBlock + tid;
+            const int k = e / kQuads, r0 = (e - k * kQuads) * 4;
+            const int lo = lh[u] & 0xFFFF, hi = lh[u] >> 16;
+            const unsigned long long key = s_key[k];
+            const int hv[4] = {h[u].x, h[u].y, h[u].z, h[u].w};
+            int cnt = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int r = r0 + j, c = hv[j];
+              if (r < lo || r > hi || c < cb || c >= ce) continue;
+              if (pass == 0)
+                atomicMax(&s_own[c - cb], key);
+              else
+                cnt += s_own[c - cb] == key ? 1 : 0;
+            }
+            if (cnt) atomicAdd(&s_cnt[k], cnt);
+          }
+        }
+        __syncthreads();
+        if (pass == 1) {
+          for (int k = tid; k < nb; k += kOwnBlock) {
+            const int v = s_cnt[k];
+            if (nch == 1)
+              sc.owned[tb + k] = v;
+            else if (v)
+              atomicAdd(&sc.owned[tb + k], v);
+          }
+        }
+        __syncthreads();
+      }
+      if (pass == 0)
+        for (int i = tid; i < ce - cb; i += kOwnBlock) sc.own[cb + i] = s_own[i];
+      __syncthreads();
     }
   }
 }
@@ -1019,7 +1337,7 @@ __global__ __launch_bounds__(kGridBlock) void k_select(KParams kp, Scratch sc) {
 constexpr int kSpanPer = 4;
 constexpr int kSpan = kScanBlock * kSpanPer;
 
-__global__ __launch_bounds__(kScanBlock) void k_tl_reduce(Scratch sc) {
+__global__ __launch_bounds__(kScanBlock) void k_tl_reduce(Scratch sc, int min_clusters) {
   __shared__ int s_w[kScanBlock / 64];
   if (event_bad(sc.counters)) return;
   const int n_tl = min(sc.counters[C_SEEDS], sc.cap_tl);
@@ -1029,8 +1347,10 @@ __global__ __launch_bounds__(kScanBlock) void k_tl_reduce(Scratch sc) {
   for (int q = 0; q < kSpanPer; ++q) {
     const int i = base + q;
     if (i < n_tl) {
-      st += sc.kept[i];
-      so += sc.owned[i];
+      const int o = sc.owned[i];
+      const bool kept = o >= min_clusters;  // section 5: at least 30 owned clusters
+      st += kept ? 1 : 0;
+      so += kept ? o : 0;
     }
   }
   int tt, to;
@@ -1042,8 +1362,8 @@ __global__ __launch_bounds__(kScanBlock) void k_tl_reduce(Scratch sc) {
   }
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_tl_scan(Scratch sc, int cap_tracks,
-                                                        int cap_track_clusters) {
+__global__ __launch_bounds__(kScanBlock) void k_tl_scan(Scratch sc, int min_clusters,
+                                                        int cap_tracks, int cap_track_clusters) {
   __shared__ int s_w[kScanBlock / 64];
   if (event_bad(sc.counters)) return;
   const int n_tl = min(sc.counters[C_SEEDS], sc.cap_tl);
@@ -1063,8 +1383,9 @@ __global__ __launch_bounds__(kScanBlock) void k_tl_scan(Scratch sc, int cap_trac
 #pragma unroll
   for (int q = 0; q < kSpanPer; ++q) {
     const int i = base + q;
-    kv[q] = i < n_tl ? sc.kept[i] : 0;
-    ov[q] = i < n_tl ? sc.owned[i] : 0;
+    const int o = i < n_tl ? sc.owned[i] : 0;
+    kv[q] = o >= min_clusters ? 1 : 0;
+    ov[q] = kv[q] ? o : 0;
     st += kv[q];
     so += ov[q];
   }
@@ -1077,6 +1398,8 @@ __global__ __launch_bounds__(kScanBlock) void k_tl_scan(Scratch sc, int cap_trac
     if (i < n_tl) {
       sc.trk_idx[i] = et;
       sc.trk_off[i] = eo;
+      sc.kept[i] = kv[q];
+      sc.owned[i] = ov[q];
     }
     et += kv[q];
     eo += ov[q];
@@ -1302,6 +1625,15 @@ static inline int tl_blocks(int64_t T) {
   if (b > 16384) b = 16384;
   return (int)(b < 1 ? 1 : b);
 }
+// Row-synchronous constructor: workgroups loop over (sector, 64-tracklet
+// chunk) items of their XCD group, so any grid is correct; this one gives
+// every item a workgroup when the groups are not more than 25% uneven.
+static inline int rows_blocks(int64_t T, int n_sectors) {
+  int64_t per_group = (T + 511) / 512 * 5 / 4 + (n_sectors + 7) / 8 + 1;
+  int64_t b = 8 * per_group;
+  if (b > 65536) b = 65536;
+  return (int)b;
+}
 static inline int wave_blocks(int64_t T) {
   int64_t b = (T + kGridBlock / 64 - 1) / (kGridBlock / 64);
   if (b > 65536) b = 65536;
@@ -1310,7 +1642,7 @@ static inline int wave_blocks(int64_t T) {
 
 const char* const kKernelNames[K_NUM] = {
     "k_zero", "k_grid", "k_nf", "k_evo", "k_scan_rows", "k_seed_write", "k_construct",
-    "k_assign", "k_select", "k_tl_reduce", "k_tl_scan", "k_output"};
+    "k_own", "k_tl_reduce", "k_tl_scan", "k_output"};
 
 hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& sc,
                          const Outputs& out, int upto, hipStream_t st, const KernelTimer* tm,
@@ -1342,25 +1674,27 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
   hipLaunchKernelGGL(k_seed_write, dim3(R), dim3(kGridBlock), 0, st, ev, sc);
   post(K_SEED_WRITE);
   if (upto <= STAGE_SEEDS) return hipGetLastError();
-  const int nb = kp.construct_blocks > 0 ? kp.construct_blocks : tl_blocks(sc.cap_tl);
   pre(K_CONSTRUCT);
-  hipLaunchKernelGGL(k_construct, dim3(nb), dim3(kTlBlock), 0, st, ev, kp, sc);
+  if (kp.construct_schedule == 0) {
+    const int nb = kp.construct_blocks > 0 ? kp.construct_blocks : rows_blocks(sc.cap_tl, ev.n_sectors);
+    hipLaunchKernelGGL(k_construct_rows, dim3(nb), dim3(64), 0, st, ev, kp, sc);
+  } else {
+    const int nb = kp.construct_blocks > 0 ? kp.construct_blocks : tl_blocks(sc.cap_tl);
+    hipLaunchKernelGGL(k_construct_lanes, dim3(nb), dim3(kTlBlock), 0, st, ev, kp, sc);
+  }
   post(K_CONSTRUCT);
   if (upto <= STAGE_TRACKLETS) return hipGetLastError();
   const int wb = wave_blocks(sc.cap_tl);
-  pre(K_ASSIGN);
-  hipLaunchKernelGGL(k_assign, dim3(wb), dim3(kGridBlock), 0, st, kp, sc);
-  post(K_ASSIGN);
-  pre(K_SELECT);
-  hipLaunchKernelGGL(k_select, dim3(wb), dim3(kGridBlock), 0, st, kp, sc);
-  post(K_SELECT);
+  pre(K_OWN);
+  hipLaunchKernelGGL(k_own, dim3(ev.n_sectors, kOwnSplit), dim3(kOwnBlock), 0, st, ev, kp, sc);
+  post(K_OWN);
   const int spans = (int)((sc.cap_tl + kSpan - 1) / kSpan);
   pre(K_TL_REDUCE);
-  hipLaunchKernelGGL(k_tl_reduce, dim3(spans), dim3(kScanBlock), 0, st, sc);
+  hipLaunchKernelGGL(k_tl_reduce, dim3(spans), dim3(kScanBlock), 0, st, sc, kp.min_clusters);
   post(K_TL_REDUCE);
   pre(K_TL_SCAN);
-  hipLaunchKernelGGL(k_tl_scan, dim3(spans), dim3(kScanBlock), 0, st, sc, out.cap_tracks,
-                     out.cap_track_clusters);
+  hipLaunchKernelGGL(k_tl_scan, dim3(spans), dim3(kScanBlock), 0, st, sc, kp.min_clusters,
+                     out.cap_tracks, out.cap_track_clusters);
   post(K_TL_SCAN);
   pre(K_OUTPUT);
   hipLaunchKernelGGL(k_output, dim3(wb), dim3(kGridBlock), 0, st, ev, kp, sc, out);

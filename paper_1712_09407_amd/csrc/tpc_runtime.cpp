@@ -140,6 +140,7 @@ KParams make_kparams(const tpc_geometry* geo, float bz, const tpc_params* p) {
   k.prior_qpt = p->prior_qpt;
   k.bin_occupancy = 1.0f;
   k.construct_blocks = 0;
+  k.construct_schedule = 0;
   return k;
 }
 
@@ -209,6 +210,7 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
   KParams kp = make_kparams(geo, bz, p);
   kp.bin_occupancy = ctx->tuning.bin_occupancy;
   kp.construct_blocks = ctx->tuning.construct_blocks;
+  kp.construct_schedule = ctx->tuning.construct_schedule;
   const DevEvent dev = make_devevent(ev);
   int64_t T = default_tracklets(ctx, N, p);
   for (int attempt = 0; attempt < 2; ++attempt) {
@@ -416,6 +418,7 @@ int run_batch(tpc_ctx* ctx, const tpc_event* evs, int E, const tpc_geometry* geo
   KParams kp = make_kparams(geo, bz, p);
   kp.bin_occupancy = ctx->tuning.bin_occupancy;
   kp.construct_blocks = ctx->tuning.construct_blocks;
+  kp.construct_schedule = ctx->tuning.construct_schedule;
   DevEvent dev = make_devevent(&bev);
   if (use_graph) {
     dev.n_clusters = (int32_t)ncap;
@@ -592,6 +595,7 @@ void tpc_tuning_default(tpc_tuning* t) {
   t->use_graph = 1;
   t->construct_blocks = 0;
   t->bin_occupancy = 1.0f;
+  t->construct_schedule = 0;
 }
 
 int tpc_ctx_set_tuning(tpc_ctx* ctx, const tpc_tuning* t) {
@@ -600,6 +604,8 @@ int tpc_ctx_set_tuning(tpc_ctx* ctx, const tpc_tuning* t) {
     return fail(TPC_ERR_INVALID_ARG, "construct_blocks outside [0, 2^20]");
   if (!(t->bin_occupancy >= 1.0f && t->bin_occupancy <= 64.f))
     return fail(TPC_ERR_INVALID_ARG, "bin_occupancy outside [1, 64]");
+  if (t->construct_schedule != 0 && t->construct_schedule != 1)
+    return fail(TPC_ERR_INVALID_ARG, "construct_schedule must be 0 or 1");
   ctx->tuning = *t;
   return TPC_OK;
 }

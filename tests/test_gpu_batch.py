@@ -120,12 +120,15 @@ def test_graph_replays_match_eager(tracker, geo, events):
             assert np.array_equal(a[k], b[k]), k
 
 
-@pytest.mark.parametrize("blocks,occ", [(0, 1.0), (64, 1.0), (512, 2.0), (0, 1.5), (2048, 4.0)])
-def test_tuning_never_changes_results(tracker, geo, events, blocks, occ):
+@pytest.mark.parametrize("blocks,occ,sched", [(0, 1.0, 0), (0, 1.0, 1), (64, 1.0, 0), (64, 1.0, 1),
+                                              (7, 1.0, 0), (512, 2.0, 1), (0, 1.5, 0),
+                                              (2048, 4.0, 0), (2048, 4.0, 1)])
+def test_tuning_never_changes_results(tracker, geo, events, blocks, occ, sched):
     devs = [dev(e) for e in events[:4]]
-    tracker.set_tuning(use_graph=0)
+    tracker.set_tuning(use_graph=0, construct_schedule=1)
     ref = [tpc.to_numpy(r) for r in tracker.track_batch(devs, geo, 0.5)]
-    tracker.set_tuning(use_graph=1, construct_blocks=blocks, bin_occupancy=occ)
+    tracker.set_tuning(use_graph=1, construct_blocks=blocks, bin_occupancy=occ,
+                       construct_schedule=sched)
     got = [tpc.to_numpy(r) for r in tracker.track_batch(devs, geo, 0.5)]
     tracker.set_tuning()
     for a, b in zip(ref, got):
@@ -148,4 +151,6 @@ def test_autotuner_picks_a_candidate(tracker, geo, events, tmp_path, monkeypatch
 def test_tuning_rejects_occupancy_below_one(tracker):
     with pytest.raises(tpc.TpcError):
         tracker.set_tuning(bin_occupancy=0.5)
+    with pytest.raises(tpc.TpcError):
+        tracker.set_tuning(construct_schedule=2)
     tracker.set_tuning()

@@ -213,6 +213,40 @@ def test_deterministic(orc, tracker, geo):
         assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("name,seed", [("c1_sector", 1), ("c2_central", 2), ("c5_stress", 5),
+                                       ("dense", 31), ("sparse", 77)])
+def test_constructor_schedules_agree_bitwise(tracker, geo, name, seed):
+    """The row-synchronous and the lane-per-tracklet constructor run the same
+    lane steps: every output bit must agree (dense rows exercise the
+    global-memory search of the row-synchronous schedule)."""
+    if name == "dense":
+        e = synth.make_event(synth.EventConfig(n_tracks=150, sectors=(0,), phi_range_deg=(0, 20),
+                                               ignore_membrane=True, noise_frac=20.0), seed)
+        assert np.diff(e.row_offsets).max() > 1024
+    elif name == "sparse":
+        e = synth.make_event(synth.EventConfig(n_tracks=3), seed)
+    else:
+        e = get_event(name, seed)
+    say("schedules", name, seed, e.n_clusters)
+    dev = dev_event(e)
+    out = []
+    for sched in (1, 0):
+        tracker.set_tuning(construct_schedule=sched)
+        tl = tracker.tracklets(dev, geo, e.bz)
+        res = tpc.to_numpy(tracker.track_event(dev, geo, e.bz))
+        out.append((tpc.to_numpy(tl), res))
+    tracker.set_tuning()
+    (tla, ra), (tlb, rb) = out
+    for k in tla:
+        if k != "hits":
+            assert np.array_equal(tla[k].view(np.uint8), tlb[k].view(np.uint8)), k
+    for t in range(len(tla["seeds"])):  # hits are defined on [row_lo, row_hi]
+        lo, hi = tla["row_lo"][t], tla["row_hi"][t]
+        assert np.array_equal(tla["hits"][t, lo:hi + 1], tlb["hits"][t, lo:hi + 1]), t
+    for k in ("track_par", "track_meta", "track_cluster", "cluster_track"):
+        assert np.array_equal(ra[k].view(np.uint8), rb[k].view(np.uint8)), k
+
+
 # ------------------------------------------------------------- edge cases
 def test_empty_and_sparse_events(orc, tracker, geo):
     ro = np.zeros(36 * 159 + 1, np.int32)
