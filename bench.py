@@ -37,9 +37,24 @@ PEAK_FP32_TFLOPS = 157.3
 FLOP_STEP = 174 + 20
 FLOP_UPDATE = 129
 FLOP_CAND = 11
-# Algorithmic HBM bytes per cluster of the streaming kernels (read once,
-# written once): see the design notes for the accounting.
-BYTES_PER_CLUSTER = {"k_grid": 8 + 8 + 12 + 8 + 4, "k_nf": 8 + 24 + 8, "k_evo": 8 + 8 + 9}
+# Algorithmic HBM bytes per cluster of the streaming kernels (each array read
+# or written once per use): k_grid reads y, z twice and writes the 16-byte grid
+# record, the bin start and cluster_track; k_nf reads the cluster's record, two
+# neighbour rows (records and bins) and writes up, dn; k_evo reads the links
+# and the partner's links and writes the reciprocal links and the start flag.
+BYTES_PER_CLUSTER = {"k_grid": 16 + 16 + 4 + 4, "k_nf": 16 + 32 + 8 + 8, "k_evo": 8 + 8 + 8 + 1}
+
+
+def path_bytes(N, tracklets, steps, cands, n_tracks, n_track_clusters):
+    """Algorithmic HBM bytes of one event through the whole path (the staged
+    accounting: every array touched once per use, row staging counted once per
+    row and neighbour, hits of a tracklet row 12 B written and read back)."""
+    b = sum(BYTES_PER_CLUSTER.values()) * N
+    b += N + 8 * tracklets                              # seed flags, seeds
+    b += 16 * cands + 12 * steps + 12 * steps           # candidates; hits written, read back
+    b += 8 * N + 2 * 4 * steps                          # owner keys; hits read twice by k_own
+    b += n_track_clusters * (4 + 8 + 8) + 48 * n_tracks  # output
+    return b
 
 
 def log(*a):
@@ -49,6 +64,16 @@ def log(*a):
 def kernel_src_sha():
     p = os.path.join(ROOT, "paper_1712_09407_amd", "csrc", "tpc_kernels.hip")
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(ev_host, geo_t, bz, gpu_res, n_clusters, seconds):
@@ -69,9 +94,13 @@ def cpu_baseline(ev_host, geo_t, bz, gpu_res, n_clusters, seconds):
         if el >= seconds or runs >= 200:
             break
     rep = concordance.compare(ref, gpu_res, n_clusters)
+    t1 = time.perf_counter()
+    oracle.track_event(ev_host, geo_t, bz, oracle.default_params(), n_threads=1)
+    single = 1.0 / (time.perf_counter() - t1)
     base = dict(value=runs / el, unit="events/s", cores=cores, kind="oracle",
                 sample=f"{runs} run(s) of the benchmark event ({n_clusters} clusters), "
-                       f"{el:.1f} s wall, {cores} threads over sectors")
+                       f"{el:.1f} s wall, {cores} threads over sectors",
+                single_thread_value=round(single, 4), cpu_model=cpu_model())
     conc = {k: rep[k] for k in ("cluster_concordance", "track_concordance", "cluster_concordance_ab",
                                 "cluster_concordance_ba", "n_tracks_a", "n_tracks_b",
                                 "par_compared", "par_fail", "par_max_rel")}
@@ -278,6 +307,20 @@ def main():
             traffic = tj.get("bytes_per_launch")
     roof["traffic"] = traffic
 
+    # the whole path against HBM: staged algorithmic bytes, and the counters
+    pb = path_bytes(N, st["tracklets"] / ev_n, st["steps"] / ev_n, st["candidates"] / ev_n,
+                    nt.value, nc.value)
+    eps = args.steps / el
+    path_hbm = dict(algorithmic_bytes_per_event=int(pb),
+                    achieved=round(pb * eps / 1e9, 2), unit="GB/s", peak=PEAK_HBM_GBS,
+                    frac=round(pb * eps / 1e9 / PEAK_HBM_GBS, 6), measured_bytes_per_event=None)
+    if os.path.exists(args.traffic_json):
+        tj = json.load(open(args.traffic_json))
+        if tj.get("kernel_src_sha") == kernel_src_sha() and tj.get("path_bytes_per_event"):
+            mb = tj["path_bytes_per_event"]
+            path_hbm.update(measured_bytes_per_event=int(mb),
+                            measured_frac=round(mb * eps / 1e9 / PEAK_HBM_GBS, 6))
+
     ms = el / args.steps * 1e3
     lat_ms = sorted(x * 1e3 for x in lat)
     p = lambda q: lat_ms[min(len(lat_ms) - 1, int(math.ceil(q * len(lat_ms))) - 1)]
@@ -295,7 +338,7 @@ def main():
                 work_per_event=dict(tracklets=st["tracklets"] / ev_n, steps=st["steps"] / ev_n,
                                     updates=st["updates"] / ev_n,
                                     candidates=st["candidates"] / ev_n),
-                roofline=roof)
+                roofline=roof, path_hbm=path_hbm)
     if args.batch_events > 0:
         log("batched path ...")
         line["batched"] = batched_section(tr, tpc, synth, geo, prm, args.batch_events,

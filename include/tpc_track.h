@@ -174,7 +174,8 @@ typedef struct {
   int32_t use_graph;        /* tpc_track_batch captures its launch sequence in a HIP
                                graph and replays it for later batches of the same
                                shape (number of events, sector slots, capacity) */
-  int32_t construct_blocks; /* tracklet-construction grid in workgroups of 64 lanes;
+  int32_t construct_blocks; /* tracklet-construction grid in workgroups of 64 lanes,
+                               rounded up to a multiple of 8 (one share per XCD);
                                0 = sized from the tracklet reservation; a smaller
                                grid makes workgroups loop over the work */
   float bin_occupancy;      /* target clusters per bin of the per-row search grids

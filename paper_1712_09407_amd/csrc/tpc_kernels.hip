@@ -1419,6 +1419,7 @@ __global__ __launch_bounds__(kGridBlock) void k_output(DevEvent ev, KParams kp, 
     return;
   }
   const int n_tl = min(sc.counters[C_SEEDS], sc.cap_tl);
+  const int n_cl = ev.n_dev ? *ev.n_dev : ev.n_clusters;
   const int lane = threadIdx.x & 63;
   const int wpb = kGridBlock / 64;
   const unsigned long long lt = (1ull << lane) - 1ull;
@@ -1428,11 +1429,11 @@ __global__ __launch_bounds__(kGridBlock) void k_output(DevEvent ev, KParams kp, 
     int off = sc.trk_off[t];
     const unsigned long long key = sc.key[t];
     const int32_t* H = sc.hits + (size_t)t * kHitStride;
-    const int lo = sc.row_lo[t], hi = sc.row_hi[t];
+    const int lo = max(sc.row_lo[t], 0), hi = min(sc.row_hi[t], kHitStride - 1);
     for (int r0 = lo; r0 <= hi; r0 += 64) {  // wave-uniform trip count
       const int r = r0 + lane;
       const int c = r <= hi ? H[r] : -1;
-      const bool mine = c >= 0 && sc.own[c] == key;
+      const bool mine = c >= 0 && c < n_cl && sc.own[c] == key;
       const unsigned long long m = __ballot(mine);
       if (mine) {
         const int k = __popcll(m & lt);
@@ -1625,6 +1626,15 @@ static inline int tl_blocks(int64_t T) {
   if (b > 16384) b = 16384;
   return (int)(b < 1 ? 1 : b);
 }
+// Both constructors give the tracklets of the sectors s = g (mod 8) to the
+// workgroups b = g (mod 8): every one of the 8 groups needs a workgroup, so
+// the grid is a non-zero multiple of 8.
+static inline int xcd_grid(int64_t b) {
+  b = (b + 7) / 8 * 8;
+  if (b < 8) b = 8;
+  if (b > (int64_t)1 << 20) b = (int64_t)1 << 20;
+  return (int)b;
+}
 // Row-synchronous constructor: workgroups loop over (sector, 64-tracklet
 // chunk) items of their XCD group, so any grid is correct; this one gives
 // every item a workgroup when the groups are not more than 25% uneven.
@@ -1676,10 +1686,11 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
   if (upto <= STAGE_SEEDS) return hipGetLastError();
   pre(K_CONSTRUCT);
   if (kp.construct_schedule == 0) {
-    const int nb = kp.construct_blocks > 0 ? kp.construct_blocks : rows_blocks(sc.cap_tl, ev.n_sectors);
+    const int nb = xcd_grid(kp.construct_blocks > 0 ? kp.construct_blocks
+                                                    : rows_blocks(sc.cap_tl, ev.n_sectors));
     hipLaunchKernelGGL(k_construct_rows, dim3(nb), dim3(64), 0, st, ev, kp, sc);
   } else {
-    const int nb = kp.construct_blocks > 0 ? kp.construct_blocks : tl_blocks(sc.cap_tl);
+    const int nb = xcd_grid(kp.construct_blocks > 0 ? kp.construct_blocks : tl_blocks(sc.cap_tl));
     hipLaunchKernelGGL(k_construct_lanes, dim3(nb), dim3(kTlBlock), 0, st, ev, kp, sc);
   }
   post(K_CONSTRUCT);

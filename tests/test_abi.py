@@ -158,3 +158,34 @@ def test_oracle_and_gpu_library_share_nothing():
         assert "tpc_oracle" not in src and "oracle/" not in src
     psrc = open(os.path.join(ROOT, "paper_1712_09407_amd", "tpc.py")).read()
     assert "import oracle" not in psrc and "from oracle" not in psrc
+
+
+STRUCTS = {  # C type name -> ctypes mirror in the binding
+    "tpc_geometry": "Geometry", "tpc_event": "Event", "tpc_params": "Params",
+    "tpc_tracks": "Tracks", "tpc_tuning": "Tuning", "tpc_server_config": "ServerConfig",
+    "tpc_server_done": "ServerDone"}
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The Python binding's ctypes structs have the header's sizes and field
+    offsets (a C program built from include/tpc_track.h prints them)."""
+    from paper_1712_09407_amd import tpc
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "tpc_track.h"', "int main(void) {"]
+    for cname, pyname in STRUCTS.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in getattr(tpc, pyname)._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", INCLUDE, str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        c, f, v = line.split()
+        got[(c, f)] = int(v)
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(tpc, pyname)
+        assert got[(cname, "size")] == C.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
