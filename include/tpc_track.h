@@ -180,11 +180,11 @@ typedef struct {
                                grid makes workgroups loop over the work */
   float bin_occupancy;      /* target clusters per bin of the per-row search grids
                                (1 .. 64; a row never gets more bins than clusters) */
-  int32_t construct_schedule; /* 0 = row-synchronous: a workgroup walks the rows of one
-                                 sector in lockstep for up to 64 of its tracklets,
-                                 the searched row staged in LDS;
-                                 1 = one lane per tracklet, each at its own row,
-                                 tracklets taken from a queue */
+  int32_t construct_schedule; /* 0 = one lane per tracklet, each at its own row,
+                                 tracklets taken from a queue;
+                                 1 = row-synchronous: a workgroup walks the rows of
+                                 one sector in lockstep for up to 64 of its
+                                 tracklets, the searched row staged in LDS */
 } tpc_tuning;
 void tpc_tuning_default(tpc_tuning* t);
 int tpc_ctx_set_tuning(tpc_ctx* ctx, const tpc_tuning* t);

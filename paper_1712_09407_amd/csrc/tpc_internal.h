@@ -27,7 +27,7 @@ struct KParams {
   float prior_sinphi, prior_tanl, prior_qpt;
   float bin_occupancy;     // target clusters per search-grid bin
   int32_t construct_blocks;  // constructor grid (0 = sized from the reservation)
-  int32_t construct_schedule;  // 0 = row-synchronous, 1 = one lane per tracklet
+  int32_t construct_schedule;  // 0 = one lane per tracklet, 1 = row-synchronous
 };
 
 struct DevEvent {

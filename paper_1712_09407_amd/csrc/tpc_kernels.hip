@@ -733,6 +733,19 @@ struct Lane {
   bool dropped = false;
   int32_t* H = nullptr;
   float2* HY = nullptr;
+  // the hit of the last step, stored at the start of the next one (or at the
+  // end), so that no wait for loads of a step also waits for these stores
+  int pend_r = -1, pend_h = -1;
+  bool pend_yz = false;
+  float pend_y = 0.f, pend_z = 0.f;
+
+  __device__ void flush() {
+    if (pend_r >= 0) {
+      H[pend_r] = pend_h;
+      if (pend_yz) HY[pend_r] = make_float2(pend_y, pend_z);
+      pend_r = -1;
+    }
+  }
 
   __device__ bool outward() const { return phase == P_CHAIN || phase == P_UP; }
   __device__ bool inward() const { return phase == P_REFIT || phase == P_DOWN; }
@@ -794,13 +807,17 @@ struct Lane {
     o0 = s.x; o1 = s.y; o2 = s.z; o3 = s.sp; o4 = s.tl; o5 = s.qpt;
     phase = P_REFIT;
     r = last_row - 1;
+    prefetch_refit();
+  }
+
+  // Cluster of row r and its coordinates, both loads in flight at once (the
+  // coordinates are used only if the row has a cluster).
+  __device__ void prefetch_refit() {
     if (r >= k0) {
       hc = H[r];
-      if (hc >= 0) {
-        const float2 v = HY[r];
-        cy = v.x;
-        cz = v.y;
-      }
+      const float2 v = HY[r];
+      cy = v.x;
+      cz = v.y;
     }
   }
 
@@ -813,6 +830,23 @@ struct Lane {
     const int nr = kp.n_rows;
     bool finish = false;
     const bool ext = extending();
+    flush();
+    // 0. the known measurement of the NEXT step (chain, refit) is loaded now,
+    //    so that it has a whole step to arrive
+    const bool pf_chain = phase == P_CHAIN && cnn >= 0 && r + 1 < nr;
+    const bool pf_refit = phase == P_REFIT && r - 1 >= k0;
+    float ny = 0.f, nz = 0.f;
+    int nc = -1;
+    if (pf_chain) {
+      ny = ev.y[cnn];
+      nz = ev.z[cnn];
+      nc = sc.up2[cnn];
+    } else if (pf_refit) {
+      nc = H[r - 1];
+      const float2 v = HY[r - 1];
+      ny = v.x;
+      nz = v.y;
+    }
     // 1. one helix step for every lane, whatever its phase
     const bool ok = propagate(s, s_x[r], kp);
     if (ok) ++wk.steps;
@@ -848,16 +882,21 @@ struct Lane {
       if (st == 0) {
         last_row = r;
         l_sp = s.sp; l_tl = s.tl; l_q = s.qpt; l_y = my; l_z = mz;
-        HY[r] = make_float2(my, mz);
       }
-      if (st != 2) H[r] = hit;
+      if (st != 2) {  // H[r] = hit, HY[r] = (my, mz) if a cluster was taken
+        pend_r = r;
+        pend_h = hit;
+        pend_yz = st == 0;
+        pend_y = my;
+        pend_z = mz;
+      }
       if (phase == P_CHAIN) {
         cn = cnn;
         ++r;
-        if (cn >= 0 && r < nr) {
-          cy = ev.y[cn];
-          cz = ev.z[cn];
-          cnn = sc.up2[cn];
+        if (pf_chain) {  // cn >= 0 && r < nr
+          cy = ny;
+          cz = nz;
+          cnn = nc;
         } else {
           phase = P_UP;
           misses = 0;
@@ -876,19 +915,20 @@ struct Lane {
         o0 = s.x; o1 = s.y; o2 = s.z; o3 = s.sp; o4 = s.tl; o5 = s.qpt;
       }
       if (phase == P_DOWN) {
-        if (st != 2) H[r] = hit;
+        if (st != 2) {  // H[r] = hit
+          pend_r = r;
+          pend_h = hit;
+          pend_yz = false;
+        }
         misses = st == 0 ? 0 : misses + 1;
         --r;
         if (st == 2 || misses > kp.max_miss || r < 0) finish = true;
       } else {
         --r;
-        if (r >= k0) {
-          hc = H[r];
-          if (hc >= 0) {
-            const float2 v = HY[r];
-            cy = v.x;
-            cz = v.y;
-          }
+        if (pf_refit) {  // r >= k0
+          hc = nc;
+          cy = ny;
+          cz = nz;
         }
       }
     }
@@ -903,6 +943,7 @@ struct Lane {
 
   // Tracklet outputs; the lane is done.
   __device__ void emit(const Scratch& sc) {
+    flush();
     if (dropped) {
       sc.row_lo[t] = 0;
       sc.row_hi[t] = -1;
@@ -1032,18 +1073,24 @@ __device__ __forceinline__ int search_row_lds(const RowStage& L, const RowGrid& 
   return bid;
 }
 
-__device__ __forceinline__ RowGrid uniform_grid(const Scratch& sc, int rs) {
-  return sc.grid[__builtin_amdgcn_readfirstlane(rs)];
-}
+// The row-synchronous workgroup is ONE wave: LDS operations of a wave are
+// performed in order, so LDS written by its lanes is visible to its later
+// reads without a workgroup barrier (whose memory fence would also wait for
+// every global load and store in flight).  wave_sync only keeps the compiler
+// from moving LDS accesses across it.
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+// s_waitcnt vmcnt(0) expcnt(7) lgkmcnt(15): wait for vector memory only
+constexpr int kWaitVm0 = 0x0F70;
 
 __global__ __launch_bounds__(64) void k_construct_rows(DevEvent ev, KParams kp, Scratch sc) {
   __shared__ float s_x[TPC_MAX_ROWS];
+  __shared__ RowGrid s_hdr[TPC_MAX_ROWS];  // grid headers of the current sector's rows
   __shared__ RowStage s_row[2];
   if (event_bad(sc.counters)) return;
   const int lane = threadIdx.x;
   const int nr = kp.n_rows;
   for (int i = lane; i < nr; i += 64) s_x[i] = kp.row_x[i];
-  __syncthreads();
+  wave_sync();
   const int n_tl = min(sc.counters[C_SEEDS], sc.cap_tl);
   Work wk;
 
@@ -1079,6 +1126,8 @@ __global__ __launch_bounds__(64) void k_construct_rows(DevEvent ev, KParams kp, 
     if (sec < 0) break;  // no more items for this workgroup
     q = __builtin_amdgcn_readfirstlane(q);
     const int rsb = sec * nr;
+    wave_sync();  // the previous item's readers of s_hdr are done (in order)
+    for (int i = lane; i < nr; i += 64) s_hdr[i] = sc.grid[rsb + i];
     const int tA = min(sc.row_cnt[rsb], n_tl), tB = min(sc.row_cnt[rsb + nr], n_tl);
     const int t = tA + q * 64 + lane;
     Lane ln;
@@ -1086,6 +1135,7 @@ __global__ __launch_bounds__(64) void k_construct_rows(DevEvent ev, KParams kp, 
       ln.begin(t, ev, kp, sc, s_x);
       if (ln.dropped) ln.emit(sc);
     }
+    wave_sync();
     StageRegs R;
     // two passes over the rows: outward (dir +1), then inward (dir -1)
     for (int dir = 1; dir >= -1; dir -= 2) {
@@ -1099,20 +1149,36 @@ __global__ __launch_bounds__(64) void k_construct_rows(DevEvent ev, KParams kp, 
       }
       ir = __builtin_amdgcn_readfirstlane(ir);
       if (ir < 0 || ir >= nr) continue;
-      RowGrid g = uniform_grid(sc, rsb + ir);
+      // pipeline: row ir in LDS buffer cur, row ir + dir in registers
+      // (loaded one iteration ago), row ir + 2 dir loaded during this one
       int cur = 0;
-      stage_load(sc, g, g.bin_base - (rsb + ir), R);
-      stage_store(g, R, s_row[cur]);
-      __syncthreads();
-      while (true) {
-        const int inext = ir + dir;
-        const bool more = inext >= 0 && inext < nr;
-        RowGrid gn = g;
-        if (more) {
-          gn = uniform_grid(sc, rsb + inext);
-          stage_load(sc, gn, gn.bin_base - (rsb + inext), R);
+      {
+        const RowGrid g0 = s_hdr[ir];
+        stage_load(sc, g0, g0.bin_base - (rsb + ir), R);
+        stage_store(g0, R, s_row[cur]);
+        const int i1 = ir + dir;
+        if (i1 >= 0 && i1 < nr) {
+          const RowGrid g1 = s_hdr[i1];
+          stage_load(sc, g1, g1.bin_base - (rsb + i1), R);
         }
+      }
+      wave_sync();
+      while (true) {
+        const int i1 = ir + dir, i2 = ir + 2 * dir;
+        const bool more = i1 >= 0 && i1 < nr;
+        // everything issued in the previous iteration (a whole step ago) has
+        // arrived: waiting here, once, keeps waits out of the step
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        if (more) {  // row ir + dir: registers -> the other buffer
+          stage_store(s_hdr[i1], R, s_row[cur ^ 1]);
+          if (i2 >= 0 && i2 < nr) {
+            const RowGrid g2 = s_hdr[i2];
+            stage_load(sc, g2, g2.bin_base - (rsb + i2), R);
+          }
+        }
+        wave_sync();
         if (active() && ln.r == ir) {
+          const RowGrid g = s_hdr[ir];
           const RowStage& L = s_row[cur];
           auto search = [&](float& my, float& mz) {
             if (stageable(g)) return search_row_lds(L, g, ln.s, kp, my, mz, wk);
@@ -1122,13 +1188,11 @@ __global__ __launch_bounds__(64) void k_construct_rows(DevEvent ev, KParams kp, 
         }
         const bool go = __ballot(ln.phase != P_DONE && active()) != 0ull && more;
         if (!go) break;
+        wave_sync();
         cur ^= 1;
-        stage_store(gn, R, s_row[cur]);
-        __syncthreads();
-        g = gn;
-        ir = inext;
+        ir = i1;
       }
-      __syncthreads();  // the buffers are reused by the next pass
+      wave_sync();  // the buffers are reused by the next pass
     }
   }
   flush_work(wk, sc);
@@ -1206,11 +1270,10 @@ __device__ __forceinline__ unsigned int order_bits(float w) {
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-constexpr int kOwnBlock = 1024;
-constexpr int kOwnChunk = 16384;  // clusters per chunk: 128 KB of 64-bit keys
+constexpr int kOwnBlock = 512;
+constexpr int kOwnChunk = 4096;   // clusters per chunk (about 18 rows of a central sector)
 constexpr int kOwnTable = 1024;   // tracklets per pass over the hit table
-constexpr int kOwnSplit = 4;      // workgroups per sector; chunks are dealt out
-constexpr int kQuads = kHitStride / 4;
+constexpr int kOwnSplit = 16;     // workgroups per sector; chunks are dealt out
 
 // Owner key of tracklet t, 0 if it does not compete: the weight
 // w = n (alpha - (chi^2/ndf)/beta) in order-preserving bits above the
@@ -1259,13 +1322,16 @@ __global__ __launch_bounds__(kOwnBlock) void k_own(DevEvent ev, KParams kp, Scra
     }
     __syncthreads();
     const int rlo = s_rows[0], rhi = s_rows[1];
+    // only the 4-row groups of the chunk's rows are read
+    const int q0 = rlo >> 2, nq = (rhi >> 2) - q0 + 1;
     for (int pass = 0; pass < 2; ++pass) {  // 0: owner keys, 1: owned counts
       for (int tb = t0; tb < t1; tb += kOwnTable) {
         const int nb = min(kOwnTable, t1 - tb);
         for (int k = tid; k < nb; k += kOwnBlock) {
           const int t = tb + k;
           const unsigned long long key = tracklet_key(kp, sc, t);
-          const int lo = max(sc.row_lo[t], rlo), hi = min(sc.row_hi[t], rhi);
+          const int lo = max(max(sc.row_lo[t], rlo), 0);
+          const int hi = min(min(sc.row_hi[t], rhi), kHitStride - 1);
           s_key[k] = key;
           s_lh[k] = (key != 0ull && lo <= hi) ? (lo | (hi << 16)) : -1;
           s_cnt[k] = 0;
@@ -1273,18 +1339,22 @@ __global__ __launch_bounds__(kOwnBlock) void k_own(DevEvent ev, KParams kp, Scra
         }
         __syncthreads();
         // (tracklet, 4 rows) elements of the batch; four loads in flight per lane
-        const int ne = nb * kQuads;
+        const int ne = nb * nq;
         for (int e0 = 0; e0 < ne; e0 += 4 * kOwnBlock) {
           int4 h[4];
-          int lh[4];
+          int lh[4], kk[4], rr[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int e = e0 + u * kOwnBlock + tid;
             lh[u] = -1;
+            kk[u] = 0;
+            rr[u] = 0;
             h[u] = make_int4(-1, -1, -1, -1);
             if (e < ne) {
-              const int k = e / kQuads, r0 = (e - k * kQuads) * 4;
+              const int k = e / nq, r0 = (q0 + (e - k * nq)) * 4;
               const int v = s_lh[k];
+              kk[u] = k;
+              rr[u] = r0;
               if (v >= 0 && r0 <= (v >> 16) && r0 + 3 >= (v & 0xFFFF)) {
                 lh[u] = v;
                 h[u] = *reinterpret_cast<const int4*>(sc.hits + (size_t)(tb + k) * kHitStride + r0);
@@ -1294,8 +1364,7 @@ __global__ __launch_bounds__(kOwnBlock) void k_own(DevEvent ev, KParams kp, Scra
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             if (lh[u] < 0) continue;
-            const int e = e0 + u * kOwnBlock + tid;
-            const int k = e / kQuads, r0 = (e - k * kQuads) * 4;
+            const int k = kk[u], r0 = rr[u];
             const int lo = lh[u] & 0xFFFF, hi = lh[u] >> 16;
             const unsigned long long key = s_key[k];
             const int hv[4] = {h[u].x, h[u].y, h[u].z, h[u].w};
@@ -1685,7 +1754,7 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
   post(K_SEED_WRITE);
   if (upto <= STAGE_SEEDS) return hipGetLastError();
   pre(K_CONSTRUCT);
-  if (kp.construct_schedule == 0) {
+  if (kp.construct_schedule == 1) {
     const int nb = xcd_grid(kp.construct_blocks > 0 ? kp.construct_blocks
                                                     : rows_blocks(sc.cap_tl, ev.n_sectors));
     hipLaunchKernelGGL(k_construct_rows, dim3(nb), dim3(64), 0, st, ev, kp, sc);

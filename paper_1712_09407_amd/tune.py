@@ -10,10 +10,10 @@ import math
 import os
 import time
 
-CANDIDATES = ([dict(construct_schedule=0, construct_blocks=0, bin_occupancy=o)
-               for o in (1.0, 2.0, 4.0)] +
-              [dict(construct_schedule=1, construct_blocks=b, bin_occupancy=o)
-               for b in (0, 4096) for o in (1.0, 2.0)])
+CANDIDATES = ([dict(construct_schedule=0, construct_blocks=b, bin_occupancy=o)
+               for b in (0, 4096) for o in (1.0, 2.0, 4.0)] +
+              [dict(construct_schedule=1, construct_blocks=0, bin_occupancy=o)
+               for o in (1.0, 2.0)])
 
 
 def bucket(evs) -> int:

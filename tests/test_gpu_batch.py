@@ -125,7 +125,7 @@ def test_graph_replays_match_eager(tracker, geo, events):
                                               (2048, 4.0, 0), (2048, 4.0, 1)])
 def test_tuning_never_changes_results(tracker, geo, events, blocks, occ, sched):
     devs = [dev(e) for e in events[:4]]
-    tracker.set_tuning(use_graph=0, construct_schedule=1)
+    tracker.set_tuning(use_graph=0, construct_schedule=0)
     ref = [tpc.to_numpy(r) for r in tracker.track_batch(devs, geo, 0.5)]
     tracker.set_tuning(use_graph=1, construct_blocks=blocks, bin_occupancy=occ,
                        construct_schedule=sched)

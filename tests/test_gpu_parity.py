@@ -230,7 +230,7 @@ def test_constructor_schedules_agree_bitwise(tracker, geo, name, seed):
     say("schedules", name, seed, e.n_clusters)
     dev = dev_event(e)
     out = []
-    for sched in (1, 0):
+    for sched in (0, 1):
         tracker.set_tuning(construct_schedule=sched)
         tl = tracker.tracklets(dev, geo, e.bz)
         res = tpc.to_numpy(tracker.track_event(dev, geo, e.bz))
