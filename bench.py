@@ -254,10 +254,13 @@ def main():
         if rc != 0:
             raise tpc.TpcError(rc, tpc.last_error())
 
-    # warm-up with every kernel timed: find the dominant kernel
-    tr.set_timing(None)
+    # warm-up, then one more step with every kernel timed: the dominant kernel
     for i in range(max(1, args.warmup)):
         step()
+    torch.cuda.synchronize()
+    tr.set_timing(None)
+    tr.reset_stats()
+    step()
     st = tr.stats()
     per = {k: st["kernel_ms"][k] / max(1, st["kernel_launches"][k]) for k in st["kernel_ms"]}
     dominant = max(per, key=per.get)
