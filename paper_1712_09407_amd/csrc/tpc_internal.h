@@ -28,6 +28,7 @@ struct KParams {
   float bin_occupancy;     // target clusters per search-grid bin
   int32_t construct_blocks;  // constructor grid (0 = sized from the reservation)
   int32_t construct_schedule;  // 0 = one lane per tracklet, 1 = row-synchronous
+  int32_t nf_dense;            // neighbours finder for dense rows (larger LDS stage)
 };
 
 struct DevEvent {

@@ -41,7 +41,13 @@ namespace tpc {
 
 constexpr int kGridBlock = 256;
 constexpr int kMaxBins = 4096;   // bins per row (LDS counting sort)
-constexpr int kNfLds = 1024;     // clusters per neighbour row staged in LDS
+// k_nf stages neighbour rows of up to CAP clusters in LDS and keeps up to
+// LIST window candidates per row and lane: (512, 16) for rows of central
+// density (smaller LDS footprint, more workgroups per CU), (1024, 32) for
+// dense events.  Larger rows or lists use the exact global-memory search;
+// every configuration gives the same links.
+constexpr int kNfCapSmall = 512, kNfListSmall = 16;
+constexpr int kNfCapLarge = 1024, kNfListLarge = 32;
 constexpr int kScanBlock = 1024;
 constexpr int kTlBlock = 64;     // one wave per block for per-tracklet kernels
 
@@ -254,7 +260,6 @@ struct RowViewG {
   __device__ int id_at(int j) const { return rec[j].id; }
 };
 
-constexpr int kNfList = 16;  // window candidates per neighbour row kept per lane
 
 // Best (chi2, d, u) pair for a cluster at (yc, zc) of row k (section 1):
 // every pair of window candidates, no lists (used for dense rows).
@@ -296,8 +301,9 @@ __device__ __forceinline__ void nf_search(const V& D, const V& U, float yc, floa
 }
 
 // Window candidates of one neighbour row: row-local positions into list
-// (column `lane` of a [kNfList][blockDim] LDS array).  Returns the count,
-// which may exceed kNfList (then the list is incomplete).
+// (column `lane` of a [LIST][blockDim] LDS array).  Returns the count,
+// which may exceed LIST (then the list is incomplete).
+template <int LIST>
 __device__ __forceinline__ int nf_collect(const RowView& V, float yc, float zc, float wy, float wz,
                                           uint16_t (*list)[kGridBlock], int lane) {
   const float m = 1e-3f;
@@ -309,7 +315,7 @@ __device__ __forceinline__ int nf_collect(const RowView& V, float yc, float zc, 
     for (int j = j0; j < j1; ++j) {
       const float2 p = V.yz[j];
       if (in_window(p, yc, zc, wy, wz)) {
-        if (cnt < kNfList) list[cnt][lane] = (uint16_t)j;
+        if (cnt < LIST) list[cnt][lane] = (uint16_t)j;
         ++cnt;
       }
     }
@@ -317,12 +323,13 @@ __device__ __forceinline__ int nf_collect(const RowView& V, float yc, float zc, 
   return cnt;
 }
 
+template <int CAP, int LIST>
 __global__ __launch_bounds__(kGridBlock) void k_nf(DevEvent ev, KParams kp, Scratch sc) {
-  __shared__ float2 s_yz[2][kNfLds];
-  __shared__ int32_t s_id[2][kNfLds];
-  __shared__ int32_t s_bins[2][kNfLds + 1];
-  __shared__ uint16_t s_dl[kNfList][kGridBlock];
-  __shared__ uint16_t s_ul[kNfList][kGridBlock];
+  __shared__ float2 s_yz[2][CAP];
+  __shared__ int32_t s_id[2][CAP];
+  __shared__ int32_t s_bins[2][CAP + 1];
+  __shared__ uint16_t s_dl[LIST][kGridBlock];
+  __shared__ uint16_t s_ul[LIST][kGridBlock];
   if (event_bad(sc.counters)) return;
   const int rs = blockIdx.x;
   const int r = rs % kp.n_rows;
@@ -337,7 +344,7 @@ __global__ __launch_bounds__(kGridBlock) void k_nf(DevEvent ev, KParams kp, Scra
   }
   const RowGrid gd = sc.grid[rs - 1], gu = sc.grid[rs + 1];
   const int bd_ = ev.ro[rs - 1], bu_ = ev.ro[rs + 1];
-  const bool stage = gd.n <= kNfLds && gu.n <= kNfLds;
+  const bool stage = gd.n <= CAP && gu.n <= CAP;
   const float xd = kp.row_x[r - 1], xc = kp.row_x[r], xu = kp.row_x[r + 1];
   const float t = (xc - xd) / (xu - xd);
   const float inorm = 1.f / (1.f + t * t + (1.f - t) * (1.f - t));
@@ -374,9 +381,9 @@ __global__ __launch_bounds__(kGridBlock) void k_nf(DevEvent ev, KParams kp, Scra
         const RowView D{s_yz[0], s_id[0], s_bins[0], gd}, U{s_yz[1], s_id[1], s_bins[1], gu};
         // candidates of each neighbour row once, then the pairs: no nested
         // bin scans, so lanes of a wave stay in step
-        const int nd = nf_collect(D, yc, zc, wy, wz, s_dl, tid);
-        const int nu = nd ? nf_collect(U, yc, zc, wy, wz, s_ul, tid) : 0;
-        if (nd <= kNfList && nu <= kNfList) {
+        const int nd = nf_collect<LIST>(D, yc, zc, wy, wz, s_dl, tid);
+        const int nu = nd ? nf_collect<LIST>(U, yc, zc, wy, wz, s_ul, tid) : 0;
+        if (nd <= LIST && nu <= LIST) {
           for (int p = 0; p < nd; ++p) {
             const int j = s_dl[p][tid];
             const float2 pd = s_yz[0][j];
@@ -1740,7 +1747,10 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
   hipLaunchKernelGGL(k_grid, dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc, out.cluster_track);
   post(K_GRID);
   pre(K_NF);
-  hipLaunchKernelGGL(k_nf, dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc);
+  if (kp.nf_dense)
+    hipLaunchKernelGGL((k_nf<kNfCapLarge, kNfListLarge>), dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc);
+  else
+    hipLaunchKernelGGL((k_nf<kNfCapSmall, kNfListSmall>), dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc);
   post(K_NF);
   pre(K_EVO);
   hipLaunchKernelGGL(k_evo, dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc);

@@ -110,6 +110,12 @@ int validate(const tpc_event* ev, const tpc_geometry* geo, const tpc_params* p) 
   return TPC_OK;
 }
 
+// Mean clusters per row slot above which the neighbours finder stages
+// larger rows and keeps longer candidate lists (speed only).
+static int32_t dense_rows(int64_t n_clusters, int64_t n_rowslots) {
+  return n_clusters > (int64_t)320 * (n_rowslots > 0 ? n_rowslots : 1) ? 1 : 0;
+}
+
 KParams make_kparams(const tpc_geometry* geo, float bz, const tpc_params* p) {
   KParams k;
   std::memset(&k, 0, sizeof(k));
@@ -141,6 +147,7 @@ KParams make_kparams(const tpc_geometry* geo, float bz, const tpc_params* p) {
   k.bin_occupancy = 1.0f;
   k.construct_blocks = 0;
   k.construct_schedule = 0;
+  k.nf_dense = 0;
   return k;
 }
 
@@ -211,6 +218,7 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
   kp.bin_occupancy = ctx->tuning.bin_occupancy;
   kp.construct_blocks = ctx->tuning.construct_blocks;
   kp.construct_schedule = ctx->tuning.construct_schedule;
+  kp.nf_dense = dense_rows(N, R);
   const DevEvent dev = make_devevent(ev);
   int64_t T = default_tracklets(ctx, N, p);
   for (int attempt = 0; attempt < 2; ++attempt) {
@@ -419,6 +427,7 @@ int run_batch(tpc_ctx* ctx, const tpc_event* evs, int E, const tpc_geometry* geo
   kp.bin_occupancy = ctx->tuning.bin_occupancy;
   kp.construct_blocks = ctx->tuning.construct_blocks;
   kp.construct_schedule = ctx->tuning.construct_schedule;
+  kp.nf_dense = dense_rows(N, R);
   DevEvent dev = make_devevent(&bev);
   if (use_graph) {
     dev.n_clusters = (int32_t)ncap;
