@@ -76,7 +76,7 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(ev_host, geo_t, bz, gpu_res, n_clusters, seconds):
+def cpu_baseline(ev_host, geo_t, bz, gpu_res, n_clusters, seconds, params=None):
     """The FP64 oracle on this host's cores, on repeats of the same event."""
     import oracle
     from oracle import concordance
@@ -88,14 +88,15 @@ def cpu_baseline(ev_host, geo_t, bz, gpu_res, n_clusters, seconds):
     runs, t0 = 0, time.perf_counter()
     ref = None
     while True:
-        ref = oracle.track_event(ev_host, geo_t, bz, oracle.default_params(), n_threads=cores)
+        ref = oracle.track_event(ev_host, geo_t, bz, params or oracle.default_params(),
+                                 n_threads=cores)
         runs += 1
         el = time.perf_counter() - t0
         if el >= seconds or runs >= 200:
             break
     rep = concordance.compare(ref, gpu_res, n_clusters)
     t1 = time.perf_counter()
-    oracle.track_event(ev_host, geo_t, bz, oracle.default_params(), n_threads=1)
+    oracle.track_event(ev_host, geo_t, bz, params or oracle.default_params(), n_threads=1)
     single = 1.0 / (time.perf_counter() - t1)
     base = dict(value=runs / el, unit="events/s", cores=cores, kind="oracle",
                 sample=f"{runs} run(s) of the benchmark event ({n_clusters} clusters), "
@@ -106,6 +107,136 @@ def cpu_baseline(ev_host, geo_t, bz, gpu_res, n_clusters, seconds):
                                 "par_compared", "par_fail", "par_max_rel")}
     conc["reference"] = "FP64 oracle"
     return base, conc
+
+
+def _gen_preset(args):
+    from paper_1712_09407_amd import synth
+    name, seed = args
+    e = synth.make_preset(name, seed)
+    return e.y, e.z, e.row_offsets, e.sector_id
+
+
+def _pool_workers():
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return max(1, min(16, n))
+
+
+def oracle_params(tpc, gpu_params):
+    """The oracle's constants: the GPU's FP32 values, widened."""
+    import oracle
+    vals = {}
+    for k, t in oracle.Params._fields_:
+        v = getattr(gpu_params, k)
+        vals[k] = float(np.float32(v)) if isinstance(v, float) else v
+    return oracle.default_params(**vals)
+
+
+def single_sector_section(tr, tpc, synth, geo, prm, steps, log_):
+    """One sector, 200 tracks: the plain path on the smallest event (latency
+    bound), the oracle on the same event, and their concordance."""
+    import torch
+    import oracle
+    from oracle import concordance
+    e = synth.make_preset("c1_sector", 1)
+    dev = tpc.DeviceEvent.from_host(e.y, e.z, e.row_offsets, e.sector_id)
+    for _ in range(5):
+        res = tr.track_event(dev, geo, e.bz, prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = tr.track_event(dev, geo, e.bz, prm)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    res = tpc.to_numpy(res)
+    ev_host = dict(y=e.y, z=e.z, row_offsets=e.row_offsets, sector_id=e.sector_id)
+    t1 = time.perf_counter()
+    ref = oracle.track_event(ev_host, (synth.ROW_X, synth.TAN_HALF, synth.Z_MAX), e.bz,
+                             oracle_params(tpc, prm), n_threads=1)
+    t_orc = time.perf_counter() - t1
+    rep = concordance.compare(ref, res, e.n_clusters)
+    return dict(workload=f"one sector, 200 helix tracks, 2% noise, seed 1, {e.n_clusters} clusters",
+                events_per_s=round(steps / el, 1), clusters_per_s=round(e.n_clusters * steps / el, 1),
+                ms_per_event=round(el / steps * 1e3, 4), oracle_s_per_event=round(t_orc, 4),
+                oracle_cores=1, n_tracks=int(res["n_tracks"]),
+                cluster_concordance=rep["cluster_concordance"],
+                track_concordance=rep["track_concordance"], par_fail=rep["par_fail"])
+
+
+def central_concordance_section(tr, tpc, synth, geo, prm, seeds, log_):
+    """Concordance with the FP64 oracle over several central events (so that
+    99.99% is resolvable on ~100k tracks)."""
+    import concurrent.futures as cf
+    import oracle
+    from oracle import concordance
+    with cf.ProcessPoolExecutor(_pool_workers()) as ex:
+        host = list(ex.map(_gen_preset, [("c2_central", s) for s in seeds]))
+    op = oracle_params(tpc, prm)
+    cores = _pool_workers()
+    n_tr = n_cl = 0
+    miss_cl = miss_tr = par_fail = par_cmp = 0
+    worst = 1.0
+    t_orc = 0.0
+    for (y, z, ro, si) in host:
+        dev = tpc.DeviceEvent.from_host(y, z, ro, si)
+        res = tpc.to_numpy(tr.track_event(dev, geo, 0.5, prm))
+        t1 = time.perf_counter()
+        ref = oracle.track_event(dict(y=y, z=z, row_offsets=ro, sector_id=si),
+                                 (synth.ROW_X, synth.TAN_HALF, synth.Z_MAX), 0.5, op,
+                                 n_threads=cores)
+        t_orc += time.perf_counter() - t1
+        rep = concordance.compare(ref, res, len(y))
+        worst = min(worst, rep["cluster_concordance"], rep["track_concordance"])
+        n_tr += rep["n_tracks_a"]
+        n_cl += len(y)
+        miss_tr += round((1 - rep["track_concordance"]) * rep["n_tracks_a"])
+        par_fail += rep["par_fail"]
+        par_cmp += rep["par_compared"]
+    return dict(workload=f"{len(seeds)} central events (seeds {seeds[0]}-{seeds[-1]})",
+                tracks=n_tr, clusters=n_cl, worst_concordance=worst,
+                unmatched_tracks=miss_tr, par_compared=par_cmp, par_fail=par_fail,
+                oracle_s_per_event=round(t_orc / len(seeds), 4), oracle_cores=cores)
+
+
+def stress_section(tr, tpc, synth, geo, n_events, steps, log_):
+    """Stress events (20000 primaries + 6000 loopers, 10% noise, sigma 0.15)
+    in batches of n_events: throughput, and concordance and parameter error
+    against the oracle on the first event."""
+    import concurrent.futures as cf
+    import torch
+    import oracle
+    from oracle import concordance
+    seeds = [5000 + i for i in range(n_events)]
+    log_(f"generating {n_events} stress events")
+    with cf.ProcessPoolExecutor(_pool_workers()) as ex:
+        host = list(ex.map(_gen_preset, [("c5_stress", s) for s in seeds]))
+    prm = tpc.default_params(sigma_y=0.15, sigma_z=0.15)
+    devs = [tpc.DeviceEvent.from_host(*h) for h in host]
+    n_cl = sum(d.n_clusters for d in devs)
+    res = tr.track_batch(devs, geo, 0.5, prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = tr.track_batch(devs, geo, 0.5, prm)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    r0 = tpc.to_numpy(res[0])
+    y, z, ro, si = host[0]
+    t1 = time.perf_counter()
+    ref = oracle.track_event(dict(y=y, z=z, row_offsets=ro, sector_id=si),
+                             (synth.ROW_X, synth.TAN_HALF, synth.Z_MAX), 0.5,
+                             oracle_params(tpc, prm), n_threads=_pool_workers())
+    t_orc = time.perf_counter() - t1
+    rep = concordance.compare(ref, r0, len(y))
+    return dict(workload=f"{n_events} stress events per batch (20000 primaries + 6000 loopers, "
+                         f"10% noise, sigma 0.15 cm; seeds {seeds[0]}+), {n_cl} clusters",
+                events_per_s=round(n_events * steps / el, 2),
+                clusters_per_s=round(n_cl * steps / el, 1),
+                ms_per_batch=round(el / steps * 1e3, 3),
+                oracle_s_per_event=round(t_orc, 3), oracle_cores=_pool_workers(),
+                cluster_concordance=rep["cluster_concordance"],
+                track_concordance=rep["track_concordance"],
+                par_compared=rep["par_compared"], par_fail=rep["par_fail"],
+                par_max_rel=rep["par_max_rel"])
 
 
 def _gen_batch_event(seed):
@@ -206,6 +337,8 @@ def main():
     ap.add_argument("--batch-events", type=int, default=64,
                     help="events in the batched-path measurement (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-extra", dest="extra", action="store_false",
+                    help="skip the single-sector, ten-event concordance and stress sections")
     ap.add_argument("--serve-events", type=int, default=1000,
                     help="events per arrival rate in the serving measurement (0 = skip)")
     args = ap.parse_args()
@@ -351,11 +484,23 @@ def main():
         log("serving ...")
         line["serving"] = serving_section(tpc, synth, geo, prm, batched_section.host_events,
                                           (200.0, 500.0, 1000.0), args.serve_events, log)
+    if args.extra:
+        sections = (("single_sector", lambda: single_sector_section(tr, tpc, synth, geo, prm, 500, log)),
+                    ("central_concordance", lambda: central_concordance_section(
+                        tr, tpc, synth, geo, prm, list(range(2, 12)), log)),
+                    ("stress", lambda: stress_section(tr, tpc, synth, geo, 16, 3, log)))
+        for name, fn in sections:
+            log(f"{name} ...")
+            try:
+                line[name] = fn()
+            except Exception as exc:  # the headline line must still be printed
+                line[name] = dict(error=f"{type(exc).__name__}: {exc}")
+            log(f"{name}:", line[name])
     if not args.no_cpu_baseline:
         log("oracle baseline on the host cores ...")
         ev_host = dict(y=e.y, z=e.z, row_offsets=e.row_offsets, sector_id=e.sector_id)
         base, conc = cpu_baseline(ev_host, (synth.ROW_X, synth.TAN_HALF, synth.Z_MAX), e.bz,
-                                  res, N, args.cpu_seconds)
+                                  res, N, args.cpu_seconds, oracle_params(tpc, prm))
         line["cpu_baseline"] = base
         line["concordance"] = conc
     else:

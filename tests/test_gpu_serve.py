@@ -58,15 +58,43 @@ def test_mix_equals_alone(geo, pool, alone):
     srv.close()
 
 
+def _footprint(h):
+    # the server's admission footprint of an event (160 B per cluster, plus
+    # 16 B per row slot and 64 KiB)
+    return 160 * h.n_clusters + 16 * 36 * 159 + (1 << 16)
+
+
 def test_admission_by_footprint_defers_not_fails(geo, pool, alone):
-    # room for about two of the larger events at a time
-    budget = 2 * 160 * max(h.n_clusters for h in pool) + (1 << 20)
-    srv = tpc.Server(geo, 0.5, max_batch=4, n_workers=2, hbm_budget_bytes=budget)
-    res, fetched = serve.run(srv, pool, rate_hz=5000.0, n_events=24, keep=set(range(24)))
-    say(res)
-    assert res["busy_retries"] > 0
-    assert res["stats"]["resident_bytes"] == 0
-    _check_same(fetched, pool, alone)
+    """A budget that holds one copy of the largest event: a second copy
+    submitted right after the first is deferred (BUSY), not failed, and is
+    admitted once the first has finished; both give the tracks of the event
+    alone, and nothing stays resident."""
+    big = max(range(len(pool)), key=lambda i: pool[i].n_clusters)
+    fp = _footprint(pool[big])
+    srv = tpc.Server(geo, 0.5, max_batch=4, n_workers=2, hbm_budget_bytes=fp + fp // 2)
+    assert srv.submit(pool[big], 0) == tpc.TPC_OK
+    busy, done = 0, {}
+    rc = srv.submit(pool[big], 1)
+    while rc == tpc.TPC_ERR_BUSY:
+        busy += 1
+        for d in srv.poll(timeout_ms=2):
+            done[int(d["tag"])] = d
+        rc = srv.submit(pool[big], 1)
+    assert rc == tpc.TPC_OK
+    assert busy > 0                      # the second copy had to wait for the first
+    while len(done) < 2:
+        for d in srv.poll(timeout_ms=100):
+            done[int(d["tag"])] = d
+    fetched = {}
+    for k, d in done.items():
+        assert d["status"] == tpc.TPC_OK
+        fetched[k] = srv.fetch(d, pool[big].n_clusters)
+    say("busy retries", busy)
+    for r in fetched.values():
+        assert r["n_tracks"] == alone[big]["n_tracks"]
+        for key in KEYS:
+            assert np.array_equal(r[key], alone[big][key]), key
+    assert srv.stats()["resident_bytes"] == 0
     srv.close()
 
 
