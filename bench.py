@@ -239,6 +239,36 @@ def stress_section(tr, tpc, synth, geo, n_events, steps, log_):
                 par_max_rel=rep["par_max_rel"])
 
 
+def _gen_event(args):
+    from paper_1712_09407_amd import synth
+    name, seed = args
+    return synth.make_preset(name, seed)
+
+
+def alpha_scan_section(tr, tpc, synth, geo, seeds, log_):
+    """Track-finding quality against MC truth as a function of the weight's
+    alpha (section 3.1; alpha = infinity is the longest-track rule), on
+    central events."""
+    import concurrent.futures as cf
+    from paper_1712_09407_amd import quality
+    with cf.ProcessPoolExecutor(_pool_workers()) as ex:
+        evs = list(ex.map(_gen_event, [("c2_central", s) for s in seeds]))
+    devs = [tpc.DeviceEvent.from_host(e.y, e.z, e.row_offsets, e.sector_id) for e in evs]
+    rows = {}
+    for a in quality.ALPHAS:
+        prm = tpc.default_params(alpha=quality.alpha_value(a))
+        reps = [quality.evaluate(e, tpc.to_numpy(tr.track_event(d, geo, e.bz, prm)))
+                for e, d in zip(evs, devs)]
+        m = quality.merge(reps)
+        rows["inf" if a == float("inf") else f"{a:g}"] = dict(
+            efficiency=round(m["efficiency"], 5), clone_rate=round(m["clone_rate"], 5),
+            fake_rate=round(m["fake_rate"], 5), tracks=m["tracks"],
+            **{f"res_{k}": round(v, 6) for k, v in m["resolution"].items() if k != "tracks"})
+        log_(f"alpha {a}: {rows['inf' if a == float('inf') else f'{a:g}']}")
+    return dict(workload=f"{len(seeds)} central events (seeds {seeds[0]}-{seeds[-1]}), "
+                         "quality against MC truth per alpha", alphas=rows)
+
+
 def _gen_batch_event(seed):
     from paper_1712_09407_amd import synth
     e = synth.batch_event(seed)
@@ -488,7 +518,8 @@ def main():
         sections = (("single_sector", lambda: single_sector_section(tr, tpc, synth, geo, prm, 500, log)),
                     ("central_concordance", lambda: central_concordance_section(
                         tr, tpc, synth, geo, prm, list(range(2, 12)), log)),
-                    ("stress", lambda: stress_section(tr, tpc, synth, geo, 16, 3, log)))
+                    ("stress", lambda: stress_section(tr, tpc, synth, geo, 16, 3, log)),
+                    ("alpha_scan", lambda: alpha_scan_section(tr, tpc, synth, geo, [2, 3, 4], log)))
         for name, fn in sections:
             log(f"{name} ...")
             try:
