@@ -185,6 +185,10 @@ typedef struct {
                                  1 = row-synchronous: a workgroup walks the rows of
                                  one sector in lockstep for up to 64 of its
                                  tracklets, the searched row staged in LDS */
+  int32_t construct_lanes;    /* lane schedule: lanes of each 64-lane wave that take
+                                 tracklets (1 .. 64); fewer lanes per wave shorten
+                                 each wave's steps at the cost of more waves;
+                                 0 = automatic (about 2048 waves for the event) */
 } tpc_tuning;
 void tpc_tuning_default(tpc_tuning* t);
 int tpc_ctx_set_tuning(tpc_ctx* ctx, const tpc_tuning* t);

@@ -29,6 +29,7 @@ struct KParams {
   int32_t construct_blocks;  // constructor grid (0 = sized from the reservation)
   int32_t construct_schedule;  // 0 = one lane per tracklet, 1 = row-synchronous
   int32_t nf_dense;            // neighbours finder for dense rows (larger LDS stage)
+  int32_t construct_lanes;     // lane schedule: lanes of a wave that take tracklets
 };
 
 struct DevEvent {

@@ -1101,17 +1101,19 @@ __global__ __launch_bounds__(64) void k_construct_rows(DevEvent ev, KParams kp, 
   const int n_tl = min(sc.counters[C_SEEDS], sc.cap_tl);
   Work wk;
 
-  // Work items are (sector, chunk of 64 tracklets).  Workgroups b = g (mod 8)
-  // take the chunks of the sectors s = g (mod 8), in order, with a stride of
+  // Work items are (sector, chunk of 64 tracklets).  Workgroups b = g (mod G)
+  // take the chunks of the sectors s = g (mod G), G = min(8, sectors), in
+  // order, with a stride of
   // the number of such workgroups: one XCD (one L2) stages the rows of only
   // a few sectors.  Any mapping gives the same results.
-  const int grp = blockIdx.x & 7;
-  const int nwg = ((int)gridDim.x - grp + 7) >> 3;
-  for (int item = blockIdx.x >> 3;; item += nwg) {
+  const int G = min(8, ev.n_sectors);
+  const int grp = blockIdx.x % G;
+  const int nwg = ((int)gridDim.x - grp + G - 1) / G;
+  for (int item = blockIdx.x / G;; item += nwg) {
     // find the sector of this item: prefix of chunk counts over the group
     int sec = -1, q = 0, base = 0;
-    for (int s0 = grp; s0 < ev.n_sectors; s0 += 8 * 64) {
-      const int sct = s0 + 8 * lane;
+    for (int s0 = grp; s0 < ev.n_sectors; s0 += G * 64) {
+      const int sct = s0 + G * lane;
       int ch = 0;
       if (sct < ev.n_sectors) {
         const int a = min(sc.row_cnt[sct * nr], n_tl), b = min(sc.row_cnt[(sct + 1) * nr], n_tl);
@@ -1123,7 +1125,7 @@ __global__ __launch_bounds__(64) void k_construct_rows(DevEvent ev, KParams kp, 
         const bool here = base + inc - ch <= item && item < base + inc;
         const unsigned long long m = __ballot(here);
         const int L = __ffsll((long long)m) - 1;
-        sec = s0 + 8 * L;
+        sec = s0 + G * L;
         q = item - (base + __shfl(inc - ch, L, 64));
         break;
       }
@@ -1217,25 +1219,30 @@ __global__ __launch_bounds__(kTlBlock) void k_construct_lanes(DevEvent ev, KPara
   Work wk;
 
   // XCD-aware mapping: workgroups are spread round-robin over the 8 XCDs,
-  // each with its own L2.  Blocks b = g (mod 8) take the tracklets of the
-  // sectors s = g (mod 8), so one XCD reads the grids of only a few sectors.
-  // Any mapping gives the same results; this one keeps the grids in L2.
-  const int grp = blockIdx.x & 7;
-  const int blocks_g = ((int)gridDim.x - grp + 7) >> 3;
-  const int lanes_g = blocks_g * kTlBlock;
+  // each with its own L2.  Blocks b = g (mod G) take the tracklets of the
+  // sectors s = g (mod G), G = min(8, sectors), so one XCD reads the grids
+  // of only a few sectors.  Only the first A lanes of a wave take tracklets:
+  // the constructor's time is the critical path of its longest tracklets, and
+  // a wave with fewer lanes waits on fewer scattered loads per step (A is a
+  // tuning knob).  Any mapping gives the same results.
+  const int G = min(8, ev.n_sectors);
+  const int A = min(max(kp.construct_lanes, 1), kTlBlock);
+  const int grp = blockIdx.x % G;
+  const int blocks_g = ((int)gridDim.x - grp + G - 1) / G;
+  const int lanes_g = blocks_g * A;
   int total_g = 0;
-  for (int sct = grp; sct < ev.n_sectors; sct += 8)
+  for (int sct = grp; sct < ev.n_sectors; sct += G)
     total_g += sc.row_cnt[(sct + 1) * nr] - sc.row_cnt[sct * nr];
   // k-th tracklet of this group -> tracklet index (sectors are contiguous)
   auto group_tracklet = [&](int k) {
-    for (int sct = grp; sct < ev.n_sectors; sct += 8) {
+    for (int sct = grp; sct < ev.n_sectors; sct += G) {
       const int o = sc.row_cnt[sct * nr], c = sc.row_cnt[(sct + 1) * nr] - o;
       if (k < c) return min(o + k, n_tl);
       k -= c;
     }
     return n_tl;
   };
-  int kg = (blockIdx.x >> 3) * kTlBlock + threadIdx.x;  // first: static
+  int kg = (int)threadIdx.x < A ? (int)(blockIdx.x / G) * A + (int)threadIdx.x : total_g;
   int t = kg < total_g ? group_tracklet(kg) : n_tl;
   Lane ln;
   RowGrid gn;  // grid header of the next extension row, loaded one step early
@@ -1697,14 +1704,14 @@ void scratch_carve(void* base, int64_t N, int64_t R, int64_t T, Scratch* sc) {
 // Constructor: one lane per tracklet of the reservation, refills from the
 // queue when the reservation exceeds the launch.  Per-tracklet kernels: one
 // wave per tracklet.
-static inline int tl_blocks(int64_t T) {
-  int64_t b = (T + kTlBlock - 1) / kTlBlock;
+static inline int tl_blocks(int64_t T, int lanes) {
+  int64_t b = (T + lanes - 1) / lanes;
   if (b > 16384) b = 16384;
   return (int)(b < 1 ? 1 : b);
 }
-// Both constructors give the tracklets of the sectors s = g (mod 8) to the
-// workgroups b = g (mod 8): every one of the 8 groups needs a workgroup, so
-// the grid is a non-zero multiple of 8.
+// Both constructors give the tracklets of the sectors s = g (mod G) to the
+// workgroups b = g (mod G), G <= 8: every group needs a workgroup, so the
+// grid is a non-zero multiple of 8.
 static inline int xcd_grid(int64_t b) {
   b = (b + 7) / 8 * 8;
   if (b < 8) b = 8;
@@ -1769,7 +1776,9 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
                                                     : rows_blocks(sc.cap_tl, ev.n_sectors));
     hipLaunchKernelGGL(k_construct_rows, dim3(nb), dim3(64), 0, st, ev, kp, sc);
   } else {
-    const int nb = xcd_grid(kp.construct_blocks > 0 ? kp.construct_blocks : tl_blocks(sc.cap_tl));
+    const int nb = xcd_grid(kp.construct_blocks > 0
+                                ? kp.construct_blocks
+                                : tl_blocks(sc.cap_tl, min(max(kp.construct_lanes, 1), kTlBlock)));
     hipLaunchKernelGGL(k_construct_lanes, dim3(nb), dim3(kTlBlock), 0, st, ev, kp, sc);
   }
   post(K_CONSTRUCT);

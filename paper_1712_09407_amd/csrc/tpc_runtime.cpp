@@ -49,7 +49,7 @@ struct tpc_ctx {
   size_t batch_bytes = 0;
   void* h_batch = nullptr;  // pinned: descriptors out, per-event counts back
   size_t h_batch_bytes = 0;
-  tpc_tuning tuning{1, 0, 1.0f};
+  tpc_tuning tuning{};  // set by tpc_ctx_create (tpc_tuning_default)
   // captured batch launch sequence and what it was captured for
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -110,6 +110,19 @@ int validate(const tpc_event* ev, const tpc_geometry* geo, const tpc_params* p) 
   return TPC_OK;
 }
 
+// Lanes per wave of the lane-schedule constructor.  Its time is the critical
+// path of the longest tracklets; a wave with fewer lanes takes shorter steps
+// (fewer scattered loads and phases per step) as long as the waves do not
+// queue on the SIMDs.  Automatic (0): about 2048 waves for the expected
+// number of tracklets (one per 36 clusters), as a power of two in [8, 64].
+static int32_t lanes_per_wave(int32_t requested, int64_t n_clusters) {
+  if (requested > 0) return requested;
+  const double waves = (double)(n_clusters / 36 + 1) / 2048.0;
+  int32_t a = 8;
+  while (a < 64 && (double)a * 1.41421356 < waves) a *= 2;
+  return a;
+}
+
 // Mean clusters per row slot above which the neighbours finder stages
 // larger rows and keeps longer candidate lists (speed only).
 static int32_t dense_rows(int64_t n_clusters, int64_t n_rowslots) {
@@ -148,6 +161,7 @@ KParams make_kparams(const tpc_geometry* geo, float bz, const tpc_params* p) {
   k.construct_blocks = 0;
   k.construct_schedule = 0;
   k.nf_dense = 0;
+  k.construct_lanes = 64;
   return k;
 }
 
@@ -218,6 +232,7 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
   kp.bin_occupancy = ctx->tuning.bin_occupancy;
   kp.construct_blocks = ctx->tuning.construct_blocks;
   kp.construct_schedule = ctx->tuning.construct_schedule;
+  kp.construct_lanes = lanes_per_wave(ctx->tuning.construct_lanes, N);
   kp.nf_dense = dense_rows(N, R);
   const DevEvent dev = make_devevent(ev);
   int64_t T = default_tracklets(ctx, N, p);
@@ -427,6 +442,7 @@ int run_batch(tpc_ctx* ctx, const tpc_event* evs, int E, const tpc_geometry* geo
   kp.bin_occupancy = ctx->tuning.bin_occupancy;
   kp.construct_blocks = ctx->tuning.construct_blocks;
   kp.construct_schedule = ctx->tuning.construct_schedule;
+  kp.construct_lanes = lanes_per_wave(ctx->tuning.construct_lanes, N);
   kp.nf_dense = dense_rows(N, R);
   DevEvent dev = make_devevent(&bev);
   if (use_graph) {
@@ -586,6 +602,7 @@ int tpc_ctx_create(int device, size_t hbm_budget_bytes, tpc_ctx** out) {
   if (!c) return fail(TPC_ERR_OOM, "host allocation failed");
   c->device = device;
   c->budget = hbm_budget_bytes;
+  tpc_tuning_default(&c->tuning);
   e = hipHostMalloc((void**)&c->h_counters, sizeof(int32_t) * C_COUNT, hipHostMallocDefault);
   if (e != hipSuccess) {
     delete c;
@@ -605,6 +622,7 @@ void tpc_tuning_default(tpc_tuning* t) {
   t->construct_blocks = 0;
   t->bin_occupancy = 1.0f;
   t->construct_schedule = 0;
+  t->construct_lanes = 0;
 }
 
 int tpc_ctx_set_tuning(tpc_ctx* ctx, const tpc_tuning* t) {
@@ -615,6 +633,8 @@ int tpc_ctx_set_tuning(tpc_ctx* ctx, const tpc_tuning* t) {
     return fail(TPC_ERR_INVALID_ARG, "bin_occupancy outside [1, 64]");
   if (t->construct_schedule != 0 && t->construct_schedule != 1)
     return fail(TPC_ERR_INVALID_ARG, "construct_schedule must be 0 or 1");
+  if (t->construct_lanes < 0 || t->construct_lanes > 64)
+    return fail(TPC_ERR_INVALID_ARG, "construct_lanes outside [0, 64]");
   ctx->tuning = *t;
   return TPC_OK;
 }

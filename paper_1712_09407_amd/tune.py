@@ -1,7 +1,7 @@
-"""Autotuner of the batched path: picks the constructor schedule and grid and
-the search-grid bin occupancy that track a sample batch fastest, and caches
-the choice per GPU and multiplicity bucket.  Every candidate gives bitwise the same tracks, so
-tuning only ever changes speed.
+"""Autotuner of the batched path: picks the constructor schedule, its lanes
+per wave and the search-grid bin occupancy that track a sample batch
+fastest, and caches the choice per GPU and multiplicity bucket.  Every
+candidate gives bitwise the same tracks, so tuning only ever changes speed.
 """
 from __future__ import annotations
 
@@ -10,10 +10,9 @@ import math
 import os
 import time
 
-CANDIDATES = ([dict(construct_schedule=0, construct_blocks=b, bin_occupancy=o)
-               for b in (0, 4096) for o in (1.0, 2.0, 4.0)] +
-              [dict(construct_schedule=1, construct_blocks=0, bin_occupancy=o)
-               for o in (1.0, 2.0)])
+CANDIDATES = ([dict(construct_schedule=0, construct_blocks=0, construct_lanes=a, bin_occupancy=o)
+               for a in (0, 16, 64) for o in (1.0, 2.0)] +
+              [dict(construct_schedule=1, construct_blocks=0, bin_occupancy=1.0)])
 
 
 def bucket(evs) -> int:
