@@ -58,6 +58,12 @@ class Tracks(C.Structure):
                 ("track_cluster", C.POINTER(C.c_int32)), ("cluster_track", C.POINTER(C.c_int32))]
 
 
+class Prolongations(C.Structure):
+    _fields_ = [("cap", C.c_int32), ("cap_clusters", C.c_int32), ("n", C.c_int32),
+                ("n_clusters", C.c_int32), ("par", C.POINTER(C.c_double)),
+                ("meta", C.POINTER(C.c_int32)), ("cluster", C.POINTER(C.c_int32))]
+
+
 class Tracklets(C.Structure):
     _fields_ = [("hits", C.POINTER(C.c_int32)), ("row_lo", C.POINTER(C.c_int32)),
                 ("row_hi", C.POINTER(C.c_int32)), ("n", C.POINTER(C.c_int32)),
@@ -78,6 +84,10 @@ def lib():
         L.orc_params_default.argtypes = [P(Params)]
         L.orc_track_event.argtypes = [P(EventS), P(Geometry), C.c_double, P(Params), P(Tracks),
                                       C.c_int]
+        L.orc_track_event_global.argtypes = [P(EventS), P(Geometry), C.c_double, P(Params),
+                                             P(Tracks), P(Prolongations), C.c_int]
+        L.orc_rotate.argtypes = [C.c_double, P(C.c_double), P(C.c_double), C.c_double,
+                                 C.c_double, P(C.c_double), P(C.c_double), P(C.c_double)]
         L.orc_neighbours.argtypes = [P(EventS), P(Geometry), P(Params), P(C.c_int32),
                                      P(C.c_int32)]
         L.orc_nf_chi2.argtypes = [P(EventS), P(Geometry), P(Params), C.c_int32, C.c_int32,
@@ -236,6 +246,67 @@ def construct(ev, geo, bz, up2, seeds_arr, params=None):
     if rc:
         raise RuntimeError("orc_construct failed")
     return {k: v[:n_tl] for k, v in a.items()}
+
+
+def track_event_global(ev: dict, geo, bz: float, params: Params | None = None,
+                       n_threads: int = 1):
+    """track_event, then the global-tracking prolongation of the tracks.
+    Returns (tracks, prolongations): prolongations has n, par [n][8] (x, y,
+    z, sinphi, tanl, qpt at the last collected cluster, chi2, ndf), meta
+    [n][5] (track index, end, sector_id entered, n_clusters, first) and
+    cluster."""
+    cx = _ctx(ev, geo)
+    prm = params or default_params()
+    n = int(cx.y.shape[0])
+    cap_t, cap_c = max(1, n // 8), max(1, n)
+    cap_p, cap_pc = 2 * cap_t + 1, max(1, n)
+    for _ in range(3):
+        par = np.zeros((cap_t, 8), np.float64)
+        meta = np.zeros((cap_t, 4), np.int32)
+        tcl = np.zeros(cap_c, np.int32)
+        ctr = np.full(max(n, 1), -1, np.int32)
+        ppar = np.zeros((cap_p, 8), np.float64)
+        pmeta = np.zeros((cap_p, 5), np.int32)
+        pcl = np.zeros(cap_pc, np.int32)
+        out = Tracks(cap_t, cap_c, 0, 0, _p(par, C.c_double), _p(meta, C.c_int32),
+                     _p(tcl, C.c_int32), _p(ctr, C.c_int32))
+        pro = Prolongations(cap_p, cap_pc, 0, 0, _p(ppar, C.c_double), _p(pmeta, C.c_int32),
+                            _p(pcl, C.c_int32))
+        rc = lib().orc_track_event_global(C.byref(cx.ev), C.byref(cx.geo), float(bz),
+                                          C.byref(prm), C.byref(out), C.byref(pro),
+                                          int(n_threads))
+        if rc == 1:
+            cap_t, cap_c = max(cap_t, out.n_tracks), max(cap_c, out.n_track_clusters)
+            cap_p, cap_pc = max(cap_p, pro.n), max(cap_pc, pro.n_clusters)
+            continue
+        if rc != 0:
+            raise RuntimeError(f"orc_track_event_global failed: {rc}")
+        nt, nc, npr, npc = out.n_tracks, out.n_track_clusters, pro.n, pro.n_clusters
+        tracks = dict(n_tracks=nt, n_track_clusters=nc, track_par=par[:nt].copy(),
+                      track_meta=meta[:nt].copy(), track_cluster=tcl[:nc].copy(),
+                      cluster_track=ctr[:n].copy())
+        prol = dict(n=npr, n_clusters=npc, par=ppar[:npr].copy(), meta=pmeta[:npr].copy(),
+                    cluster=pcl[:npc].copy())
+        return tracks, prol
+    raise RuntimeError("capacity retry failed")
+
+
+def rotate(x: float, state, cov, d: float, bz: float):
+    """Rotation of a state (5) and covariance (5x5) at x into a frame turned by
+    d radians: returns (x', state', cov'), or None if the direction does not
+    point along the new x axis."""
+    st = np.ascontiguousarray(state, np.float64)
+    cv = np.ascontiguousarray(cov if cov is not None else np.zeros((5, 5)), np.float64)
+    xo = C.c_double(0.0)
+    so = np.zeros(5, np.float64)
+    co = np.zeros((5, 5), np.float64)
+    rc = lib().orc_rotate(float(x), _p(st, C.c_double), _p(cv, C.c_double), float(d), float(bz),
+                          C.byref(xo), _p(so, C.c_double), _p(co, C.c_double))
+    if rc == 1:
+        return None
+    if rc:
+        raise RuntimeError("orc_rotate failed")
+    return xo.value, so, co
 
 
 def select(ev, geo, bz, ids, tl: dict, params=None, weights=None):

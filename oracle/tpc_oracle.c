@@ -474,6 +474,8 @@ typedef struct {
   int32_t row_lo, row_hi, n, ndf;
   double chi2;
   double par[6];
+  kstate s_in;   /* inward fit at the innermost collected cluster */
+  kstate s_out;  /* outward filter at the outermost collected cluster */
 } tl_result;
 
 /* Extension step at row r: returns 0 = hit, 1 = miss, 2 = stop. */
@@ -590,6 +592,8 @@ static void build_tracklet(const sector_ctx* sc, const int32_t* up2, int32_t sta
   res->chi2 = chi2;
   res->par[0] = inner_s.x;
   for (int i = 0; i < 5; ++i) res->par[1 + i] = inner_s.p[i];
+  res->s_in = inner_s;
+  res->s_out = last;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -657,6 +661,8 @@ typedef struct {
   double* par;       /* [n_tracks][8] */
   int32_t* meta;     /* [n_tracks][4] (first relative to this sector) */
   int32_t* clusters; /* [n_clusters] */
+  kstate* ends;      /* [n_tracks][2]: inner and outer end states */
+  int32_t* end_rows; /* [n_tracks][2]: their rows */
   int status;
 } sector_out;
 
@@ -677,15 +683,18 @@ static void track_sector(const orc_event* ev, const orc_geometry* geo, double bz
   int32_t* ids = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_tl + 1));
   sector_seeds(&sc, up2, dn2, ids, n_tl);
   int32_t* hits = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_tl * nr + 1));
-  int32_t* row_lo = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_tl + 1));
-  int32_t* row_hi = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_tl + 1));
-  int32_t* nn = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_tl + 1));
-  int32_t* ndf = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_tl + 1));
-  double* chi2 = (double*)malloc(sizeof(double) * (size_t)(n_tl + 1));
-  double* par = (double*)malloc(sizeof(double) * (size_t)(6 * n_tl + 1));
+  int32_t* row_lo = (int32_t*)calloc((size_t)(n_tl + 1), sizeof(int32_t));
+  int32_t* row_hi = (int32_t*)calloc((size_t)(n_tl + 1), sizeof(int32_t));
+  int32_t* nn = (int32_t*)calloc((size_t)(n_tl + 1), sizeof(int32_t));
+  int32_t* ndf = (int32_t*)calloc((size_t)(n_tl + 1), sizeof(int32_t));
+  double* chi2 = (double*)calloc((size_t)(n_tl + 1), sizeof(double));
+  double* par = (double*)calloc((size_t)(6 * n_tl + 1), sizeof(double));
+  kstate* ends = (kstate*)malloc(sizeof(kstate) * (size_t)(2 * n_tl + 1));
   for (int64_t t = 0; t < n_tl; ++t) {
     tl_result res;
     build_tracklet(&sc, up2, ids[t], hits + t * nr, &res);
+    ends[2 * t] = res.s_in;
+    ends[2 * t + 1] = res.s_out;
     row_lo[t] = res.row_lo;
     row_hi[t] = res.row_hi;
     nn[t] = res.n;
@@ -712,6 +721,8 @@ static void track_sector(const orc_event* ev, const orc_geometry* geo, double bz
   so->par = (double*)malloc(sizeof(double) * (size_t)(8 * nt + 1));
   so->meta = (int32_t*)malloc(sizeof(int32_t) * (size_t)(4 * nt + 1));
   so->clusters = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nc + 1));
+  so->ends = (kstate*)malloc(sizeof(kstate) * (size_t)(2 * nt + 1));
+  so->end_rows = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * nt + 1));
   int64_t it = 0, ic = 0;
   for (int64_t t = 0; t < n_tl; ++t) {
     if (!keep[t]) continue;
@@ -727,10 +738,14 @@ static void track_sector(const orc_event* ev, const orc_geometry* geo, double bz
     so->meta[4 * it + 1] = (int32_t)(ic - first);
     so->meta[4 * it + 2] = (int32_t)first;
     so->meta[4 * it + 3] = ids[t];
+    so->ends[2 * it] = ends[2 * t];
+    so->ends[2 * it + 1] = ends[2 * t + 1];
+    so->end_rows[2 * it] = row_lo[t];
+    so->end_rows[2 * it + 1] = row_hi[t];
     ++it;
   }
   free(ids); free(hits); free(row_lo); free(row_hi); free(nn); free(ndf); free(chi2);
-  free(par); free(owner); free(keep);
+  free(par); free(owner); free(keep); free(ends);
   sector_free(&sc);
 }
 
@@ -770,8 +785,258 @@ static int check_event(const orc_event* ev, const orc_geometry* geo) {
   return 0;
 }
 
-int orc_track_event(const orc_event* ev, const orc_geometry* geo, double bz,
-                    const orc_params* prm, orc_tracks* out, int n_threads) {
+/* ------------------------------------------------------------------------ */
+/* Global tracking (section 5)                                               */
+/* ------------------------------------------------------------------------ */
+/*
+ * A sector track needs min_clusters clusters, so the part of a track beyond a
+ * sector boundary that is too short to be a sector track of its own is not
+ * found.  The paper prolongs the track segments that end at a sector edge:
+ * their parameters are converted to the neighbouring sector's frame and the
+ * tracklet construction continues there.  Reading used:
+ *   - both ends of every sector track are tried: the inner end starts from
+ *     the inward fit at the innermost cluster, the outer end from the
+ *     outward filter at the outermost cluster (state and covariance);
+ *   - from the end, the track is propagated row by row away from its
+ *     clusters (inward: decreasing rows) in its own sector, without search
+ *     (those rows were searched by the sector tracker); if at some row it is
+ *     outside the trapezoid (|y| > x tan_half) it has left through the side
+ *     edge; reaching the first/last row, |sin phi| > max_sinphi or
+ *     |z| > z_max ends it without prolongation;
+ *   - the neighbour is the sector on that side: same z half (section 1:
+ *     2 x 18 sectors), sector index +1 (mod 18) for y > 0, -1 for y < 0, if
+ *     the event holds it; its centre line is one sector width (2 atan of
+ *     tan_half) away;
+ *   - the state at the last row inside the own sector is rotated into the
+ *     neighbour's frame (krotate), so that the neighbour's rows crossed
+ *     between the edge and the next own row are not skipped, and the
+ *     construction continues from the first row beyond the rotated x in the
+ *     same direction (rows where the track is outside the neighbour's
+ *     trapezoid hold none of its clusters and count as misses), with the sector tracker's extension rule (chi^2 gate,
+ *     stop after more than max_miss consecutive misses, same stops), taking
+ *     only clusters that no sector track owns;
+ *   - a free cluster taken by several prolongations goes to the one with the
+ *     smallest (seed id of its track, end); each prolongation keeps the
+ *     clusters it owns (at least one, else it is not reported) and reports
+ *     the state of its own fit at its last collected cluster, the chi^2 of
+ *     its updates and ndf = 2 per collected cluster.
+ */
+
+/* Rotation of the local frame by d (radians; the new x axis at angle d from
+ * the old one).  The point and the direction stay; the reference x becomes
+ * the rotated x.  For the covariance, a change of the old y at fixed old x
+ * is brought back onto the new reference plane along the track: the
+ * Jacobian has dy'/dy = cos(phi)/cos(phi'), dz'/dy = -sin(d) tan(lambda) /
+ * cos(phi'), d sin(phi')/dy = kappa sin(d) (the turn over that path) and
+ * d sin(phi')/d sin(phi) = cos(phi')/cos(phi).  Returns 1, state unchanged,
+ * if the direction would not point along +x' (cos(phi') <= 0). */
+static int krotate(kstate* s, double d, double bz) {
+  const double ca = cos(d), sa = sin(d);
+  const double sp = s->p[2], cp = sqrt((1.0 - sp) * (1.0 + sp));
+  const double sp2 = sp * ca - cp * sa, cp2 = cp * ca + sp * sa;
+  if (!(cp2 > 0.0)) return 1;
+  double J[5][5] = {{0}};
+  J[0][0] = cp / cp2;
+  J[1][0] = -sa * s->p[3] / cp2;
+  J[1][1] = 1.0;
+  J[2][0] = CLIGHT * bz * s->p[4] * sa;
+  J[2][2] = cp2 / cp;
+  J[3][3] = 1.0;
+  J[4][4] = 1.0;
+  const double x2 = s->x * ca + s->p[0] * sa, y2 = -s->x * sa + s->p[0] * ca;
+  s->x = x2;
+  s->p[0] = y2;
+  s->p[2] = sp2;
+  mat_jcjt(s->C, J);
+  return 0;
+}
+
+/* search_row among the clusters no track owns (cluster_track < 0). */
+static int32_t search_row_free(const sector_ctx* sc, int r, const kstate* s,
+                               const int32_t* cluster_track) {
+  const orc_params* p = sc->prm;
+  double sy2 = p->sigma_y * p->sigma_y, sz2 = p->sigma_z * p->sigma_z;
+  double S00 = s->C[0][0] + sy2, S11 = s->C[1][1] + sz2;
+  double wy = sqrt(p->chi2_gate * S00) * (1.0 + 1e-9) + 1e-12;
+  double wz = sqrt(p->chi2_gate * S11) * (1.0 + 1e-9) + 1e-12;
+  int64_t base = sc->ro[0], end = sc->ro[r + 1] - base;
+  double best = INFINITY;
+  int32_t bi = -1;
+  for (int64_t i = row_lower_bound(sc, r, s->p[0] - wy); i < end; ++i) {
+    int32_t j = sc->sorted[i];
+    double yj = sc->ev->y[j];
+    if (yj > s->p[0] + wy) break;
+    if (cluster_track[j] >= 0) continue;
+    double zj = sc->ev->z[j];
+    if (fabs(zj - s->p[1]) > wz) continue;
+    double chi2 = kchi2(s, yj, zj, sy2, sz2);
+    if (chi2 <= p->chi2_gate && (chi2 < best || (chi2 == best && j < bi))) {
+      best = chi2;
+      bi = j;
+    }
+  }
+  return bi;
+}
+
+typedef struct {
+  int32_t track, end, seed, sector_id, n;
+  int32_t* cl;   /* [n_rows] collected clusters in the order met */
+  double chi2;
+  kstate fin;
+} prol_t;
+
+/* Prolongation of one end of one track; returns 1 if it collected clusters. */
+static int prolong_one(const orc_event* ev, const orc_geometry* geo, double bz,
+                       const orc_params* p, const sector_ctx* ctx, const int* phys2slot,
+                       int slot, const kstate* start, int row, int dir,
+                       const int32_t* cluster_track, prol_t* out) {
+  const int nr = geo->n_rows;
+  const double th = (double)geo->tan_half_angle;
+  const double sy2 = p->sigma_y * p->sigma_y, sz2 = p->sigma_z * p->sigma_z;
+  kstate s = *start, last = *start;
+  /* 1. own sector: propagate until the track leaves through a side edge;
+   * `last` is the state at the last row inside */
+  int exit_row = -1;
+  for (int r = row + dir; r >= 0 && r < nr; r += dir) {
+    if (kprop(&s, geo->row_x[r], bz, p->max_sinphi, NULL)) return 0;
+    if (fabs(s.p[1]) > (double)geo->z_max) return 0;
+    if (fabs(s.p[0]) > (double)geo->row_x[r] * th) {
+      exit_row = r;
+      break;
+    }
+    last = s;
+  }
+  if (exit_row < 0) return 0;
+  /* 2. the neighbour on that side */
+  const int phys = ev->sector_id[slot];
+  const int half = phys / 18, idx = phys % 18;
+  const int up = s.p[0] > 0.0;
+  s = last;
+  const int nphys = half * 18 + (idx + (up ? 1 : 17)) % 18;
+  const int nslot = (nphys >= 0 && nphys < 36) ? phys2slot[nphys] : -1;
+  if (nslot < 0) return 0;
+  /* neighbouring sectors' centre lines are one sector width apart */
+  const double width = 2.0 * atan(th);
+  if (krotate(&s, (up ? 1.0 : -1.0) * width, bz)) return 0;
+  if (fabs(s.p[2]) > p->max_sinphi) return 0;
+  /* 3. continue the construction there, from the first row beyond x */
+  int r = dir < 0 ? nr - 1 : 0;
+  if (dir < 0)
+    while (r >= 0 && (double)geo->row_x[r] >= s.x) --r;
+  else
+    while (r < nr && (double)geo->row_x[r] <= s.x) ++r;
+  const sector_ctx* sc = &ctx[nslot];
+  int misses = 0, n = 0;
+  double chi2 = 0.0;
+  for (; r >= 0 && r < nr; r += dir) {
+    if (kprop(&s, geo->row_x[r], bz, p->max_sinphi, NULL)) break;
+    if (fabs(s.p[1]) > (double)geo->z_max) break;
+    int32_t h = -1;
+    if (!(fabs(s.p[0]) > (double)geo->row_x[r] * th)) h = search_row_free(sc, r, &s, cluster_track);
+    if (h >= 0) {
+      chi2 += kupdate(&s, sc->ev->y[h], sc->ev->z[h], sy2, sz2);
+      out->cl[n++] = h;
+      out->fin = s;
+      misses = 0;
+    } else if (++misses > p->max_miss) {
+      break;
+    }
+  }
+  if (n == 0) return 0;
+  out->n = n;
+  out->chi2 = chi2;
+  out->sector_id = nphys;
+  return 1;
+}
+
+static int global_tracking(const orc_event* ev, const orc_geometry* geo, double bz,
+                           const orc_params* prm, const sector_out* outs,
+                           const orc_tracks* trk, orc_prolongations* pro) {
+  const int nr = geo->n_rows;
+  int phys2slot[36];
+  for (int i = 0; i < 36; ++i) phys2slot[i] = -1;
+  for (int sl = 0; sl < ev->n_sectors; ++sl) {
+    int ph = ev->sector_id[sl];
+    if (ph >= 0 && ph < 36 && phys2slot[ph] < 0) phys2slot[ph] = sl;
+  }
+  sector_ctx* ctx = (sector_ctx*)calloc((size_t)(ev->n_sectors + 1), sizeof(sector_ctx));
+  for (int sl = 0; sl < ev->n_sectors; ++sl)
+    if (sector_init(&ctx[sl], ev, geo, prm, bz, sl)) {
+      for (int k = 0; k < sl; ++k) sector_free(&ctx[k]);
+      free(ctx);
+      return -1;
+    }
+  int64_t nt = trk->n_tracks;
+  prol_t* pr = (prol_t*)calloc((size_t)(2 * nt + 1), sizeof(prol_t));
+  int32_t* pool = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * nt * nr + 1));
+  int64_t np = 0, it = 0;
+  for (int sl = 0; sl < ev->n_sectors; ++sl) {
+    const sector_out* so = &outs[sl];
+    for (int64_t t = 0; t < so->n_tracks; ++t, ++it)
+      for (int end = 0; end < 2; ++end) {
+        prol_t* q = &pr[np];
+        q->cl = pool + np * nr;
+        q->track = (int32_t)it;
+        q->end = end;
+        q->seed = so->meta[4 * t + 3];
+        if (prolong_one(ev, geo, bz, prm, ctx, phys2slot, sl, &so->ends[2 * t + end],
+                        so->end_rows[2 * t + end], end ? 1 : -1, trk->cluster_track, q))
+          ++np;
+      }
+  }
+  /* free clusters claimed several times: smallest (seed id, end) wins */
+  int64_t N = ev->n_clusters;
+  int32_t* owner = (int32_t*)malloc(sizeof(int32_t) * (size_t)(N > 0 ? N : 1));
+  for (int64_t c = 0; c < N; ++c) owner[c] = -1;
+  for (int64_t k = 0; k < np; ++k)
+    for (int32_t j = 0; j < pr[k].n; ++j) {
+      int32_t c = pr[k].cl[j];
+      int32_t o = owner[c];
+      if (o < 0 || pr[k].seed < pr[o].seed || (pr[k].seed == pr[o].seed && pr[k].end < pr[o].end))
+        owner[c] = (int32_t)k;
+    }
+  int64_t n_out = 0, n_cl = 0;
+  for (int64_t k = 0; k < np; ++k) {
+    int32_t own = 0;
+    for (int32_t j = 0; j < pr[k].n; ++j) own += owner[pr[k].cl[j]] == k;
+    if (own > 0) {
+      ++n_out;
+      n_cl += own;
+    }
+  }
+  pro->n = (int32_t)n_out;
+  pro->n_clusters = (int32_t)n_cl;
+  int status = (n_out > pro->cap || n_cl > pro->cap_clusters) ? 1 : 0;
+  if (status == 0) {
+    int64_t io = 0, ic = 0;
+    for (int64_t k = 0; k < np; ++k) {  /* already in (track, end) order */
+      int64_t first = ic;
+      for (int32_t j = 0; j < pr[k].n; ++j)
+        if (owner[pr[k].cl[j]] == k) pro->cluster[ic++] = pr[k].cl[j];
+      if (ic == first) continue;
+      double* P = pro->par + 8 * io;
+      P[0] = pr[k].fin.x;
+      for (int i = 0; i < 5; ++i) P[1 + i] = pr[k].fin.p[i];
+      P[6] = pr[k].chi2;
+      P[7] = 2.0 * pr[k].n;
+      int32_t* M = pro->meta + 5 * io;
+      M[0] = pr[k].track;
+      M[1] = pr[k].end;
+      M[2] = pr[k].sector_id;
+      M[3] = (int32_t)(ic - first);
+      M[4] = (int32_t)first;
+      ++io;
+    }
+  }
+  free(owner); free(pool); free(pr);
+  for (int sl = 0; sl < ev->n_sectors; ++sl) sector_free(&ctx[sl]);
+  free(ctx);
+  return status;
+}
+
+static int track_all(const orc_event* ev, const orc_geometry* geo, double bz,
+                     const orc_params* prm, orc_tracks* out, orc_prolongations* pro,
+                     int n_threads) {
   if (check_event(ev, geo) || !prm || !out) return -1;
   int64_t N = ev->n_clusters;
   size_t nb = sizeof(int32_t) * (size_t)(N > 0 ? N : 1);
@@ -816,12 +1081,43 @@ int orc_track_event(const orc_event* ev, const orc_geometry* geo, double bz,
       memcpy(out->track_cluster + ic, so->clusters, sizeof(int32_t) * (size_t)so->n_clusters);
       ic += so->n_clusters;
     }
+    if (pro) status = global_tracking(ev, geo, bz, prm, P.outs, out, pro);
   }
   for (int s = 0; s < ev->n_sectors; ++s) {
     free(P.outs[s].par); free(P.outs[s].meta); free(P.outs[s].clusters);
+    free(P.outs[s].ends); free(P.outs[s].end_rows);
   }
   free(P.outs); free(P.up); free(P.dn); free(P.up2); free(P.dn2);
   return status;
+}
+
+int orc_track_event(const orc_event* ev, const orc_geometry* geo, double bz,
+                    const orc_params* prm, orc_tracks* out, int n_threads) {
+  return track_all(ev, geo, bz, prm, out, NULL, n_threads);
+}
+
+int orc_track_event_global(const orc_event* ev, const orc_geometry* geo, double bz,
+                           const orc_params* prm, orc_tracks* out, orc_prolongations* pro,
+                           int n_threads) {
+  if (!pro) return -1;
+  return track_all(ev, geo, bz, prm, out, pro, n_threads);
+}
+
+int orc_rotate(double x, const double* st, const double* cov, double d, double bz,
+               double* x_out, double* st_out, double* cov_out) {
+  if (!st || !x_out || !st_out) return -1;
+  kstate s;
+  s.x = x;
+  for (int i = 0; i < 5; ++i) s.p[i] = st[i];
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j) s.C[i][j] = cov ? cov[5 * i + j] : 0.0;
+  if (krotate(&s, d, bz)) return 1;
+  *x_out = s.x;
+  for (int i = 0; i < 5; ++i) st_out[i] = s.p[i];
+  if (cov_out)
+    for (int i = 0; i < 5; ++i)
+      for (int j = 0; j < 5; ++j) cov_out[5 * i + j] = s.C[i][j];
+  return 0;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -89,6 +89,32 @@ void orc_params_default(orc_params* p);
 int orc_track_event(const orc_event* ev, const orc_geometry* geo, double bz,
                     const orc_params* prm, orc_tracks* out, int n_threads);
 
+/* ---- global tracking (section 5) ----------------------------------------
+ * Prolongation of sector tracks that leave their sector through a side edge
+ * into the neighbouring sector (reading in tpc_oracle.c).  Prolongations are
+ * ordered by (track index, end) and each holds the free clusters it owns. */
+typedef struct {
+  int32_t cap, cap_clusters;   /* in: capacities */
+  int32_t n, n_clusters;       /* out: sizes (also when too small) */
+  double* par;      /* [cap][8]: x, y, z, sinphi, tanl, qpt at the last collected
+                       cluster, in the frame of the sector entered; chi2; ndf */
+  int32_t* meta;    /* [cap][5]: track index, end (0 inner, 1 outer), sector_id
+                       entered, n_clusters, first */
+  int32_t* cluster; /* [cap_clusters]: cluster indices in the order met */
+} orc_prolongations;
+
+/* orc_track_event, then the prolongation of its tracks.  Returns 1 if a
+ * capacity is too small (sizes reported). */
+int orc_track_event_global(const orc_event* ev, const orc_geometry* geo, double bz,
+                           const orc_params* prm, orc_tracks* out,
+                           orc_prolongations* pro, int n_threads);
+
+/* Rotation of a state (and covariance, may be NULL) at x into a frame turned
+ * by d radians.  Returns 1 if the direction would not point along the new
+ * x axis. */
+int orc_rotate(double x, const double* st, const double* cov, double d, double bz,
+               double* x_out, double* st_out, double* cov_out);
+
 /* ---- individual steps, for stage-by-stage checks ---------------------- */
 
 /* Neighbours finder (section 1): up/dn links of every cluster, -1 = none. */
