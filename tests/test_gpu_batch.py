@@ -149,11 +149,11 @@ def test_autotuner_picks_a_candidate(tracker, geo, events, tmp_path, monkeypatch
     tracker.set_tuning()
 
 
-def test_tuning_rejects_occupancy_below_one(tracker):
+def test_tuning_rejects_out_of_range_settings(tracker):
     with pytest.raises(tpc.TpcError):
         tracker.set_tuning(bin_occupancy=0.5)
     with pytest.raises(tpc.TpcError):
         tracker.set_tuning(construct_schedule=2)
     with pytest.raises(tpc.TpcError):
-        tracker.set_tuning(construct_lanes=0)
+        tracker.set_tuning(construct_lanes=65)
     tracker.set_tuning()
