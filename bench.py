@@ -131,12 +131,16 @@ def oracle_params(tpc, gpu_params):
     return oracle.default_params(**vals)
 
 
+# Oracle work of the sections: each section stores what the oracle needs here
+# and the cpu_baseline leg (the only code that runs the oracle) fills in the
+# comparisons.
+ORACLE_CHECKS = {}
+
+
 def single_sector_section(tr, tpc, synth, geo, prm, steps, log_):
     """One sector, 200 tracks: the plain path on the smallest event (latency
-    bound), the oracle on the same event, and their concordance."""
+    bound); the oracle's time and concordance come from the cpu_baseline leg."""
     import torch
-    import oracle
-    from oracle import concordance
     e = synth.make_preset("c1_sector", 1)
     dev = tpc.DeviceEvent.from_host(e.y, e.z, e.row_offsets, e.sector_id)
     for _ in range(5):
@@ -148,63 +152,38 @@ def single_sector_section(tr, tpc, synth, geo, prm, steps, log_):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     res = tpc.to_numpy(res)
-    ev_host = dict(y=e.y, z=e.z, row_offsets=e.row_offsets, sector_id=e.sector_id)
-    t1 = time.perf_counter()
-    ref = oracle.track_event(ev_host, (synth.ROW_X, synth.TAN_HALF, synth.Z_MAX), e.bz,
-                             oracle_params(tpc, prm), n_threads=1)
-    t_orc = time.perf_counter() - t1
-    rep = concordance.compare(ref, res, e.n_clusters)
+    ORACLE_CHECKS["single_sector"] = dict(
+        ev=dict(y=e.y, z=e.z, row_offsets=e.row_offsets, sector_id=e.sector_id), bz=e.bz,
+        res=res, n=e.n_clusters)
     return dict(workload=f"one sector, 200 helix tracks, 2% noise, seed 1, {e.n_clusters} clusters",
                 events_per_s=round(steps / el, 1), clusters_per_s=round(e.n_clusters * steps / el, 1),
-                ms_per_event=round(el / steps * 1e3, 4), oracle_s_per_event=round(t_orc, 4),
-                oracle_cores=1, n_tracks=int(res["n_tracks"]),
-                cluster_concordance=rep["cluster_concordance"],
-                track_concordance=rep["track_concordance"], par_fail=rep["par_fail"])
+                ms_per_event=round(el / steps * 1e3, 4), n_tracks=int(res["n_tracks"]))
 
 
 def central_concordance_section(tr, tpc, synth, geo, prm, seeds, log_):
-    """Concordance with the FP64 oracle over several central events (so that
-    99.99% is resolvable on ~100k tracks)."""
+    """The GPU's tracks of several central events (so that concordance with
+    the oracle, computed by the cpu_baseline leg, resolves 99.99% on ~100k
+    tracks)."""
     import concurrent.futures as cf
-    import oracle
-    from oracle import concordance
     with cf.ProcessPoolExecutor(_pool_workers()) as ex:
         host = list(ex.map(_gen_preset, [("c2_central", s) for s in seeds]))
-    op = oracle_params(tpc, prm)
-    cores = _pool_workers()
-    n_tr = n_cl = 0
-    miss_cl = miss_tr = par_fail = par_cmp = 0
-    worst = 1.0
-    t_orc = 0.0
+    runs = []
     for (y, z, ro, si) in host:
         dev = tpc.DeviceEvent.from_host(y, z, ro, si)
-        res = tpc.to_numpy(tr.track_event(dev, geo, 0.5, prm))
-        t1 = time.perf_counter()
-        ref = oracle.track_event(dict(y=y, z=z, row_offsets=ro, sector_id=si),
-                                 (synth.ROW_X, synth.TAN_HALF, synth.Z_MAX), 0.5, op,
-                                 n_threads=cores)
-        t_orc += time.perf_counter() - t1
-        rep = concordance.compare(ref, res, len(y))
-        worst = min(worst, rep["cluster_concordance"], rep["track_concordance"])
-        n_tr += rep["n_tracks_a"]
-        n_cl += len(y)
-        miss_tr += round((1 - rep["track_concordance"]) * rep["n_tracks_a"])
-        par_fail += rep["par_fail"]
-        par_cmp += rep["par_compared"]
+        runs.append((dict(y=y, z=z, row_offsets=ro, sector_id=si),
+                     tpc.to_numpy(tr.track_event(dev, geo, 0.5, prm))))
+    ORACLE_CHECKS["central_concordance"] = dict(runs=runs)
     return dict(workload=f"{len(seeds)} central events (seeds {seeds[0]}-{seeds[-1]})",
-                tracks=n_tr, clusters=n_cl, worst_concordance=worst,
-                unmatched_tracks=miss_tr, par_compared=par_cmp, par_fail=par_fail,
-                oracle_s_per_event=round(t_orc / len(seeds), 4), oracle_cores=cores)
+                tracks=int(sum(r["n_tracks"] for _, r in runs)),
+                clusters=int(sum(len(h["y"]) for h, _ in runs)))
 
 
 def stress_section(tr, tpc, synth, geo, n_events, steps, log_):
     """Stress events (20000 primaries + 6000 loopers, 10% noise, sigma 0.15)
-    in batches of n_events: throughput, and concordance and parameter error
-    against the oracle on the first event."""
+    in batches of n_events: throughput; concordance and parameter error
+    against the oracle on the first event come from the cpu_baseline leg."""
     import concurrent.futures as cf
     import torch
-    import oracle
-    from oracle import concordance
     seeds = [5000 + i for i in range(n_events)]
     log_(f"generating {n_events} stress events")
     with cf.ProcessPoolExecutor(_pool_workers()) as ex:
@@ -219,24 +198,121 @@ def stress_section(tr, tpc, synth, geo, n_events, steps, log_):
         res = tr.track_batch(devs, geo, 0.5, prm)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    r0 = tpc.to_numpy(res[0])
     y, z, ro, si = host[0]
-    t1 = time.perf_counter()
-    ref = oracle.track_event(dict(y=y, z=z, row_offsets=ro, sector_id=si),
-                             (synth.ROW_X, synth.TAN_HALF, synth.Z_MAX), 0.5,
-                             oracle_params(tpc, prm), n_threads=_pool_workers())
-    t_orc = time.perf_counter() - t1
-    rep = concordance.compare(ref, r0, len(y))
+    ORACLE_CHECKS["stress"] = dict(ev=dict(y=y, z=z, row_offsets=ro, sector_id=si), bz=0.5,
+                                   res=tpc.to_numpy(res[0]), n=len(y), prm=prm)
     return dict(workload=f"{n_events} stress events per batch (20000 primaries + 6000 loopers, "
                          f"10% noise, sigma 0.15 cm; seeds {seeds[0]}+), {n_cl} clusters",
                 events_per_s=round(n_events * steps / el, 2),
                 clusters_per_s=round(n_cl * steps / el, 1),
-                ms_per_batch=round(el / steps * 1e3, 3),
-                oracle_s_per_event=round(t_orc, 3), oracle_cores=_pool_workers(),
-                cluster_concordance=rep["cluster_concordance"],
-                track_concordance=rep["track_concordance"],
-                par_compared=rep["par_compared"], par_fail=rep["par_fail"],
-                par_max_rel=rep["par_max_rel"])
+                ms_per_batch=round(el / steps * 1e3, 3))
+
+
+def global_section(tr, tpc, synth, geo, prm, e, dev_ev, steps, log_):
+    """Global tracking (section 5) on the benchmark event: the whole path
+    followed by the prolongation of the tracks into neighbouring sectors,
+    against the plain path, and what it adds against MC truth; the oracle's
+    prolongations (concordance) come from the cpu_baseline leg."""
+    import torch
+    from paper_1712_09407_amd import quality
+    for _ in range(3):
+        trk, pro = tr.track_event_global(dev_ev, geo, e.bz, prm)
+        tr.track_event(dev_ev, geo, e.bz, prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        tr.track_event(dev_ev, geo, e.bz, prm)
+    torch.cuda.synchronize()
+    plain = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        trk, pro = tr.track_event_global(dev_ev, geo, e.bz, prm)
+    torch.cuda.synchronize()
+    glob = (time.perf_counter() - t0) / steps
+    tr.set_timing(None)
+    tr.reset_stats()
+    tr.track_event_global(dev_ev, geo, e.bz, prm)
+    st = tr.stats()
+    tr.set_timing([])
+    trk, pro = tpc.to_numpy(trk), tpc.to_numpy(pro)
+    q = quality.prolongation_report(e, trk, pro)
+    ORACLE_CHECKS["global_tracking"] = dict(
+        ev=dict(y=e.y, z=e.z, row_offsets=e.row_offsets, sector_id=e.sector_id), bz=e.bz,
+        trk=trk, pro=pro)
+    ks = ("k_construct", "k_pro_init", "k_prolong", "k_pro_own", "k_pro_reduce", "k_pro_scan",
+          "k_pro_output")
+    return dict(workload="benchmark central event, whole path + prolongation into "
+                         "neighbouring sectors",
+                events_per_s=round(1.0 / glob, 2), ms_per_event=round(glob * 1e3, 4),
+                plain_ms_per_event=round(plain * 1e3, 4),
+                overhead_ms=round((glob - plain) * 1e3, 4),
+                kernels_ms={k: round(st["kernel_ms"][k] / max(1, st["kernel_launches"][k]), 5)
+                            for k in ks},
+                **q)
+
+
+def cpu_baseline_leg(tpc, prm, main_args, log_):
+    """The oracle, on this host's cores: the headline baseline, then the
+    comparisons the sections asked for (ORACLE_CHECKS).  Returns the baseline,
+    the headline concordance and, per section, fields to merge into it."""
+    import oracle
+    from oracle import concordance
+    from paper_1712_09407_amd import synth
+    geo_t = (synth.ROW_X, synth.TAN_HALF, synth.Z_MAX)
+    op = oracle_params(tpc, prm)
+    base, conc = cpu_baseline(*main_args, op)
+    cores = _pool_workers()
+    extra = {}
+    for name, chk in ORACLE_CHECKS.items():
+        log_(f"oracle check: {name}")
+        try:
+            if name == "single_sector":
+                t1 = time.perf_counter()
+                ref = oracle.track_event(chk["ev"], geo_t, chk["bz"], op, n_threads=1)
+                t_orc = time.perf_counter() - t1
+                rep = concordance.compare(ref, chk["res"], chk["n"])
+                extra[name] = dict(oracle_s_per_event=round(t_orc, 4), oracle_cores=1,
+                                   cluster_concordance=rep["cluster_concordance"],
+                                   track_concordance=rep["track_concordance"],
+                                   par_fail=rep["par_fail"])
+            elif name == "central_concordance":
+                worst, miss_tr, par_fail, par_cmp, t_orc = 1.0, 0, 0, 0, 0.0
+                for ev, res in chk["runs"]:
+                    t1 = time.perf_counter()
+                    ref = oracle.track_event(ev, geo_t, 0.5, op, n_threads=cores)
+                    t_orc += time.perf_counter() - t1
+                    rep = concordance.compare(ref, res, len(ev["y"]))
+                    worst = min(worst, rep["cluster_concordance"], rep["track_concordance"])
+                    miss_tr += round((1 - rep["track_concordance"]) * rep["n_tracks_a"])
+                    par_fail += rep["par_fail"]
+                    par_cmp += rep["par_compared"]
+                extra[name] = dict(worst_concordance=worst, unmatched_tracks=miss_tr,
+                                   par_compared=par_cmp, par_fail=par_fail,
+                                   oracle_s_per_event=round(t_orc / len(chk["runs"]), 4),
+                                   oracle_cores=cores)
+            elif name == "stress":
+                t1 = time.perf_counter()
+                ref = oracle.track_event(chk["ev"], geo_t, chk["bz"],
+                                         oracle_params(tpc, chk["prm"]), n_threads=cores)
+                t_orc = time.perf_counter() - t1
+                rep = concordance.compare(ref, chk["res"], chk["n"])
+                extra[name] = dict(oracle_s_per_event=round(t_orc, 3), oracle_cores=cores,
+                                   cluster_concordance=rep["cluster_concordance"],
+                                   track_concordance=rep["track_concordance"],
+                                   par_compared=rep["par_compared"], par_fail=rep["par_fail"],
+                                   par_max_rel=rep["par_max_rel"])
+            elif name == "global_tracking":
+                t1 = time.perf_counter()
+                rtr, rpro = oracle.track_event_global(chk["ev"], geo_t, chk["bz"], op,
+                                                      n_threads=cores)
+                t_orc = time.perf_counter() - t1
+                extra[name] = dict(oracle_s_per_event=round(t_orc, 4), oracle_cores=cores,
+                                   oracle_prolongations=int(rpro["n"]),
+                                   **concordance.compare_prolongations(
+                                       rtr, rpro, chk["trk"], chk["pro"], len(chk["ev"]["y"])))
+        except Exception as exc:  # the headline line must still be printed
+            extra[name] = dict(oracle_error=f"{type(exc).__name__}: {exc}")
+    return base, conc, extra
 
 
 def _gen_event(args):
@@ -519,6 +595,8 @@ def main():
                     ("central_concordance", lambda: central_concordance_section(
                         tr, tpc, synth, geo, prm, list(range(2, 12)), log)),
                     ("stress", lambda: stress_section(tr, tpc, synth, geo, 16, 3, log)),
+                    ("global_tracking", lambda: global_section(tr, tpc, synth, geo, prm, e,
+                                                               dev_ev, 20, log)),
                     ("alpha_scan", lambda: alpha_scan_section(tr, tpc, synth, geo, [2, 3, 4], log)))
         for name, fn in sections:
             log(f"{name} ...")
@@ -530,10 +608,14 @@ def main():
     if not args.no_cpu_baseline:
         log("oracle baseline on the host cores ...")
         ev_host = dict(y=e.y, z=e.z, row_offsets=e.row_offsets, sector_id=e.sector_id)
-        base, conc = cpu_baseline(ev_host, (synth.ROW_X, synth.TAN_HALF, synth.Z_MAX), e.bz,
-                                  res, N, args.cpu_seconds, oracle_params(tpc, prm))
+        base, conc, extra = cpu_baseline_leg(
+            tpc, prm, (ev_host, (synth.ROW_X, synth.TAN_HALF, synth.Z_MAX), e.bz, res, N,
+                       args.cpu_seconds), log)
         line["cpu_baseline"] = base
         line["concordance"] = conc
+        for name, fields in extra.items():
+            if isinstance(line.get(name), dict):
+                line[name].update(fields)
     else:
         line["cpu_baseline"] = None
     tr.close()

@@ -147,6 +147,55 @@ int tpc_track_batch(tpc_ctx* ctx, const tpc_event* events, int n_events, const t
                     float bz_tesla, const tpc_params* params, tpc_tracks* outputs,
                     void* hip_stream);
 
+/* ---- global tracking (section 5) ----------------------------------------
+ * A sector track needs min_clusters clusters, so a short piece of a track
+ * beyond a sector edge is not found by the sector tracker.  Global tracking
+ * prolongs the ends of the sector tracks that leave their sector through a
+ * side edge: the end state is rotated into the neighbouring sector's frame
+ * and the construction continues there on the clusters no sector track owns.
+ * Reading of the paper's short description:
+ *   - both ends of every track are tried: the inner one from the inward fit
+ *     at its innermost cluster, the outer one from the outward filter at its
+ *     outermost cluster; helix steps away from the track through the own
+ *     sector's rows (no search) find the row where it leaves the trapezoid
+ *     (first/last row, |sin phi| > max_sinphi or |z| > z_max: no
+ *     prolongation);
+ *   - the neighbour is the sector on that side in the same half of the
+ *     2 x 18 layout (sector_id 0-17 and 18-35; index +1 mod 18 for y > 0,
+ *     -1 for y < 0), the event's first slot with that id; slots with other
+ *     ids are not prolonged;
+ *   - the state at the last row inside is rotated by one sector width
+ *     (2 atan(tan_half_angle)) and the extension continues from the first
+ *     row beyond its x, in the same direction, with the construction's
+ *     chi^2 gate and miss limit, taking only clusters whose cluster_track is
+ *     -1;
+ *   - a cluster collected by several prolongations goes to the one with the
+ *     smallest (seed id, end); a prolongation is reported if it owns at
+ *     least one cluster.
+ * Sector tracks and cluster_track are exactly those of tpc_track_event. */
+typedef struct {
+  int32_t cap;            /* rows of par / meta */
+  int32_t cap_clusters;   /* length of cluster */
+  int32_t* n;             /* HOST out: number of prolongations (also on CAPACITY) */
+  int32_t* n_clusters;    /* HOST out: clusters owned by them (also on CAPACITY) */
+  float* par;             /* DEVICE [cap][8]: x, y, z, sinphi, tanl, q/pT at the last
+                             collected cluster, in the frame of the sector entered;
+                             chi2 of its updates; ndf = 2 x clusters collected */
+  int32_t* meta;          /* DEVICE [cap][5]: track index, end (0 inner, 1 outer),
+                             sector_id entered, n_clusters owned, first (offset
+                             into cluster) */
+  int32_t* cluster;       /* DEVICE [cap_clusters]: owned clusters in the order
+                             collected (away from the track) */
+} tpc_prolongations;
+
+/* tpc_track_event followed by global tracking.  Prolongations are ordered by
+ * (track index, end).  Returns TPC_ERR_CAPACITY with the sizes set when the
+ * track or the prolongation outputs are too small (*pro->n and
+ * *pro->n_clusters are 0 when the tracks did not fit). */
+int tpc_track_event_global(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo,
+                           float bz_tesla, const tpc_params* params, tpc_tracks* out,
+                           tpc_prolongations* pro, void* hip_stream);
+
 /* Stage-by-stage access for checks (same kernels as tpc_track_event).
  * Runs the neighbours finder and the evolution step and copies the link
  * arrays into DEVICE buffers of n_clusters int32 each (any may be NULL):

@@ -58,8 +58,7 @@ def _best_partner(cl_a, own_a, n_a, ct_b, seed_b):
     return best, shared
 
 
-def compare(res_a, res_b, n_clusters: int, rel_tol: float = 1e-3) -> dict:
-    """Concordance of run B against run A (A = reference, e.g. the oracle)."""
+def _match(res_a, res_b, n_clusters: int):
     cl_a, own_a, n_a, seed_a = _track_of_clusters(res_a)
     cl_b, own_b, n_b, seed_b = _track_of_clusters(res_b)
     ct_a = np.asarray(res_a["cluster_track"])[:n_clusters]
@@ -73,6 +72,20 @@ def compare(res_a, res_b, n_clusters: int, rel_tol: float = 1e-3) -> dict:
     match_a = np.where(mutual, best_ab, -1)
     match_b = np.full(n_b.shape[0], -1, np.int64)
     match_b[match_a[mutual]] = ia[mutual]
+    return n_a, n_b, sh_ab, mutual, match_a, match_b
+
+
+def match_tracks(res_a, res_b, n_clusters: int):
+    """The one-to-one correspondence of the two runs' tracks: for each track
+    of A its partner in B or -1, and for each track of B its partner in A."""
+    _, _, _, _, match_a, match_b = _match(res_a, res_b, n_clusters)
+    return match_a, match_b
+
+
+def compare(res_a, res_b, n_clusters: int, rel_tol: float = 1e-3) -> dict:
+    """Concordance of run B against run A (A = reference, e.g. the oracle)."""
+    n_a, n_b, sh_ab, mutual, match_a, match_b = _match(res_a, res_b, n_clusters)
+    ia = np.arange(n_a.shape[0])
     # per matched pair: identical clusters (same cluster => same row) and the union of rows
     agree = np.where(mutual, sh_ab, 0)
     union = np.where(mutual, n_a + n_b[np.maximum(match_a, 0)] - sh_ab if n_b.size else n_a, n_a)
@@ -111,3 +124,65 @@ def compare(res_a, res_b, n_clusters: int, rel_tol: float = 1e-3) -> dict:
     out["cluster_concordance"] = min(out["cluster_concordance_ab"], out["cluster_concordance_ba"])
     out["track_concordance"] = min(out["track_concordance_ab"], out["track_concordance_ba"])
     return out
+
+
+def _prolongations_by_key(pro, track_key=None):
+    """(key of the prolonged track, end) -> (sector id entered, clusters,
+    par); the key is the track index, mapped through track_key if given
+    (tracks without a key get a key of their own, -1 - index)."""
+    out = {}
+    meta = np.asarray(pro["meta"]).reshape(-1, 5)
+    for k in range(int(pro["n"])):
+        t, end, sec, n, first = (int(v) for v in meta[k])
+        key = t if track_key is None else int(track_key[t])
+        if key < 0:
+            key = -1 - t
+        out[(key, end)] = (sec, np.asarray(pro["cluster"][first:first + n]),
+                           np.asarray(pro["par"][k], np.float64))
+    return out
+
+
+def compare_prolongations(tracks_a, pro_a, tracks_b, pro_b, n_clusters: int,
+                          rel_tol: float = 1e-3, chi2_tol: float = 1e-2) -> dict:
+    """Agreement of two runs' global-tracking prolongations.  Their tracks are
+    put in correspondence first (as in compare: a track is the same track in
+    both runs even when FP32 and FP64 chose different seeds among tracklets
+    with the same clusters); prolongations are then matched by (track, end).
+    cluster_concordance_ab: the fraction of A's prolongation clusters that
+    B's prolongation of the same (track, end) also holds; _ba the other way.
+    For pairs with identical clusters whose tracks grew from the same seed in
+    both runs, the parameters x..q/pT must agree within rel_tol relative
+    (absolute below 1), ndf exactly and chi2 within chi2_tol relative
+    (absolute below 1).  The chi2 of an update is r^2/S with a residual r of
+    about sigma: an FP32 rounding of 1e-5 in sin(phi) of the filtered state,
+    over the 10-20 cm lever arm to the next cluster, moves r by ~2e-4 cm, i.e.
+    chi2 by several 1e-3 relative, while the parameters agree far within
+    rel_tol; chi2_tol = 1e-2 covers that."""
+    match_a, match_b = match_tracks(tracks_a, tracks_b, n_clusters)
+    seed_a = np.asarray(tracks_a["track_meta"]).reshape(-1, 4)[:, 3]
+    seed_b = np.asarray(tracks_b["track_meta"]).reshape(-1, 4)[:, 3]
+    a = _prolongations_by_key(pro_a)
+    b = _prolongations_by_key(pro_b, match_b)   # unmatched tracks: negative keys
+    same = sum(np.intersect1d(v[1], b[k][1]).size for k, v in a.items() if k in b)
+    tot_a = sum(v[1].size for v in a.values())
+    tot_b = sum(v[1].size for v in b.values())
+    identical = compared = fail = other_seed = 0
+    for k, v in a.items():
+        if not (k in b and b[k][0] == v[0] and np.array_equal(b[k][1], v[1])):
+            continue
+        identical += 1
+        if seed_a[k[0]] != seed_b[match_a[k[0]]]:
+            # the same track built from another seed: its end states come from
+            # another outward filter, so its parameters are not compared
+            other_seed += 1
+            continue
+        compared += 1
+        pa, pb = v[2], b[k][2]
+        ok = np.all(np.abs(pb[:6] - pa[:6]) <= rel_tol * np.maximum(1.0, np.abs(pa[:6])))
+        ok = ok and pb[7] == pa[7] and abs(pb[6] - pa[6]) <= chi2_tol * max(1.0, abs(pa[6]))
+        fail += 0 if ok else 1
+    return dict(n_a=len(a), n_b=len(b), clusters_a=tot_a, clusters_b=tot_b,
+                cluster_concordance_ab=same / max(1, tot_a),
+                cluster_concordance_ba=same / max(1, tot_b),
+                identical=identical, other_seed=other_seed, par_compared=compared,
+                par_fail=fail)

@@ -30,6 +30,7 @@ struct KParams {
   int32_t construct_schedule;  // 0 = one lane per tracklet, 1 = row-synchronous
   int32_t nf_dense;            // neighbours finder for dense rows (larger LDS stage)
   int32_t construct_lanes;     // lane schedule: lanes of a wave that take tracklets
+  float rot_c, rot_s;          // cos, sin of one sector width (global tracking)
 };
 
 struct DevEvent {
@@ -69,6 +70,8 @@ enum Counter {
 enum ErrBits { E_OFFSETS = 1, E_NONFINITE = 2, E_TL_OVERFLOW = 4, E_CAPACITY = 8 };
 
 constexpr int kHitStride = 160;  // per-tracklet row slots (>= n_rows, padded)
+constexpr int kEndStride = 24;   // floats per tracklet end state (x, 5 state, 15 cov, pad)
+constexpr int kLayoutSectors = 36;  // 2 x 18 sectors: ids 0-17 and 18-35
 
 // Device scratch of one event.
 struct Scratch {
@@ -93,6 +96,30 @@ struct Scratch {
   int32_t *owned, *kept;   // [T]
   int32_t *trk_idx, *trk_off; // [T]
   int32_t* span_sum;       // [2 * spans]: kept / owned sums per span of tracklets
+  float* ends;             // [T][2][kEndStride] inner / outer end states, or null
+                           // (recorded only for global tracking)
+};
+
+// Device scratch of global tracking (section 5): one prolongation slot per
+// (tracklet, end), slot = 2 * tracklet + end.
+struct GlobalScratch {
+  int32_t* counters;   // [C_COUNT]: C_SEEDS = slots, C_TRACKS / C_TRACK_CLUSTERS = output
+                       // prolongations / clusters, C_ERR copied from the sector tracker
+  int32_t* p2s;        // [kLayoutSectors] first slot of each physical sector, or -1
+  int32_t* claim;      // [N] smallest slot that collected the cluster
+  int32_t* n;          // [2T] clusters collected (0 = no prolongation)
+  int32_t* nslot;      // [2T] sector slot entered
+  float* par;          // [2T][8] x, state at the last collected cluster, chi2, ndf
+  int32_t* hit;        // [2T][kHitStride] clusters in the order met
+  int32_t *owned, *kept, *idx, *off;  // [2T] clusters owned, reported, output index/offset
+  int32_t* span_sum;   // scan partials
+};
+
+struct ProOutputs {
+  int32_t cap, cap_clusters;
+  float* par;        // [cap][8]
+  int32_t* meta;     // [cap][5]: track, end, sector id, n_clusters, first
+  int32_t* cluster;  // [cap_clusters]
 };
 
 struct Outputs {
@@ -142,13 +169,19 @@ hipError_t enqueue_batch_scatter(const BatchBuffers& bb, const Scratch& sc, int 
                                  hipStream_t st);
 
 size_t scratch_bytes(int64_t n_clusters, int64_t n_rowslots, int64_t cap_tl);
+// Global tracking: the end states (Scratch::ends) and GlobalScratch.
+size_t global_bytes(int64_t n_clusters, int64_t cap_tl);
+void global_carve(void* base, int64_t n_clusters, int64_t cap_tl, float** ends,
+                  GlobalScratch* gs);
 void scratch_carve(void* base, int64_t n_clusters, int64_t n_rowslots, int64_t cap_tl,
                    Scratch* sc);
 
 // Kernels of one event, in launch order (index into timing tables).
 enum KernelId {
   K_ZERO, K_GRID, K_NF, K_EVO, K_SCAN_ROWS, K_SEED_WRITE, K_CONSTRUCT, K_OWN,
-  K_TL_REDUCE, K_TL_SCAN, K_OUTPUT, K_NUM
+  K_TL_REDUCE, K_TL_SCAN, K_OUTPUT,
+  // global tracking
+  K_PRO_INIT, K_PROLONG, K_PRO_OWN, K_PRO_REDUCE, K_PRO_SCAN, K_PRO_OUTPUT, K_NUM
 };
 extern const char* const kKernelNames[K_NUM];
 
@@ -163,5 +196,10 @@ enum Stage { STAGE_LINKS = 1, STAGE_SEEDS = 2, STAGE_TRACKLETS = 3, STAGE_ALL = 
 hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& sc,
                          const Outputs& out, int upto, hipStream_t st,
                          const KernelTimer* timer = nullptr, bool zero_counters = true);
+// Global tracking after enqueue_event(STAGE_ALL) with Scratch::ends set:
+// prolongs the event's tracks (reads the tracker's cluster_track output).
+hipError_t enqueue_global(const DevEvent& ev, const KParams& kp, const Scratch& sc,
+                          const Outputs& out, const GlobalScratch& gs, const ProOutputs& po,
+                          hipStream_t st, const KernelTimer* timer = nullptr);
 
 }  // namespace tpc

@@ -35,6 +35,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "tpc_internal.h"
 
 namespace tpc {
@@ -675,11 +677,17 @@ struct Work {
   int steps = 0, updates = 0, cands = 0;
 };
 
-// Best cluster of a row inside the chi^2 gate (smallest (chi2, index)); its
-// coordinates come back with it, so no reload is needed.
+struct AcceptAll {
+  __device__ bool operator()(int) const { return true; }
+};
+
+// Best cluster of a row inside the chi^2 gate (smallest (chi2, index)) among
+// those `accept` admits; its coordinates come back with it, so no reload is
+// needed.
+template <class Accept = AcceptAll>
 __device__ __forceinline__ int search_row(const Scratch& sc, const RowGrid& g, int rb,
                                           const KState& s, const KParams& kp, float& by,
-                                          float& bz_, Work& wk) {
+                                          float& bz_, Work& wk, Accept accept = Accept()) {
   if (g.n == 0) return -1;
   const float S00 = s.C.c00 + kp.sy2, S01 = s.C.c10, S11 = s.C.c11 + kp.sz2;
   const float idet = frcp(S00 * S11 - S01 * S01);
@@ -697,7 +705,8 @@ __device__ __forceinline__ int search_row(const Scratch& sc, const RowGrid& g, i
       const GridRec v = sc.g_rec[rb + j];
       const float ry = v.y - s.y, rz = v.z - s.z;
       const float chi2 = (ry * ry * S11 - 2.f * ry * rz * S01 + rz * rz * S00) * idet;
-      if (chi2 <= kp.chi2_gate && (chi2 < best || (chi2 == best && v.id < bid))) {
+      if (chi2 <= kp.chi2_gate && (chi2 < best || (chi2 == best && v.id < bid)) &&
+          accept(v.id)) {
         best = chi2;
         bid = v.id;
         by = v.y;
@@ -728,6 +737,35 @@ __device__ __forceinline__ int search_row(const Scratch& sc, const RowGrid& g, i
 
 enum Phase { P_CHAIN = 0, P_UP = 1, P_REFIT = 2, P_DOWN = 3, P_DONE = 4 };
 
+// End state of a tracklet (global tracking): x, state, packed covariance,
+// kEndStride floats, six 16-byte stores.
+__device__ __forceinline__ void store_end(float* E, const KState& s) {
+  float4* q = reinterpret_cast<float4*>(E);
+  const Cov& C = s.C;
+  q[0] = make_float4(s.x, s.y, s.z, s.sp);
+  q[1] = make_float4(s.tl, s.qpt, C.c00, C.c10);
+  q[2] = make_float4(C.c11, C.c20, C.c21, C.c22);
+  q[3] = make_float4(C.c30, C.c31, C.c32, C.c33);
+  q[4] = make_float4(C.c40, C.c41, C.c42, C.c43);
+  q[5] = make_float4(C.c44, 0.f, 0.f, 0.f);
+}
+__device__ __forceinline__ void load_end(const float* E, KState& s) {
+  const float4* q = reinterpret_cast<const float4*>(E);
+  const float4 a = q[0], b = q[1], c = q[2], d = q[3], e = q[4], f = q[5];
+  s.x = a.x; s.y = a.y; s.z = a.z; s.sp = a.w;
+  s.tl = b.x; s.qpt = b.y;
+  Cov& C = s.C;
+  C.c00 = b.z; C.c10 = b.w;
+  C.c11 = c.x; C.c20 = c.y; C.c21 = c.z; C.c22 = c.w;
+  C.c30 = d.x; C.c31 = d.y; C.c32 = d.z; C.c33 = d.w;
+  C.c40 = e.x; C.c41 = e.y; C.c42 = e.z; C.c43 = e.w;
+  C.c44 = f.x;
+}
+
+// ENDS: also record the two end states global tracking starts from -- the
+// outward filter at the outermost collected cluster and the inward fit at
+// the innermost one -- overwritten at every update of the respective pass.
+template <bool ENDS>
 struct Lane {
   KState s;
   int t = 0, phase = P_DONE, r = 0, k0 = 0, rsb = 0, last_row = 0, misses = 0, n = 0, inner = 0;
@@ -783,6 +821,7 @@ struct Lane {
     seed3(s, s_x[k0], ev.y[start], ev.z[start], s_x[k0 + m / 2], ev.y[bmid], s_x[k0 + m - 1],
           ev.y[last], ev.z[last], kp);
     dropped = fabsf(s.sp) > kp.max_sinphi;
+    if constexpr (ENDS) store_end(sc.ends + ((size_t)tt * 2 + 1) * kEndStride, s);
     last_row = k0;
     l_sp = s.sp; l_tl = s.tl; l_q = s.qpt; l_y = s.y; l_z = s.z;
     HY[k0] = make_float2(s.y, s.z);
@@ -800,7 +839,7 @@ struct Lane {
   }
 
   // Inward refit set-up from the outermost collected cluster.
-  __device__ void begin_refit(const KParams& kp, const float* s_x) {
+  __device__ void begin_refit(const KParams& kp, const Scratch& sc, const float* s_x) {
     s.x = s_x[last_row];
     s.y = l_y;
     s.z = l_z;
@@ -812,6 +851,7 @@ struct Lane {
     inner = last_row;
     chi2 = 0.f;
     o0 = s.x; o1 = s.y; o2 = s.z; o3 = s.sp; o4 = s.tl; o5 = s.qpt;
+    if constexpr (ENDS) store_end(sc.ends + (size_t)t * 2 * kEndStride, s);
     phase = P_REFIT;
     r = last_row - 1;
     prefetch_refit();
@@ -889,6 +929,7 @@ struct Lane {
       if (st == 0) {
         last_row = r;
         l_sp = s.sp; l_tl = s.tl; l_q = s.qpt; l_y = my; l_z = mz;
+        if constexpr (ENDS) store_end(sc.ends + ((size_t)t * 2 + 1) * kEndStride, s);
       }
       if (st != 2) {  // H[r] = hit, HY[r] = (my, mz) if a cluster was taken
         pend_r = r;
@@ -907,12 +948,12 @@ struct Lane {
         } else {
           phase = P_UP;
           misses = 0;
-          if (r >= nr) begin_refit(kp, s_x);
+          if (r >= nr) begin_refit(kp, sc, s_x);
         }
       } else {
         misses = st == 0 ? 0 : misses + 1;
         ++r;
-        if (st == 2 || misses > kp.max_miss || r >= nr) begin_refit(kp, s_x);
+        if (st == 2 || misses > kp.max_miss || r >= nr) begin_refit(kp, sc, s_x);
       }
     } else {  // P_REFIT or P_DOWN: collected clusters enter the final fit
       if (st == 0) {
@@ -920,6 +961,7 @@ struct Lane {
         ++n;
         inner = r;
         o0 = s.x; o1 = s.y; o2 = s.z; o3 = s.sp; o4 = s.tl; o5 = s.qpt;
+        if constexpr (ENDS) store_end(sc.ends + (size_t)t * 2 * kEndStride, s);
       }
       if (phase == P_DOWN) {
         if (st != 2) {  // H[r] = hit
@@ -1089,6 +1131,7 @@ __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 // s_waitcnt vmcnt(0) expcnt(7) lgkmcnt(15): wait for vector memory only
 constexpr int kWaitVm0 = 0x0F70;
 
+template <bool ENDS>
 __global__ __launch_bounds__(64) void k_construct_rows(DevEvent ev, KParams kp, Scratch sc) {
   __shared__ float s_x[TPC_MAX_ROWS];
   __shared__ RowGrid s_hdr[TPC_MAX_ROWS];  // grid headers of the current sector's rows
@@ -1139,7 +1182,7 @@ __global__ __launch_bounds__(64) void k_construct_rows(DevEvent ev, KParams kp, 
     for (int i = lane; i < nr; i += 64) s_hdr[i] = sc.grid[rsb + i];
     const int tA = min(sc.row_cnt[rsb], n_tl), tB = min(sc.row_cnt[rsb + nr], n_tl);
     const int t = tA + q * 64 + lane;
-    Lane ln;
+    Lane<ENDS> ln;
     if (t < tB) {
       ln.begin(t, ev, kp, sc, s_x);
       if (ln.dropped) ln.emit(sc);
@@ -1209,6 +1252,7 @@ __global__ __launch_bounds__(64) void k_construct_rows(DevEvent ev, KParams kp, 
 
 // ---- lane schedule
 
+template <bool ENDS>
 __global__ __launch_bounds__(kTlBlock) void k_construct_lanes(DevEvent ev, KParams kp, Scratch sc) {
   __shared__ float s_x[TPC_MAX_ROWS];
   if (event_bad(sc.counters)) return;
@@ -1244,7 +1288,7 @@ __global__ __launch_bounds__(kTlBlock) void k_construct_lanes(DevEvent ev, KPara
   };
   int kg = (int)threadIdx.x < A ? (int)(blockIdx.x / G) * A + (int)threadIdx.x : total_g;
   int t = kg < total_g ? group_tracklet(kg) : n_tl;
-  Lane ln;
+  Lane<ENDS> ln;
   RowGrid gn;  // grid header of the next extension row, loaded one step early
   if (t < n_tl) ln.begin(t, ev, kp, sc, s_x);
   while (t < n_tl) {
@@ -1544,6 +1588,237 @@ __global__ __launch_bounds__(kGridBlock) void k_output(DevEvent ev, KParams kp, 
   }
 }
 
+// ------------------------------------------------------------------ global tracking
+//
+// Section 5: the end of a sector track that leaves its sector through a side
+// edge is prolonged into the neighbouring sector.  One lane per slot
+// q = 2 * tracklet + end of a kept tracklet (end 0 = inner, 1 = outer):
+//   1. from the end state recorded by the constructor, helix steps away from
+//      the track through the own sector's rows, without search, until the
+//      track is outside the trapezoid; reaching the first/last row, the
+//      |sin phi| limit or |z| > z_max ends it without prolongation;
+//   2. the neighbour on that side -- same half of the 2 x 18 layout, index
+//      +1 (y > 0) or -1 (mod 18) -- if the event holds it (its first slot with
+//      that id); the state at the last row inside is rotated into its frame;
+//   3. the construction's extension continues there, row by row in the same
+//      direction (chi^2 gate, stop after more than max_miss consecutive
+//      misses), among the clusters no sector track owns.  A collected
+//      cluster is claimed with an atomic minimum of q, so that one collected
+//      by several prolongations goes to the smallest (seed id, end): tracklet
+//      indices follow the seed ids.
+// k_pro_own then counts the clusters each slot owns, the selection's scan
+// numbers the slots that own at least one, and k_pro_output writes them in
+// (track, end) order.
+
+__global__ __launch_bounds__(kGridBlock) void k_pro_init(DevEvent ev, Scratch sc,
+                                                         GlobalScratch gs) {
+  __shared__ int s_p2s[kLayoutSectors];
+  const int n_cl = ev.n_dev ? *ev.n_dev : ev.n_clusters;
+  for (int i = blockIdx.x * kGridBlock + threadIdx.x; i < n_cl; i += gridDim.x * kGridBlock)
+    gs.claim[i] = 0x7fffffff;
+  if (blockIdx.x != 0) return;
+  if (threadIdx.x < kLayoutSectors) s_p2s[threadIdx.x] = 0x7fffffff;
+  __syncthreads();
+  for (int sl = threadIdx.x; sl < ev.n_sectors; sl += kGridBlock) {
+    const int ph = ev.sector_id[sl];
+    if (ph >= 0 && ph < kLayoutSectors) atomicMin(&s_p2s[ph], sl);
+  }
+  __syncthreads();
+  if (threadIdx.x < kLayoutSectors) {
+    const int v = s_p2s[threadIdx.x];
+    gs.p2s[threadIdx.x] = v == 0x7fffffff ? -1 : v;
+  }
+  if (threadIdx.x < C_COUNT) {
+    // after any error of the sector tracker (its outputs are then not
+    // written) there are no slots: every later kernel does nothing
+    const int err = sc.counters[C_ERR];
+    int v = 0;
+    if (threadIdx.x == C_ERR) v = err;
+    else if (threadIdx.x == C_SEEDS) v = err ? 0 : 2 * min(sc.counters[C_SEEDS], sc.cap_tl);
+    gs.counters[threadIdx.x] = v;
+  }
+}
+
+// Rotation of the local frame by the angle whose cosine and sine are (ca, sa):
+// the point and the direction stay, x becomes the rotated x.  A change of y
+// at fixed x is carried along the track onto the new reference plane:
+// dy'/dy = cos(phi)/cos(phi'), dz'/dy = -sin(d) tan(lambda)/cos(phi'),
+// dsin(phi')/dy = kappa sin(d), dsin(phi')/dsin(phi) = cos(phi')/cos(phi).
+// False (state unchanged) if the direction would not point along +x'.
+__device__ __forceinline__ bool rotate(KState& s, float ca, float sa, const KParams& kp) {
+  const float sp = s.sp, cp = fsqrt((1.f - sp) * (1.f + sp));
+  const float sp2 = sp * ca - cp * sa, cp2 = cp * ca + sp * sa;
+  if (!(cp2 > 0.f)) return false;
+  const float j00 = cp / cp2, j10 = -sa * s.tl / cp2, j20 = kp.k_curv * s.qpt * sa;
+  const float j22 = cp2 / cp;
+  Cov& C = s.C;
+  // rows of J C: row 1 = j10 (C row 0) + (C row 1), row 2 = j20 (C row 0) + j22 (C row 2)
+  const float b0 = j10 * C.c00 + C.c10, b1 = j10 * C.c10 + C.c11;
+  const float b3 = j10 * C.c30 + C.c31, b4 = j10 * C.c40 + C.c41;
+  const float a0 = j20 * C.c00 + j22 * C.c20, a1 = j20 * C.c10 + j22 * C.c21;
+  const float a2 = j20 * C.c20 + j22 * C.c22, a3 = j20 * C.c30 + j22 * C.c32;
+  const float a4 = j20 * C.c40 + j22 * C.c42;
+  Cov N;
+  N.c00 = j00 * j00 * C.c00;
+  N.c10 = j00 * b0;
+  N.c11 = b0 * j10 + b1;
+  N.c20 = j00 * a0;
+  N.c21 = a0 * j10 + a1;
+  N.c22 = a0 * j20 + a2 * j22;
+  N.c30 = j00 * C.c30;
+  N.c31 = b3;
+  N.c32 = a3;
+  N.c33 = C.c33;
+  N.c40 = j00 * C.c40;
+  N.c41 = b4;
+  N.c42 = a4;
+  N.c43 = C.c43;
+  N.c44 = C.c44;
+  C = N;
+  const float x2 = s.x * ca + s.y * sa, y2 = -s.x * sa + s.y * ca;
+  s.x = x2;
+  s.y = y2;
+  s.sp = sp2;
+  return true;
+}
+
+struct FreeCluster {
+  const int32_t* cluster_track;
+  __device__ bool operator()(int c) const { return cluster_track[c] < 0; }
+};
+
+// Prolongation of slot q; returns the number of clusters collected.
+__device__ int prolong_slot(int q, const DevEvent& ev, const KParams& kp, const Scratch& sc,
+                            const GlobalScratch& gs, const int32_t* cluster_track,
+                            const float* s_x) {
+  const int t = q >> 1, e = q & 1, dir = e ? 1 : -1, nr = kp.n_rows;
+  KState s;
+  load_end(sc.ends + (size_t)q * kEndStride, s);
+  KState last = s;
+  int r = (e ? sc.row_hi[t] : sc.row_lo[t]) + dir;
+  // 1. own sector, no search, until the track is outside the trapezoid
+  bool left = false;
+  for (; r >= 0 && r < nr; r += dir) {
+    if (!propagate(s, s_x[r], kp)) return 0;
+    if (fabsf(s.z) > kp.z_max) return 0;
+    if (fabsf(s.y) > s_x[r] * kp.tan_half) {
+      left = true;
+      break;
+    }
+    last = s;
+  }
+  if (!left) return 0;
+  // 2. the neighbour on that side
+  const int phys = ev.sector_id[sc.seed_rs[t] / nr];
+  if (phys < 0 || phys >= kLayoutSectors) return 0;
+  const bool up = s.y > 0.f;
+  const int nphys = (phys / 18) * 18 + (phys % 18 + (up ? 1 : 17)) % 18;
+  const int ns = gs.p2s[nphys];
+  if (ns < 0) return 0;
+  s = last;
+  if (!rotate(s, kp.rot_c, up ? kp.rot_s : -kp.rot_s, kp)) return 0;
+  if (fabsf(s.sp) > kp.max_sinphi) return 0;
+  // 3. extension in the neighbour from the first row beyond x
+  r = dir < 0 ? nr - 1 : 0;
+  if (dir < 0)
+    while (r >= 0 && s_x[r] >= s.x) --r;
+  else
+    while (r < nr && s_x[r] <= s.x) ++r;
+  int32_t* H = gs.hit + (size_t)q * kHitStride;
+  float* P = gs.par + (size_t)q * 8;
+  const FreeCluster free_only{cluster_track};
+  Work wk;
+  int misses = 0, n = 0;
+  float chi2 = 0.f;
+  for (; r >= 0 && r < nr; r += dir) {
+    if (!propagate(s, s_x[r], kp)) break;
+    if (fabsf(s.z) > kp.z_max) break;
+    int h = -1;
+    float my = 0.f, mz = 0.f;
+    if (!(fabsf(s.y) > s_x[r] * kp.tan_half)) {
+      const int rs = ns * nr + r;
+      const RowGrid g = sc.grid[rs];
+      h = search_row(sc, g, g.bin_base - rs, s, kp, my, mz, wk, free_only);
+    }
+    if (h >= 0) {
+      chi2 += kf_update(s, my, mz, kp);
+      H[n++] = h;
+      atomicMin(&gs.claim[h], q);
+      P[0] = s.x; P[1] = s.y; P[2] = s.z; P[3] = s.sp; P[4] = s.tl; P[5] = s.qpt;
+      misses = 0;
+    } else if (++misses > kp.max_miss) {
+      break;
+    }
+  }
+  if (n > 0) {
+    P[6] = chi2;
+    P[7] = (float)(2 * n);
+    gs.nslot[q] = ns;
+  }
+  return n;
+}
+
+__global__ __launch_bounds__(kGridBlock) void k_prolong(DevEvent ev, KParams kp, Scratch sc,
+                                                        GlobalScratch gs,
+                                                        const int32_t* cluster_track) {
+  __shared__ float s_x[TPC_MAX_ROWS];
+  for (int i = threadIdx.x; i < kp.n_rows; i += kGridBlock) s_x[i] = kp.row_x[i];
+  __syncthreads();
+  if (event_bad(gs.counters)) return;
+  const int n_slots = gs.counters[C_SEEDS];
+  for (int q = blockIdx.x * kGridBlock + threadIdx.x; q < n_slots; q += gridDim.x * kGridBlock)
+    gs.n[q] = sc.kept[q >> 1] ? prolong_slot(q, ev, kp, sc, gs, cluster_track, s_x) : 0;
+}
+
+__global__ __launch_bounds__(kGridBlock) void k_pro_own(GlobalScratch gs) {
+  if (event_bad(gs.counters)) return;
+  const int n_slots = gs.counters[C_SEEDS];
+  for (int q = blockIdx.x * kGridBlock + threadIdx.x; q < n_slots; q += gridDim.x * kGridBlock) {
+    const int n = gs.n[q];
+    const int32_t* H = gs.hit + (size_t)q * kHitStride;
+    int o = 0;
+    for (int j = 0; j < n; ++j) o += gs.claim[H[j]] == q ? 1 : 0;
+    gs.owned[q] = o;
+  }
+}
+
+// One wave per slot: the owned clusters in the order met, state, meta.
+__global__ __launch_bounds__(kGridBlock) void k_pro_output(DevEvent ev, Scratch sc,
+                                                           GlobalScratch gs, ProOutputs po) {
+  if (__builtin_nontemporal_load(&gs.counters[C_ERR]) != 0) return;
+  const int n_slots = gs.counters[C_SEEDS];
+  const int lane = threadIdx.x & 63;
+  const int wpb = kGridBlock / 64;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  for (int q = blockIdx.x * wpb + (threadIdx.x >> 6); q < n_slots; q += gridDim.x * wpb) {
+    if (!gs.kept[q]) continue;  // wave-uniform
+    const int i = gs.idx[q];
+    int off = gs.off[q];
+    const int n = min(gs.n[q], kHitStride);
+    const int32_t* H = gs.hit + (size_t)q * kHitStride;
+    for (int j0 = 0; j0 < n; j0 += 64) {  // wave-uniform trip count
+      const int j = j0 + lane;
+      const int c = j < n ? H[j] : -1;
+      const bool mine = c >= 0 && gs.claim[c] == q;
+      const unsigned long long m = __ballot(mine);
+      if (mine) po.cluster[off + __popcll(m & lt)] = c;
+      off += __popcll(m);
+    }
+    if (lane < 8) {
+      po.par[(size_t)i * 8 + lane] = gs.par[(size_t)q * 8 + lane];
+    } else if (lane < 13) {
+      const int k = lane - 8;
+      int v;
+      if (k == 0) v = sc.trk_idx[q >> 1];
+      else if (k == 1) v = q & 1;
+      else if (k == 2) v = ev.sector_id[gs.nslot[q]];
+      else if (k == 3) v = gs.owned[q];
+      else v = gs.off[q];
+      po.meta[(size_t)i * 5 + k] = v;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ batches
 //
 // A batch is tracked as one event whose sector slots are those of all its
@@ -1699,6 +1974,45 @@ void scratch_carve(void* base, int64_t N, int64_t R, int64_t T, Scratch* sc) {
   sc->trk_idx = (int32_t*)take(sizeof(int32_t) * T);
   sc->trk_off = (int32_t*)take(sizeof(int32_t) * T);
   sc->span_sum = (int32_t*)take(sizeof(int32_t) * (2 * ((T + kSpan - 1) / kSpan) + 2));
+  sc->ends = nullptr;
+}
+
+size_t global_bytes(int64_t N, int64_t T) {
+  const int64_t Q = 2 * T;
+  size_t b = 0;
+  b += align_up(sizeof(float) * Q * kEndStride);
+  b += align_up(sizeof(int32_t) * C_COUNT);
+  b += align_up(sizeof(int32_t) * kLayoutSectors);
+  b += align_up(sizeof(int32_t) * (N > 0 ? N : 1));
+  b += align_up(sizeof(int32_t) * Q) * 2;
+  b += align_up(sizeof(float) * Q * 8);
+  b += align_up(sizeof(int32_t) * Q * kHitStride);
+  b += align_up(sizeof(int32_t) * Q) * 4;
+  b += align_up(sizeof(int32_t) * (2 * ((Q + kSpan - 1) / kSpan) + 2));
+  return b;
+}
+
+void global_carve(void* base, int64_t N, int64_t T, float** ends, GlobalScratch* gs) {
+  const int64_t Q = 2 * T;
+  char* p = (char*)base;
+  auto take = [&](size_t bytes) {
+    void* r = p;
+    p += align_up(bytes);
+    return r;
+  };
+  *ends = (float*)take(sizeof(float) * Q * kEndStride);
+  gs->counters = (int32_t*)take(sizeof(int32_t) * C_COUNT);
+  gs->p2s = (int32_t*)take(sizeof(int32_t) * kLayoutSectors);
+  gs->claim = (int32_t*)take(sizeof(int32_t) * (N > 0 ? N : 1));
+  gs->n = (int32_t*)take(sizeof(int32_t) * Q);
+  gs->nslot = (int32_t*)take(sizeof(int32_t) * Q);
+  gs->par = (float*)take(sizeof(float) * Q * 8);
+  gs->hit = (int32_t*)take(sizeof(int32_t) * Q * kHitStride);
+  gs->owned = (int32_t*)take(sizeof(int32_t) * Q);
+  gs->kept = (int32_t*)take(sizeof(int32_t) * Q);
+  gs->idx = (int32_t*)take(sizeof(int32_t) * Q);
+  gs->off = (int32_t*)take(sizeof(int32_t) * Q);
+  gs->span_sum = (int32_t*)take(sizeof(int32_t) * (2 * ((Q + kSpan - 1) / kSpan) + 2));
 }
 
 // Constructor: one lane per tracklet of the reservation, refills from the
@@ -1735,7 +2049,8 @@ static inline int wave_blocks(int64_t T) {
 
 const char* const kKernelNames[K_NUM] = {
     "k_zero", "k_grid", "k_nf", "k_evo", "k_scan_rows", "k_seed_write", "k_construct",
-    "k_own", "k_tl_reduce", "k_tl_scan", "k_output"};
+    "k_own", "k_tl_reduce", "k_tl_scan", "k_output", "k_pro_init", "k_prolong", "k_pro_own",
+    "k_pro_reduce", "k_pro_scan", "k_pro_output"};
 
 hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& sc,
                          const Outputs& out, int upto, hipStream_t st, const KernelTimer* tm,
@@ -1774,12 +2089,18 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
   if (kp.construct_schedule == 1) {
     const int nb = xcd_grid(kp.construct_blocks > 0 ? kp.construct_blocks
                                                     : rows_blocks(sc.cap_tl, ev.n_sectors));
-    hipLaunchKernelGGL(k_construct_rows, dim3(nb), dim3(64), 0, st, ev, kp, sc);
+    if (sc.ends)
+      hipLaunchKernelGGL(k_construct_rows<true>, dim3(nb), dim3(64), 0, st, ev, kp, sc);
+    else
+      hipLaunchKernelGGL(k_construct_rows<false>, dim3(nb), dim3(64), 0, st, ev, kp, sc);
   } else {
     const int nb = xcd_grid(kp.construct_blocks > 0
                                 ? kp.construct_blocks
                                 : tl_blocks(sc.cap_tl, min(max(kp.construct_lanes, 1), kTlBlock)));
-    hipLaunchKernelGGL(k_construct_lanes, dim3(nb), dim3(kTlBlock), 0, st, ev, kp, sc);
+    if (sc.ends)
+      hipLaunchKernelGGL(k_construct_lanes<true>, dim3(nb), dim3(kTlBlock), 0, st, ev, kp, sc);
+    else
+      hipLaunchKernelGGL(k_construct_lanes<false>, dim3(nb), dim3(kTlBlock), 0, st, ev, kp, sc);
   }
   post(K_CONSTRUCT);
   if (upto <= STAGE_TRACKLETS) return hipGetLastError();
@@ -1798,6 +2119,53 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
   pre(K_OUTPUT);
   hipLaunchKernelGGL(k_output, dim3(wb), dim3(kGridBlock), 0, st, ev, kp, sc, out);
   post(K_OUTPUT);
+  return hipGetLastError();
+}
+
+hipError_t enqueue_global(const DevEvent& ev, const KParams& kp, const Scratch& sc,
+                          const Outputs& out, const GlobalScratch& gs, const ProOutputs& po,
+                          hipStream_t st, const KernelTimer* tm) {
+  auto pre = [&](int k) {
+    if (tm && (tm->mask >> k & 1u)) (void)hipEventRecord(tm->ev[k][0], st);
+  };
+  auto post = [&](int k) {
+    if (tm && (tm->mask >> k & 1u)) (void)hipEventRecord(tm->ev[k][1], st);
+  };
+  const int64_t Q = 2 * (int64_t)sc.cap_tl;
+  const int cb = (int)std::min<int64_t>(std::max<int64_t>((ev.n_clusters + kGridBlock - 1) /
+                                                              kGridBlock, 1), 2048);
+  const int qb = (int)std::min<int64_t>(std::max<int64_t>((Q + kGridBlock - 1) / kGridBlock, 1),
+                                        65535);
+  pre(K_PRO_INIT);
+  hipLaunchKernelGGL(k_pro_init, dim3(cb), dim3(kGridBlock), 0, st, ev, sc, gs);
+  post(K_PRO_INIT);
+  pre(K_PROLONG);
+  hipLaunchKernelGGL(k_prolong, dim3(qb), dim3(kGridBlock), 0, st, ev, kp, sc, gs,
+                     (const int32_t*)out.cluster_track);
+  post(K_PROLONG);
+  pre(K_PRO_OWN);
+  hipLaunchKernelGGL(k_pro_own, dim3(qb), dim3(kGridBlock), 0, st, gs);
+  post(K_PRO_OWN);
+  // numbering of the slots that own clusters: the selection's scan over slots
+  Scratch ps = sc;
+  ps.counters = gs.counters;
+  ps.cap_tl = (int32_t)Q;
+  ps.owned = gs.owned;
+  ps.kept = gs.kept;
+  ps.trk_idx = gs.idx;
+  ps.trk_off = gs.off;
+  ps.span_sum = gs.span_sum;
+  const int spans = (int)((Q + kSpan - 1) / kSpan);
+  pre(K_PRO_REDUCE);
+  hipLaunchKernelGGL(k_tl_reduce, dim3(spans), dim3(kScanBlock), 0, st, ps, 1);
+  post(K_PRO_REDUCE);
+  pre(K_PRO_SCAN);
+  hipLaunchKernelGGL(k_tl_scan, dim3(spans), dim3(kScanBlock), 0, st, ps, 1, po.cap,
+                     po.cap_clusters);
+  post(K_PRO_SCAN);
+  pre(K_PRO_OUTPUT);
+  hipLaunchKernelGGL(k_pro_output, dim3(wave_blocks(Q)), dim3(kGridBlock), 0, st, ev, sc, gs, po);
+  post(K_PRO_OUTPUT);
   return hipGetLastError();
 }
 

@@ -37,7 +37,9 @@ struct tpc_ctx {
   size_t budget = 0;        // 0 = unlimited
   void* arena = nullptr;
   size_t arena_bytes = 0;
-  int32_t* h_counters = nullptr;  // pinned
+  int32_t* h_counters = nullptr;  // pinned: sector tracker's, then global tracking's counters
+  void* glob_arena = nullptr;     // global tracking scratch
+  size_t glob_bytes = 0;
   int64_t learned_tl = 0;   // tracklet reservation learned from overflows
   tpc::KernelTimer timer;   // HIP events around selected kernels
   bool timer_ready = false;
@@ -216,12 +218,39 @@ int ensure_arena(tpc_ctx* ctx, int64_t N, int64_t R, int64_t T, hipStream_t st) 
   return TPC_OK;
 }
 
+int ensure_glob(tpc_ctx* ctx, int64_t N, int64_t T, hipStream_t st) {
+  size_t need = global_bytes(N, T);
+  if (need <= ctx->glob_bytes) return TPC_OK;
+  size_t want = need + need / 4;
+  if (ctx->budget && ctx->arena_bytes + want > ctx->budget) want = need;
+  if (ctx->budget && ctx->arena_bytes + need > ctx->budget)
+    return fail(TPC_ERR_OOM, "global tracking scratch of %zu bytes exceeds the context budget",
+                need);
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  if (ctx->glob_arena) {
+    e = hipFree(ctx->glob_arena);
+    ctx->glob_arena = nullptr;
+    ctx->glob_bytes = 0;
+    if (e != hipSuccess) return hip_fail(e, "hipFree");
+  }
+  e = hipMalloc(&ctx->glob_arena, want);
+  if (e != hipSuccess) {
+    ctx->glob_arena = nullptr;
+    (void)hipGetLastError();
+    return fail(TPC_ERR_OOM, "hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+  }
+  ctx->glob_bytes = want;
+  return TPC_OK;
+}
+
 // Runs the kernels up to `upto`, reads the counters back, maps device error
-// bits to return codes.  On a tracklet overflow the reservation is raised and
+// bits to return codes.  With `po`, global tracking follows the whole path
+// and its counters land in h_counters[C_COUNT ..].  On a tracklet overflow the reservation is raised and
 // the event is run once more (results do not depend on the reservation).
 int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float bz,
               const tpc_params* p, const Outputs& out, int upto, hipStream_t st,
-              Scratch* sc_out) {
+              Scratch* sc_out, const ProOutputs* po = nullptr) {
   int rc = validate(ev, geo, p);
   if (rc) return rc;
   if (!std::isfinite(bz)) return fail(TPC_ERR_INVALID_ARG, "bz must be finite");
@@ -234,6 +263,11 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
   kp.construct_schedule = ctx->tuning.construct_schedule;
   kp.construct_lanes = lanes_per_wave(ctx->tuning.construct_lanes, N);
   kp.nf_dense = dense_rows(N, R);
+  {  // neighbouring sectors' centre lines are one sector width, 2 atan(tan_half), apart
+    const double w = 2.0 * std::atan((double)geo->tan_half_angle);
+    kp.rot_c = (float)std::cos(w);
+    kp.rot_s = (float)std::sin(w);
+  }
   const DevEvent dev = make_devevent(ev);
   int64_t T = default_tracklets(ctx, N, p);
   for (int attempt = 0; attempt < 2; ++attempt) {
@@ -241,9 +275,22 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
     if (rc) return rc;
     Scratch sc;
     scratch_carve(ctx->arena, N, R, T, &sc);
+    GlobalScratch gs{};
+    if (po) {
+      rc = ensure_glob(ctx, N, T, st);
+      if (rc) return rc;
+      global_carve(ctx->glob_arena, N, T, &sc.ends, &gs);
+    }
     const bool timed = ctx->timer.mask != 0;
     e = enqueue_event(dev, kp, sc, out, upto, st, timed ? &ctx->timer : nullptr);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    if (po) {
+      e = enqueue_global(dev, kp, sc, out, gs, *po, st, timed ? &ctx->timer : nullptr);
+      if (e != hipSuccess) return hip_fail(e, "kernel launch (global tracking)");
+      e = hipMemcpyAsync(ctx->h_counters + C_COUNT, gs.counters, sizeof(int32_t) * C_COUNT,
+                         hipMemcpyDeviceToHost, st);
+      if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(counters)");
+    }
     e = hipMemcpyAsync(ctx->h_counters, sc.counters, sizeof(int32_t) * C_COUNT,
                        hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(counters)");
@@ -265,7 +312,8 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
       continue;
     }
     if (timed) {
-      const int last = upto >= STAGE_ALL ? K_OUTPUT
+      const int last = po ? K_PRO_OUTPUT
+                       : upto >= STAGE_ALL ? K_OUTPUT
                        : upto >= STAGE_TRACKLETS ? K_CONSTRUCT
                        : upto >= STAGE_SEEDS ? K_SEED_WRITE : K_EVO;
       for (int k = 0; k <= last; ++k) {
@@ -603,7 +651,7 @@ int tpc_ctx_create(int device, size_t hbm_budget_bytes, tpc_ctx** out) {
   c->device = device;
   c->budget = hbm_budget_bytes;
   tpc_tuning_default(&c->tuning);
-  e = hipHostMalloc((void**)&c->h_counters, sizeof(int32_t) * C_COUNT, hipHostMallocDefault);
+  e = hipHostMalloc((void**)&c->h_counters, sizeof(int32_t) * 2 * C_COUNT, hipHostMallocDefault);
   if (e != hipSuccess) {
     delete c;
     return hip_fail(e, "hipHostMalloc");
@@ -695,6 +743,7 @@ void tpc_ctx_destroy(tpc_ctx* ctx) {
       for (int j = 0; j < 2; ++j) (void)hipEventDestroy(ctx->timer.ev[k][j]);
   if (ctx->arena) (void)hipFree(ctx->arena);
   if (ctx->batch_arena) (void)hipFree(ctx->batch_arena);
+  if (ctx->glob_arena) (void)hipFree(ctx->glob_arena);
   if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
   if (ctx->h_batch) (void)hipHostFree(ctx->h_batch);
   delete ctx;
@@ -716,6 +765,41 @@ int tpc_track_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, 
   if (c[C_ERR] & E_CAPACITY)
     return fail(TPC_ERR_CAPACITY, "need %d tracks / %d track clusters, have %d / %d",
                 c[C_TRACKS], c[C_TRACK_CLUSTERS], out->cap_tracks, out->cap_track_clusters);
+  return TPC_OK;
+}
+
+int tpc_track_event_global(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo,
+                           float bz_tesla, const tpc_params* params, tpc_tracks* out,
+                           tpc_prolongations* pro, void* hip_stream) {
+  if (!ctx) return fail(TPC_ERR_INVALID_ARG, "ctx is null");
+  int rc0 = check_outputs(ev, out);
+  if (rc0) return rc0;
+  if (!pro || !pro->n || !pro->n_clusters)
+    return fail(TPC_ERR_INVALID_ARG, "pro or its size pointers are null");
+  if (pro->cap < 0 || pro->cap_clusters < 0)
+    return fail(TPC_ERR_INVALID_ARG, "negative prolongation capacity");
+  if ((pro->cap > 0 && (!pro->par || !pro->meta)) || (pro->cap_clusters > 0 && !pro->cluster))
+    return fail(TPC_ERR_INVALID_ARG, "prolongation output array is null");
+  Outputs o{out->cap_tracks, out->cap_track_clusters, out->track_par, out->track_meta,
+            out->track_cluster, out->cluster_track};
+  ProOutputs po{pro->cap, pro->cap_clusters, pro->par, pro->meta, pro->cluster};
+  hipStream_t st = (hipStream_t)hip_stream;
+  int rc = run_event(ctx, ev, geo, bz_tesla, params, o, STAGE_ALL, st, nullptr, &po);
+  if (rc) return rc;
+  const int32_t* c = ctx->h_counters;
+  const int32_t* g = ctx->h_counters + C_COUNT;
+  *out->n_tracks = c[C_TRACKS];
+  *out->n_track_clusters = c[C_TRACK_CLUSTERS];
+  *pro->n = 0;
+  *pro->n_clusters = 0;
+  if (c[C_ERR] & E_CAPACITY)
+    return fail(TPC_ERR_CAPACITY, "need %d tracks / %d track clusters, have %d / %d",
+                c[C_TRACKS], c[C_TRACK_CLUSTERS], out->cap_tracks, out->cap_track_clusters);
+  *pro->n = g[C_TRACKS];
+  *pro->n_clusters = g[C_TRACK_CLUSTERS];
+  if (g[C_ERR] & E_CAPACITY)
+    return fail(TPC_ERR_CAPACITY, "need %d prolongations / %d clusters, have %d / %d",
+                g[C_TRACKS], g[C_TRACK_CLUSTERS], pro->cap, pro->cap_clusters);
   return TPC_OK;
 }
 

@@ -136,3 +136,51 @@ def alpha_value(alpha: float) -> float:
     length alone and equal lengths tie, to be broken by the seed id: the
     longest-track rule of section 3.1."""
     return 1.0e9 if math.isinf(alpha) else float(alpha)
+
+
+def prolongation_report(e: synth.Event, res: dict, pro: dict, min_clusters: int = 30,
+                        purity: float = 0.9) -> dict:
+    """What global tracking (section 5) adds to one event's tracks.
+
+    A short piece is a particle's clusters in one sector slot when they are
+    fewer than `min_clusters` (so no sector track can hold them) and the
+    particle has a found (non-fake) sector track in another slot.  Reported:
+    the clusters of short pieces, the fraction of them that a prolongation of
+    one of the particle's tracks collected, and the purity of the prolongation
+    clusters (the fraction that belong to the particle of their track).
+    """
+    mc = np.asarray(e.mc_track)
+    slot = e.row_of() // synth.N_ROWS
+    meta = np.asarray(res["track_meta"])
+    tcl = np.asarray(res["track_cluster"])
+    label = np.full(int(res["n_tracks"]), -1, np.int64)
+    for t in range(int(res["n_tracks"])):
+        cl = tcl[meta[t, 2]:meta[t, 2] + meta[t, 1]]
+        lab, c = np.unique(mc[cl], return_counts=True)
+        j = int(np.argmax(c))
+        if lab[j] >= 0 and c[j] >= purity * cl.shape[0]:
+            label[t] = lab[j]
+    found = set(label[label >= 0].tolist())
+    sig = mc >= 0
+    key = mc[sig].astype(np.int64) * int(e.sector_id.shape[0]) + slot[sig]
+    keys, cnt = np.unique(key, return_counts=True)
+    short = {int(k) for k, n in zip(keys, cnt)
+             if n < min_clusters and int(k) // int(e.sector_id.shape[0]) in found}
+    in_short = np.zeros(mc.shape[0], bool)
+    idx = np.nonzero(sig)[0]
+    in_short[idx] = np.isin(key, np.fromiter(short, np.int64, len(short)))
+    pm = np.asarray(pro["meta"])
+    pcl = np.asarray(pro["cluster"])
+    got = right = 0
+    total_pro = int(pcl.shape[0])
+    for k in range(int(pro["n"])):
+        t, _, _, n, first = (int(v) for v in pm[k])
+        cl = pcl[first:first + n]
+        ok = mc[cl] == label[t]
+        right += int(np.sum(ok & (label[t] >= 0)))
+        got += int(np.sum(ok & in_short[cl] & (label[t] >= 0)))
+    n_short = int(np.sum(in_short))
+    return dict(prolongations=int(pro["n"]), prolongation_clusters=total_pro,
+                short_piece_clusters=n_short,
+                short_piece_recovered=got / max(1, n_short),
+                prolongation_purity=right / max(1, total_pro))

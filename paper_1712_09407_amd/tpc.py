@@ -70,8 +70,14 @@ class Tracks(C.Structure):
                 ("track_cluster", C.c_void_p), ("cluster_track", C.c_void_p)]
 
 
+class Prolongations(C.Structure):
+    _fields_ = [("cap", C.c_int32), ("cap_clusters", C.c_int32), ("n", C.POINTER(C.c_int32)),
+                ("n_clusters", C.POINTER(C.c_int32)), ("par", C.c_void_p), ("meta", C.c_void_p),
+                ("cluster", C.c_void_p)]
+
+
 EXPORTS = ["tpc_params_default", "tpc_validate", "tpc_ctx_create", "tpc_ctx_destroy",
-           "tpc_track_event", "tpc_track_batch", "tpc_debug_links", "tpc_debug_tracklets", "tpc_last_error",
+           "tpc_track_event", "tpc_track_event_global", "tpc_track_batch", "tpc_debug_links", "tpc_debug_tracklets", "tpc_last_error",
            "tpc_kernel_count", "tpc_kernel_name", "tpc_ctx_set_timing", "tpc_ctx_get_stats",
            "tpc_ctx_reset_stats", "tpc_tuning_default", "tpc_ctx_set_tuning",
            "tpc_ctx_graph_launches", "tpc_server_config_default", "tpc_server_create",
@@ -92,6 +98,8 @@ def _load():
     L.tpc_ctx_destroy.restype = None
     L.tpc_track_event.argtypes = [C.c_void_p, P(Event), P(Geometry), C.c_float, P(Params),
                                   P(Tracks), C.c_void_p]
+    L.tpc_track_event_global.argtypes = [C.c_void_p, P(Event), P(Geometry), C.c_float,
+                                         P(Params), P(Tracks), P(Prolongations), C.c_void_p]
     L.tpc_track_batch.argtypes = [C.c_void_p, P(Event), C.c_int, P(Geometry), C.c_float,
                                   P(Params), P(Tracks), C.c_void_p]
     L.tpc_debug_links.argtypes = [C.c_void_p, P(Event), P(Geometry), P(Params), C.c_void_p,
@@ -244,6 +252,52 @@ class Tracker:
                     track_par=out["track_par"][:nt.value], track_meta=out["track_meta"][:nt.value],
                     track_cluster=out["track_cluster"][:nc.value],
                     cluster_track=out["cluster_track"][:n])
+
+    def track_event_global(self, ev: DeviceEvent, geo: Geometry, bz: float,
+                           params: Params = None, cap_tracks: int = None,
+                           cap_track_clusters: int = None, cap_pro: int = None,
+                           cap_pro_clusters: int = None, stream=None):
+        """The whole path, then global tracking (section 5).  Returns the
+        track dict of track_event and a dict of the prolongations (n,
+        n_clusters, par [n][8], meta [n][5], cluster), device tensors."""
+        import torch
+        n = ev.n_clusters
+        dev = ev.y.device
+        auto = all(c is None for c in (cap_tracks, cap_track_clusters, cap_pro, cap_pro_clusters))
+        ct = cap_tracks if cap_tracks is not None else max(16, n // 40)
+        cc = cap_track_clusters if cap_track_clusters is not None else max(16, n)
+        cp = cap_pro if cap_pro is not None else max(16, ct)
+        cpc = cap_pro_clusters if cap_pro_clusters is not None else max(16, n // 8)
+        f32 = dict(dtype=torch.float32, device=dev)
+        i32 = dict(dtype=torch.int32, device=dev)
+        out = dict(track_par=torch.empty((ct, 8), **f32), track_meta=torch.empty((ct, 4), **i32),
+                   track_cluster=torch.empty(cc, **i32),
+                   cluster_track=torch.empty(max(n, 1), **i32))
+        po = dict(par=torch.empty((max(cp, 1), 8), **f32), meta=torch.empty((max(cp, 1), 5), **i32),
+                  cluster=torch.empty(max(cpc, 1), **i32))
+        nt, nc, npr, npc = C.c_int32(0), C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        tr = Tracks(ct, cc, C.pointer(nt), C.pointer(nc), out["track_par"].data_ptr(),
+                    out["track_meta"].data_ptr(), out["track_cluster"].data_ptr(),
+                    out["cluster_track"].data_ptr())
+        pr = Prolongations(cp, cpc, C.pointer(npr), C.pointer(npc), po["par"].data_ptr(),
+                           po["meta"].data_ptr(), po["cluster"].data_ptr())
+        e = ev.cstruct()
+        rc = lib.tpc_track_event_global(self._h, C.byref(e), C.byref(geo), float(bz),
+                                        C.byref(params or default_params()), C.byref(tr),
+                                        C.byref(pr), _stream_handle(stream))
+        if rc == TPC_ERR_CAPACITY and auto:
+            return self.track_event_global(ev, geo, bz, params, max(ct, nt.value + 16),
+                                           max(cc, nc.value + 16), max(cp, npr.value + 16),
+                                           max(cpc, npc.value + 16), stream)
+        _check(rc)
+        tracks = dict(n_tracks=nt.value, n_track_clusters=nc.value,
+                      track_par=out["track_par"][:nt.value],
+                      track_meta=out["track_meta"][:nt.value],
+                      track_cluster=out["track_cluster"][:nc.value],
+                      cluster_track=out["cluster_track"][:n])
+        pro = dict(n=npr.value, n_clusters=npc.value, par=po["par"][:npr.value],
+                   meta=po["meta"][:npr.value], cluster=po["cluster"][:npc.value])
+        return tracks, pro
 
     def set_tuning(self, **kw):
         """Speed knobs (results never change): use_graph, construct_blocks,

@@ -138,6 +138,18 @@ def test_null_context_is_an_error_not_a_crash():
     assert rc == tpc.TPC_ERR_INVALID_ARG
 
 
+def test_global_entry_rejects_null_arguments():
+    tpc, geo, ev = _valid_host_structs()
+    nt, nc = C.c_int32(0), C.c_int32(0)
+    tr = tpc.Tracks(0, 0, C.pointer(nt), C.pointer(nc), None, None, None, None)
+    n, m = C.c_int32(0), C.c_int32(0)
+    pr = tpc.Prolongations(0, 0, C.pointer(n), C.pointer(m), None, None, None)
+    rc = tpc.lib.tpc_track_event_global(None, C.byref(ev), C.byref(geo), 0.5,
+                                        C.byref(tpc.default_params()), C.byref(tr), C.byref(pr),
+                                        None)
+    assert rc == tpc.TPC_ERR_INVALID_ARG
+
+
 def test_oracle_library_exports(orc):
     out = subprocess.run(["nm", "-D", "--defined-only", orc.LIB], capture_output=True, text=True,
                          check=True).stdout
@@ -163,7 +175,7 @@ def test_oracle_and_gpu_library_share_nothing():
 STRUCTS = {  # C type name -> ctypes mirror in the binding
     "tpc_geometry": "Geometry", "tpc_event": "Event", "tpc_params": "Params",
     "tpc_tracks": "Tracks", "tpc_tuning": "Tuning", "tpc_server_config": "ServerConfig",
-    "tpc_server_done": "ServerDone"}
+    "tpc_server_done": "ServerDone", "tpc_prolongations": "Prolongations"}
 
 
 def test_struct_layouts_match_the_header(tmp_path):

@@ -1,0 +1,173 @@
+"""Global tracking (section 5) through the C ABI against the FP64 oracle.
+
+The sector tracks of tpc_track_event_global are bitwise those of
+tpc_track_event.  Prolongations are compared per (seed id of the track, end):
+on noiseless tracks that cross a sector edge the two sides must give the
+same prolongations with the same clusters; on central events the clusters of
+the prolongations must agree to >= 99.9% both ways (a decision on an FP32
+chi^2 near the gate, or a near-tie of two candidates, may differ from the
+FP64 oracle, and a changed pick changes the rest of that prolongation), and
+the parameters of prolongations with identical clusters within 1e-3
+relative (absolute for |value| < 1), chi2 within 1e-2, when both sides built
+the track from the same seed (FP32 and FP64 may keep different seeds among tracklets with the
+same clusters; the outer end state then comes from another outward filter).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from conftest import event_dict, f32
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import concordance  # noqa: E402
+from paper_1712_09407_amd import synth, tpc  # noqa: E402
+
+THREADS = min(16, os.cpu_count() or 1)
+GEO_T = (synth.ROW_X, synth.TAN_HALF, synth.Z_MAX)
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def tracker():
+    t = tpc.Tracker(0)
+    yield t
+    t.close()
+
+
+@pytest.fixture(scope="module")
+def geo():
+    return tpc.make_geometry(*GEO_T)
+
+
+def params_pair(orc, sigma=0.1):
+    g = tpc.default_params(sigma_y=sigma, sigma_z=sigma)
+    o = orc.default_params(**{k: f32(getattr(g, k)) if isinstance(getattr(g, k), float)
+                              else getattr(g, k) for k, _ in orc.Params._fields_})
+    return g, o
+
+
+def dev_event(e, sector_id=None):
+    sid = e.sector_id if sector_id is None else sector_id
+    return tpc.DeviceEvent.from_host(e.y, e.z, e.row_offsets, sid, device="cuda:0")
+
+
+def run_both(orc, tracker, geo, e, sector_id=None):
+    # noiseless events are fitted with the default resolution
+    pg, po = params_pair(orc, e.config.sigma if e.config.sigma > 0 else 0.1)
+    tr, pr = tracker.track_event_global(dev_event(e, sector_id), geo, e.bz, pg)
+    tr, pr = tpc.to_numpy(tr), tpc.to_numpy(pr)
+    ev = event_dict(e)
+    if sector_id is not None:
+        ev["sector_id"] = sector_id
+    tro, pro = orc.track_event_global(ev, GEO_T, e.bz, po, n_threads=THREADS)
+    return (tr, pr), (tro, pro)
+
+
+def par_close(a, b, tol=1e-3):
+    return np.all(np.abs(a - b) <= tol * np.maximum(1.0, np.abs(b)))
+
+
+def crossing_event(seed, phi_range):
+    cfg = synth.EventConfig(n_tracks=8, sectors=tuple(range(18)), phi_range_deg=phi_range,
+                            sigma=0.0, noise_frac=0.0, pt_min=1.9, pt_mean=1e-9, eta_max=0.5)
+    return synth.make_event(cfg, seed)
+
+
+@pytest.mark.parametrize("phi_range", [(14.5, 15.5), (17.2, 18.2)])
+def test_crossing_tracks_match_the_oracle(orc, tracker, geo, phi_range):
+    """Noiseless tracks that cross the 20-degree edge near the outer (inner)
+    rows: the same prolongations, the same clusters, parameters within 1e-3."""
+    n = 0
+    for seed in range(100, 108):
+        e = crossing_event(seed, phi_range)
+        say("crossing", phi_range, seed, e.n_clusters)
+        gpu, ref = run_both(orc, tracker, geo, e)
+        rep = concordance.compare_prolongations(*ref, *gpu, e.n_clusters)
+        assert rep["n_a"] == rep["n_b"] == rep["identical"], rep
+        assert rep["par_fail"] == 0, rep
+        n += rep["n_a"]
+    assert n >= 6
+
+
+@pytest.mark.parametrize("seed", [2, 3])
+def test_central_event_prolongations(orc, tracker, geo, seed):
+    e = synth.make_preset("c2_central", seed)
+    say("central global", seed, e.n_clusters)
+    gpu, ref = run_both(orc, tracker, geo, e)
+    rep = concordance.compare_prolongations(*ref, *gpu, e.n_clusters)
+    say(rep)
+    assert rep["n_a"] > 100
+    assert rep["cluster_concordance_ab"] >= 0.999 and rep["cluster_concordance_ba"] >= 0.999
+    assert rep["par_compared"] >= 0.7 * rep["n_a"]
+    assert rep["par_fail"] <= max(2, 2e-3 * rep["par_compared"])
+    # output invariants of the GPU side
+    tr, pr = gpu
+    cl = pr["cluster"]
+    assert np.unique(cl).size == cl.size                       # each cluster once
+    assert np.all(tr["cluster_track"][cl] < 0)                 # never a sector track's
+    meta = pr["meta"]
+    assert np.all(np.diff(meta[:, 0] * 2 + meta[:, 1]) > 0)    # (track, end) order
+    assert np.array_equal(meta[:, 4], np.concatenate([[0], np.cumsum(meta[:-1, 3])]))
+    assert np.all(meta[:, 3] >= 1) and np.all(pr["par"][:, 7] >= 2 * meta[:, 3])
+
+
+def test_sector_tracks_are_those_of_the_plain_path(tracker, geo):
+    e = synth.make_preset("c2_central", 2)
+    dev = dev_event(e)
+    a = tpc.to_numpy(tracker.track_event(dev, geo, e.bz))
+    b, pr = tracker.track_event_global(dev, geo, e.bz)
+    b = tpc.to_numpy(b)
+    for k in ("track_par", "track_meta", "track_cluster", "cluster_track"):
+        assert np.array_equal(a[k].view(np.uint8), b[k].view(np.uint8)), k
+    assert pr["n"] > 0
+    # and the prolongations are deterministic
+    b2, pr2 = tracker.track_event_global(dev, geo, e.bz)
+    for k in ("par", "meta", "cluster"):
+        assert np.array_equal(pr[k].cpu().numpy(), pr2[k].cpu().numpy()), k
+
+
+def test_no_neighbour_no_prolongation(orc, tracker, geo):
+    """One sector slot; and a full event whose sector ids are outside the
+    2 x 18 layout: there is no neighbour to enter."""
+    e = synth.make_preset("c1_sector", 1)
+    gpu, ref = run_both(orc, tracker, geo, e)
+    assert gpu[0]["n_tracks"] > 50 and gpu[1]["n"] == 0 and ref[1]["n"] == 0
+    e = synth.make_event(synth.EventConfig(n_tracks=800), 12)
+    gpu, ref = run_both(orc, tracker, geo, e, sector_id=np.asarray(e.sector_id) + 100)
+    assert gpu[0]["n_tracks"] > 100 and gpu[1]["n"] == 0 and ref[1]["n"] == 0
+    gpu, ref = run_both(orc, tracker, geo, e)
+    assert gpu[1]["n"] > 0
+    assert concordance.compare_prolongations(*ref, *gpu, e.n_clusters)["cluster_concordance_ab"] \
+        >= 0.999
+
+
+def test_empty_event(tracker, geo):
+    ro = np.zeros(36 * 159 + 1, np.int32)
+    dev = tpc.DeviceEvent.from_host(np.zeros(0), np.zeros(0), ro, np.arange(36))
+    tr, pr = tracker.track_event_global(dev, geo, 0.5)
+    assert tr["n_tracks"] == 0 and pr["n"] == 0 and pr["n_clusters"] == 0
+
+
+def test_capacity_error_reports_sizes(tracker, geo):
+    e = synth.make_event(synth.EventConfig(n_tracks=1500), 8)
+    dev = dev_event(e)
+    tr, pr = tracker.track_event_global(dev, geo, e.bz)
+    assert pr["n"] > 2
+    with pytest.raises(tpc.TpcError) as ex:
+        tracker.track_event_global(dev, geo, e.bz, cap_tracks=tr["n_tracks"],
+                                   cap_track_clusters=tr["n_track_clusters"], cap_pro=1,
+                                   cap_pro_clusters=10**6)
+    assert ex.value.code == tpc.TPC_ERR_CAPACITY
+    assert f"need {pr['n']} prolongations / {pr['n_clusters']} clusters" in str(ex.value)
+    # the context still works afterwards, with the same result
+    tr2, pr2 = tracker.track_event_global(dev, geo, e.bz)
+    assert np.array_equal(pr["cluster"].cpu().numpy(), pr2["cluster"].cpu().numpy())

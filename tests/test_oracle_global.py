@@ -129,3 +129,27 @@ def test_prolonged_clusters_are_free_and_unique(orc, geo):
     purity = np.mean([np.all(e.mc_track[cl[f:f + n]] == label(tc[tm[t, 2]:tm[t, 2] + tm[t, 1]]))
                       for t, _, _, n, f in meta])
     assert purity > 0.9
+
+
+def test_prolongation_comparison_detects_differences(orc, geo):
+    from oracle import concordance
+    e = synth.make_event(synth.EventConfig(n_tracks=1500), 8)
+    tr, pr = orc.track_event_global(event_dict(e), geo, e.bz, n_threads=4)
+    rep = concordance.compare_prolongations(tr, pr, tr, pr, e.n_clusters)
+    assert rep["cluster_concordance_ab"] == rep["cluster_concordance_ba"] == 1.0
+    assert rep["identical"] == rep["n_a"] == pr["n"] == rep["par_compared"]
+    assert rep["par_fail"] == 0 and rep["other_seed"] == 0
+    # B loses the last cluster of its first prolongation and shifts another's q/pT
+    b = {k: (v.copy() if hasattr(v, "copy") else v) for k, v in pr.items()}
+    m = b["meta"]
+    keep = np.ones(b["cluster"].shape[0], bool)
+    keep[m[0, 4] + m[0, 3] - 1] = False
+    b["cluster"] = b["cluster"][keep]
+    m[0, 3] -= 1
+    m[1:, 4] -= 1
+    b["n_clusters"] -= 1
+    b["par"][1, 5] *= 1.01
+    rep = concordance.compare_prolongations(tr, pr, tr, b, e.n_clusters)
+    assert rep["cluster_concordance_ab"] == pytest.approx(1 - 1 / pr["n_clusters"])
+    assert rep["cluster_concordance_ba"] == 1.0
+    assert rep["identical"] == pr["n"] - 1 and rep["par_fail"] == 1

@@ -110,3 +110,38 @@ def test_alpha_infinity_is_the_longest_track_rule():
             w = np.float32(n) * (a - np.float32(chi))
             assert w == np.float32(n) * a     # the fit quality no longer counts
     assert np.float32(31) * a > np.float32(30) * a
+
+
+def test_prolongation_report_on_known_answers(event):
+    """Perfect sector tracks plus prolongations that carry exactly the short
+    pieces of their particles recover all of them at purity 1; no
+    prolongations recover none; a prolongation of another particle's clusters
+    has purity 0."""
+    res = truth_tracks(event)
+    slot = event.row_of() // synth.N_ROWS
+    mc = event.mc_track
+    lab = {int(mc[res["track_cluster"][m[2]]]): t for t, m in enumerate(res["track_meta"])}
+    meta, cl = [], []
+    for p, t in sorted(lab.items()):
+        for s in np.unique(slot[mc == p]):
+            c = np.nonzero((mc == p) & (slot == s))[0]
+            if c.shape[0] < 30:
+                meta.append([t, 1, int(event.sector_id[s]), c.shape[0], len(cl)])
+                cl.extend(c.tolist())
+    order = np.argsort([m[0] * 2 + m[1] for m in meta], kind="stable")
+    pro = dict(n=len(meta), meta=np.array(meta, np.int32)[order], cluster=np.array(cl, np.int32))
+    # re-base the offsets after sorting
+    pro["meta"][:, 4] = np.concatenate([[0], np.cumsum(pro["meta"][:-1, 3])])
+    pro["cluster"] = np.concatenate([np.array(cl, np.int32)[m[4]:m[4] + m[3]]
+                                     for m in np.array(meta, np.int32)[order]])
+    r = quality.prolongation_report(event, res, pro)
+    assert r["short_piece_clusters"] == len(cl) > 20
+    assert r["short_piece_recovered"] == 1.0 and r["prolongation_purity"] == 1.0
+    none = dict(n=0, meta=np.zeros((0, 5), np.int32), cluster=np.zeros(0, np.int32))
+    assert quality.prolongation_report(event, res, none)["short_piece_recovered"] == 0.0
+    # attach track 0's prolongation to track 1 instead: wrong particle
+    wrong = dict(pro)
+    wrong["meta"] = pro["meta"].copy()
+    wrong["meta"][:, 0] = (pro["meta"][:, 0] + 1) % res["n_tracks"]
+    r = quality.prolongation_report(event, res, wrong)
+    assert r["prolongation_purity"] == 0.0 and r["short_piece_recovered"] == 0.0
