@@ -64,6 +64,13 @@ class Prolongations(C.Structure):
                 ("meta", C.POINTER(C.c_int32)), ("cluster", C.POINTER(C.c_int32))]
 
 
+class Merged(C.Structure):
+    _fields_ = [("cap", C.c_int32), ("cap_clusters", C.c_int32), ("n", C.c_int32),
+                ("n_clusters", C.c_int32), ("par", C.POINTER(C.c_double)),
+                ("meta", C.POINTER(C.c_int32)), ("cluster", C.POINTER(C.c_int32)),
+                ("track_merged", C.POINTER(C.c_int32))]
+
+
 class Tracklets(C.Structure):
     _fields_ = [("hits", C.POINTER(C.c_int32)), ("row_lo", C.POINTER(C.c_int32)),
                 ("row_hi", C.POINTER(C.c_int32)), ("n", C.POINTER(C.c_int32)),
@@ -86,6 +93,11 @@ def lib():
                                       C.c_int]
         L.orc_track_event_global.argtypes = [P(EventS), P(Geometry), C.c_double, P(Params),
                                              P(Tracks), P(Prolongations), C.c_int]
+        L.orc_track_event_merged.argtypes = [P(EventS), P(Geometry), C.c_double, P(Params),
+                                             C.c_double, P(Tracks), P(Prolongations), P(Merged),
+                                             C.c_int]
+        L.orc_refit.argtypes = [P(EventS), P(Geometry), C.c_double, P(Params), C.c_int32,
+                                P(C.c_int32), P(C.c_int32), P(C.c_double), P(C.c_int32)]
         L.orc_rotate.argtypes = [C.c_double, P(C.c_double), P(C.c_double), C.c_double,
                                  C.c_double, P(C.c_double), P(C.c_double), P(C.c_double)]
         L.orc_neighbours.argtypes = [P(EventS), P(Geometry), P(Params), P(C.c_int32),
@@ -289,6 +301,86 @@ def track_event_global(ev: dict, geo, bz: float, params: Params | None = None,
                     cluster=pcl[:npc].copy())
         return tracks, prol
     raise RuntimeError("capacity retry failed")
+
+
+MERGE_CHI2 = 25.0   # joins: chi^2(5) <= 25, a 1e-4 tail for the same particle
+
+
+def track_event_merged(ev: dict, geo, bz: float, params: Params | None = None,
+                       merge_chi2: float = MERGE_CHI2, use_global: bool = True,
+                       n_threads: int = 1):
+    """track_event (and, with use_global, the prolongations), then the track
+    merger with refit.  Returns (tracks, prolongations or None, merged):
+    merged has n, par [n][8] (x, y, z, sinphi, tanl, qpt at the innermost
+    fitted cluster in the frame of sector meta[:, 0], chi2, ndf; ndf 0 =
+    refit failed), meta [n][5] (frame sector_id, tracks joined, n_clusters,
+    first, first track), cluster (path order), track_merged [n_tracks]."""
+    cx = _ctx(ev, geo)
+    prm = params or default_params()
+    n = int(cx.y.shape[0])
+    cap_t, cap_c = max(1, n // 8), max(1, n)
+    cap_p, cap_pc = 2 * cap_t + 1, max(1, n)
+    cap_m, cap_mc = cap_t, max(1, n)
+    for _ in range(3):
+        par = np.zeros((cap_t, 8), np.float64)
+        meta = np.zeros((cap_t, 4), np.int32)
+        tcl = np.zeros(cap_c, np.int32)
+        ctr = np.full(max(n, 1), -1, np.int32)
+        ppar = np.zeros((cap_p, 8), np.float64)
+        pmeta = np.zeros((cap_p, 5), np.int32)
+        pcl = np.zeros(cap_pc, np.int32)
+        mpar = np.zeros((cap_m, 8), np.float64)
+        mmeta = np.zeros((cap_m, 5), np.int32)
+        mcl = np.zeros(cap_mc, np.int32)
+        tm = np.full(cap_t, -1, np.int32)
+        out = Tracks(cap_t, cap_c, 0, 0, _p(par, C.c_double), _p(meta, C.c_int32),
+                     _p(tcl, C.c_int32), _p(ctr, C.c_int32))
+        pro = Prolongations(cap_p, cap_pc, 0, 0, _p(ppar, C.c_double), _p(pmeta, C.c_int32),
+                            _p(pcl, C.c_int32))
+        mrg = Merged(cap_m, cap_mc, 0, 0, _p(mpar, C.c_double), _p(mmeta, C.c_int32),
+                     _p(mcl, C.c_int32), _p(tm, C.c_int32))
+        rc = lib().orc_track_event_merged(C.byref(cx.ev), C.byref(cx.geo), float(bz),
+                                          C.byref(prm), float(merge_chi2), C.byref(out),
+                                          C.byref(pro) if use_global else None, C.byref(mrg),
+                                          int(n_threads))
+        if rc == 1:
+            cap_t, cap_c = max(cap_t, out.n_tracks), max(cap_c, out.n_track_clusters)
+            cap_p, cap_pc = max(cap_p, pro.n), max(cap_pc, pro.n_clusters)
+            cap_m, cap_mc = max(cap_m, mrg.n, out.n_tracks), max(cap_mc, mrg.n_clusters)
+            continue
+        if rc != 0:
+            raise RuntimeError(f"orc_track_event_merged failed: {rc}")
+        nt, nc = out.n_tracks, out.n_track_clusters
+        tracks = dict(n_tracks=nt, n_track_clusters=nc, track_par=par[:nt].copy(),
+                      track_meta=meta[:nt].copy(), track_cluster=tcl[:nc].copy(),
+                      cluster_track=ctr[:n].copy())
+        prol = dict(n=pro.n, n_clusters=pro.n_clusters, par=ppar[:pro.n].copy(),
+                    meta=pmeta[:pro.n].copy(), cluster=pcl[:pro.n_clusters].copy()) \
+            if use_global else None
+        merged = dict(n=mrg.n, n_clusters=mrg.n_clusters, par=mpar[:mrg.n].copy(),
+                      meta=mmeta[:mrg.n].copy(), cluster=mcl[:mrg.n_clusters].copy(),
+                      track_merged=tm[:nt].copy())
+        return tracks, prol, merged
+    raise RuntimeError("capacity retry failed")
+
+
+def refit(ev: dict, geo, bz: float, lists, params: Params | None = None):
+    """The merger's refit of cluster lists (each in path order).  Returns
+    (par [n][8], frame sector_id [n], -1 = failed)."""
+    cx = _ctx(ev, geo)
+    lens = [len(l) for l in lists]
+    off = np.zeros(len(lists) + 1, np.int32)
+    np.cumsum(lens, out=off[1:])
+    cl = np.ascontiguousarray(np.concatenate([np.asarray(l, np.int32) for l in lists])
+                              if lists else np.zeros(1, np.int32), np.int32)
+    par = np.zeros((max(1, len(lists)), 8), np.float64)
+    fr = np.zeros(max(1, len(lists)), np.int32)
+    rc = lib().orc_refit(C.byref(cx.ev), C.byref(cx.geo), float(bz),
+                         C.byref(params or default_params()), len(lists), _p(off, C.c_int32),
+                         _p(cl, C.c_int32), _p(par, C.c_double), _p(fr, C.c_int32))
+    if rc:
+        raise RuntimeError("orc_refit failed")
+    return par[:len(lists)], fr[:len(lists)]
 
 
 def rotate(x: float, state, cov, d: float, bz: float):

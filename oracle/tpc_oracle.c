@@ -804,8 +804,9 @@ static int check_event(const orc_event* ev, const orc_geometry* geo) {
  *     edge; reaching the first/last row, |sin phi| > max_sinphi or
  *     |z| > z_max ends it without prolongation;
  *   - the neighbour is the sector on that side: same z half (section 1:
- *     2 x 18 sectors), sector index +1 (mod 18) for y > 0, -1 for y < 0, if
- *     the event holds it; its centre line is one sector width (2 atan of
+ *     2 x 18 sectors, ids 0-17 and 18-35), sector index +1 (mod 18) for
+ *     y > 0, -1 for y < 0, if the event holds it (its first slot with that
+ *     id); a slot whose id is outside 0-35 is not prolonged; its centre line is one sector width (2 atan of
  *     tan_half) away;
  *   - the state at the last row inside the own sector is rotated into the
  *     neighbour's frame (krotate), so that the neighbour's rows crossed
@@ -909,6 +910,7 @@ static int prolong_one(const orc_event* ev, const orc_geometry* geo, double bz,
   if (exit_row < 0) return 0;
   /* 2. the neighbour on that side */
   const int phys = ev->sector_id[slot];
+  if (phys < 0 || phys >= 36) return 0;  /* not a sector of the 2 x 18 layout */
   const int half = phys / 18, idx = phys % 18;
   const int up = s.p[0] > 0.0;
   s = last;
@@ -1034,9 +1036,14 @@ static int global_tracking(const orc_event* ev, const orc_geometry* geo, double 
   return status;
 }
 
+static int locate(const orc_event* ev, const orc_geometry* geo, int32_t c, int* row);
+static int merge_tracks(const orc_event* ev, const orc_geometry* geo, double bz,
+                        const orc_params* prm, double cut, const sector_out* outs,
+                        const orc_tracks* trk, const orc_prolongations* pro, orc_merged* mrg);
+
 static int track_all(const orc_event* ev, const orc_geometry* geo, double bz,
                      const orc_params* prm, orc_tracks* out, orc_prolongations* pro,
-                     int n_threads) {
+                     orc_merged* mrg, double merge_chi2, int n_threads) {
   if (check_event(ev, geo) || !prm || !out) return -1;
   int64_t N = ev->n_clusters;
   size_t nb = sizeof(int32_t) * (size_t)(N > 0 ? N : 1);
@@ -1082,6 +1089,8 @@ static int track_all(const orc_event* ev, const orc_geometry* geo, double bz,
       ic += so->n_clusters;
     }
     if (pro) status = global_tracking(ev, geo, bz, prm, P.outs, out, pro);
+    if (mrg && status == 0)
+      status = merge_tracks(ev, geo, bz, prm, merge_chi2, P.outs, out, pro, mrg);
   }
   for (int s = 0; s < ev->n_sectors; ++s) {
     free(P.outs[s].par); free(P.outs[s].meta); free(P.outs[s].clusters);
@@ -1093,14 +1102,21 @@ static int track_all(const orc_event* ev, const orc_geometry* geo, double bz,
 
 int orc_track_event(const orc_event* ev, const orc_geometry* geo, double bz,
                     const orc_params* prm, orc_tracks* out, int n_threads) {
-  return track_all(ev, geo, bz, prm, out, NULL, n_threads);
+  return track_all(ev, geo, bz, prm, out, NULL, NULL, 0.0, n_threads);
 }
 
 int orc_track_event_global(const orc_event* ev, const orc_geometry* geo, double bz,
                            const orc_params* prm, orc_tracks* out, orc_prolongations* pro,
                            int n_threads) {
   if (!pro) return -1;
-  return track_all(ev, geo, bz, prm, out, pro, n_threads);
+  return track_all(ev, geo, bz, prm, out, pro, NULL, 0.0, n_threads);
+}
+
+int orc_track_event_merged(const orc_event* ev, const orc_geometry* geo, double bz,
+                           const orc_params* prm, double merge_chi2, orc_tracks* out,
+                           orc_prolongations* pro, orc_merged* mrg, int n_threads) {
+  if (!mrg || !mrg->track_merged || !(merge_chi2 >= 0.0)) return -1;
+  return track_all(ev, geo, bz, prm, out, pro, mrg, merge_chi2, n_threads);
 }
 
 int orc_rotate(double x, const double* st, const double* cov, double d, double bz,
@@ -1117,6 +1133,361 @@ int orc_rotate(double x, const double* st, const double* cov, double d, double b
   if (cov_out)
     for (int i = 0; i < 5; ++i)
       for (int j = 0; j < 5; ++j) cov_out[5 * i + j] = s.C[i][j];
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Track merger with refit                                                   */
+/* ------------------------------------------------------------------------ */
+/*
+ * After the sector tracker, the track merger joins the sector tracks of one
+ * particle and refits each joined track from its cluster list alone, so
+ * that the same clusters always give the same fit whatever the sector
+ * tracker computed on the way (section 3.3).  The paper gives no more
+ * detail; reading used:
+ *   - a join links the outer end of a track A to the inner end of a track B
+ *     in a side neighbour of A's sector (same half, index +-1 mod 18) or in
+ *     its membrane partner (same index, other half), if B's innermost
+ *     cluster is farther from the beam axis than A's outermost (joins go
+ *     outward; tracks that curl back are not joined): A's outward filter at
+ *     its outermost cluster is rotated into B's frame and propagated to the x
+ *     of B's inward fit at its innermost cluster; the two estimates are
+ *     independent, so chi^2 = d^T (C_A + C_B)^-1 d over the five parameters
+ *     follows chi^2(5) for the same particle; candidates need chi^2 <=
+ *     merge_chi2;
+ *   - A and B are linked if each is the other's best candidate (smallest
+ *     chi^2, then smallest track index); links form chains; a chain that
+ *     closes on itself starts at its smallest track index;
+ *   - a joined track's cluster list, in path order: the inner prolongation
+ *     of its first track (outward order), each track's own clusters (row
+ *     order), the outer prolongation of its last track; prolongations at the
+ *     joins are not used;
+ *   - refit (refit_list): the seed circle of the first run of at least three
+ *     consecutive clusters of one sector with increasing rows (its first
+ *     min(m, seed_window) clusters, as for a tracklet), an outward filter
+ *     from there to the end of the list, then an inward fit from the last
+ *     cluster with a fresh covariance over the whole list; between clusters
+ *     of different sectors the state is rotated into the next sector's frame
+ *     (a multiple of the sector width); a cluster whose step fails
+ *     (|sin phi| limit, rotation) is skipped; the result is the inward fit at
+ *     the innermost fitted cluster, with its chi^2 and ndf = 2n - 5; fewer
+ *     than three fitted clusters, or a list over several sectors with an id
+ *     outside 0-35, fail (ndf 0).
+ */
+
+static int frame_steps(int p, int q) {
+  int k = (q % 18) - (p % 18);
+  if (k > 8) k -= 18;
+  if (k < -9) k += 18;
+  return k;
+}
+
+typedef struct {
+  double par[8];
+  int32_t frame;   /* sector_id of the frame of par, -1 if failed */
+  int32_t n;
+} refit_res;
+
+static int refit_list(const orc_event* ev, const orc_geometry* geo, double bz,
+                      const orc_params* p, int32_t n, const int32_t* cl, refit_res* out) {
+  memset(out, 0, sizeof(*out));
+  out->frame = -1;
+  if (n < 3) return 1;
+  const float* X = geo->row_x;
+  const float* Y = ev->y;
+  const float* Z = ev->z;
+  const double width = 2.0 * atan((double)geo->tan_half_angle);
+  const double sy2 = p->sigma_y * p->sigma_y, sz2 = p->sigma_z * p->sigma_z;
+  int* slot = (int*)malloc(sizeof(int) * (size_t)n);
+  int* row = (int*)malloc(sizeof(int) * (size_t)n);
+  int status = 1, multi = 0;
+  for (int32_t j = 0; j < n; ++j) {
+    slot[j] = locate(ev, geo, cl[j], &row[j]);
+    if (slot[j] < 0) goto done;
+    multi |= slot[j] != slot[0];
+  }
+  if (multi)
+    for (int32_t j = 0; j < n; ++j) {
+      int ph = ev->sector_id[slot[j]];
+      if (ph < 0 || ph >= 36) goto done;
+    }
+  /* seed: first run of >= 3 same-sector clusters with increasing rows */
+  int32_t i0 = -1;
+  for (int32_t i = 0; i + 2 < n; ++i)
+    if (slot[i + 1] == slot[i] && slot[i + 2] == slot[i] && row[i] < row[i + 1] &&
+        row[i + 1] < row[i + 2]) {
+      i0 = i;
+      break;
+    }
+  if (i0 < 0) goto done;
+  int32_t m = 1;
+  while (i0 + m < n && m < p->seed_window && slot[i0 + m] == slot[i0] &&
+         row[i0 + m] > row[i0 + m - 1])
+    ++m;
+  {
+    const int32_t a = i0, b = i0 + m / 2, e = i0 + m - 1;
+    kstate s;
+    kseed(&s, X[row[a]], Y[cl[a]], Z[cl[a]], X[row[b]], Y[cl[b]], X[row[e]], Y[cl[e]], Z[cl[e]],
+          bz, p);
+    if (fabs(s.p[2]) > p->max_sinphi) goto done;
+    /* outward filter */
+    int fr = slot[i0];
+    int32_t last = i0;
+    for (int32_t j = i0 + 1; j < n; ++j) {
+      kstate t = s;
+      if (slot[j] != fr &&
+          krotate(&t, frame_steps(ev->sector_id[fr], ev->sector_id[slot[j]]) * width, bz))
+        continue;
+      if (kprop(&t, X[row[j]], bz, p->max_sinphi, NULL)) continue;
+      kupdate(&t, Y[cl[j]], Z[cl[j]], sy2, sz2);
+      s = t;
+      fr = slot[j];
+      last = j;
+    }
+    /* inward fit from the last cluster, fresh covariance */
+    kstate w;
+    w.x = X[row[last]];
+    w.p[0] = Y[cl[last]];
+    w.p[1] = Z[cl[last]];
+    w.p[2] = s.p[2];
+    w.p[3] = s.p[3];
+    w.p[4] = s.p[4];
+    kreset_cov(&w, p);
+    double chi2 = 0.0;
+    int32_t nn = 1;
+    kstate inner = w;
+    int ifr = slot[last];
+    for (int32_t j = last - 1; j >= 0; --j) {
+      kstate t = w;
+      if (slot[j] != fr &&
+          krotate(&t, frame_steps(ev->sector_id[fr], ev->sector_id[slot[j]]) * width, bz))
+        continue;
+      if (kprop(&t, X[row[j]], bz, p->max_sinphi, NULL)) continue;
+      chi2 += kupdate(&t, Y[cl[j]], Z[cl[j]], sy2, sz2);
+      w = t;
+      fr = slot[j];
+      ++nn;
+      inner = w;
+      ifr = fr;
+    }
+    if (nn < 3) goto done;
+    out->par[0] = inner.x;
+    for (int i = 0; i < 5; ++i) out->par[1 + i] = inner.p[i];
+    out->par[6] = chi2;
+    out->par[7] = 2.0 * nn - 5.0;
+    out->frame = ev->sector_id[ifr];
+    out->n = nn;
+    status = 0;
+  }
+done:
+  free(slot);
+  free(row);
+  return status;
+}
+
+/* chi^2 of joining A's outer end to B's inner end, or -1 if they cannot join */
+static double join_chi2(const kstate* a_out, int pa, const kstate* b_in, int pb, double bz,
+                        const orc_params* p, double width, double cut) {
+  /* tan(lambda) and q/pT are unchanged by rotation and propagation, and so
+   * are their variances: d_i^2 / S_ii <= chi^2 for any positive-definite S,
+   * so these two bounds reject exactly */
+  for (int i = 3; i < 5; ++i) {
+    double d = b_in->p[i] - a_out->p[i], v = a_out->C[i][i] + b_in->C[i][i];
+    if (d * d > cut * v) return -1.0;
+  }
+  /* outward only: B starts farther from the beam than A ends (the radius
+   * does not depend on the frame); otherwise A's outer end, propagated
+   * backwards, would also match the inner end of the track it continues */
+  if (!(hypot(b_in->x, b_in->p[0]) > hypot(a_out->x, a_out->p[0]))) return -1.0;
+  kstate t = *a_out;
+  int k = frame_steps(pa, pb);
+  if (k != 0 && krotate(&t, k * width, bz)) return -1.0;
+  if (kprop(&t, b_in->x, bz, p->max_sinphi, NULL)) return -1.0;
+  double S[5][5], d[5];
+  for (int i = 0; i < 5; ++i) {
+    d[i] = b_in->p[i] - t.p[i];
+    for (int j = 0; j < 5; ++j) S[i][j] = t.C[i][j] + b_in->C[i][j];
+  }
+  /* Cholesky S = L L^T, then chi^2 = |L^-1 d|^2 */
+  double L[5][5] = {{0}};
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double v = S[i][j];
+      for (int q = 0; q < j; ++q) v -= L[i][q] * L[j][q];
+      if (i == j) {
+        if (!(v > 0.0)) return -1.0;
+        L[i][i] = sqrt(v);
+      } else {
+        L[i][j] = v / L[j][j];
+      }
+    }
+  double chi2 = 0.0, yv[5];
+  for (int i = 0; i < 5; ++i) {
+    double v = d[i];
+    for (int q = 0; q < i; ++q) v -= L[i][q] * yv[q];
+    yv[i] = v / L[i][i];
+    chi2 += yv[i] * yv[i];
+  }
+  return chi2;
+}
+
+static int merge_tracks(const orc_event* ev, const orc_geometry* geo, double bz,
+                        const orc_params* prm, double cut, const sector_out* outs,
+                        const orc_tracks* trk, const orc_prolongations* pro, orc_merged* mrg) {
+  const int64_t nt = trk->n_tracks;
+  const double width = 2.0 * atan((double)geo->tan_half_angle);
+  int phys2slot[36];
+  for (int i = 0; i < 36; ++i) phys2slot[i] = -1;
+  for (int sl = 0; sl < ev->n_sectors; ++sl) {
+    int ph = ev->sector_id[sl];
+    if (ph >= 0 && ph < 36 && phys2slot[ph] < 0) phys2slot[ph] = sl;
+  }
+  size_t nb = (size_t)(nt + 1);
+  int32_t* slot_of = (int32_t*)malloc(sizeof(int32_t) * nb);
+  const kstate** e_in = (const kstate**)malloc(sizeof(kstate*) * nb);
+  const kstate** e_out = (const kstate**)malloc(sizeof(kstate*) * nb);
+  int64_t* first_of_slot = (int64_t*)calloc((size_t)ev->n_sectors + 1, sizeof(int64_t));
+  {
+    int64_t it = 0;
+    for (int sl = 0; sl < ev->n_sectors; ++sl) {
+      first_of_slot[sl] = it;
+      for (int64_t t = 0; t < outs[sl].n_tracks; ++t, ++it) {
+        slot_of[it] = sl;
+        e_in[it] = &outs[sl].ends[2 * t];
+        e_out[it] = &outs[sl].ends[2 * t + 1];
+      }
+    }
+    first_of_slot[ev->n_sectors] = it;
+  }
+  int32_t* best_next = (int32_t*)malloc(sizeof(int32_t) * nb);
+  int32_t* best_prev = (int32_t*)malloc(sizeof(int32_t) * nb);
+  double* chi_next = (double*)malloc(sizeof(double) * nb);
+  double* chi_prev = (double*)malloc(sizeof(double) * nb);
+  for (int64_t i = 0; i < nt; ++i) {
+    best_next[i] = best_prev[i] = -1;
+    chi_next[i] = chi_prev[i] = INFINITY;
+  }
+  for (int64_t a = 0; a < nt; ++a) {
+    const int pa = ev->sector_id[slot_of[a]];
+    if (pa < 0 || pa >= 36) continue;
+    const int half = pa / 18, idx = pa % 18;
+    int cand[3] = {phys2slot[half * 18 + (idx + 1) % 18], phys2slot[half * 18 + (idx + 17) % 18],
+                   phys2slot[(pa + 18) % 36]};
+    for (int c = 0; c < 3; ++c) {
+      const int sb = cand[c];
+      if (sb < 0 || sb == slot_of[a]) continue;
+      int dup = 0;
+      for (int c2 = 0; c2 < c; ++c2) dup |= cand[c2] == sb;
+      if (dup) continue;
+      const int pb = ev->sector_id[sb];
+      for (int64_t b = first_of_slot[sb]; b < first_of_slot[sb + 1]; ++b) {
+        double x2 = join_chi2(e_out[a], pa, e_in[b], pb, bz, prm, width, cut);
+        if (x2 < 0.0 || x2 > cut) continue;
+        if (x2 < chi_next[a] || (x2 == chi_next[a] && b < best_next[a])) {
+          chi_next[a] = x2;
+          best_next[a] = (int32_t)b;
+        }
+        if (x2 < chi_prev[b] || (x2 == chi_prev[b] && a < best_prev[b])) {
+          chi_prev[b] = x2;
+          best_prev[b] = (int32_t)a;
+        }
+      }
+    }
+  }
+  int32_t* next = (int32_t*)malloc(sizeof(int32_t) * nb);
+  int32_t* prev = (int32_t*)malloc(sizeof(int32_t) * nb);
+  for (int64_t i = 0; i < nt; ++i) next[i] = prev[i] = -1;
+  for (int64_t a = 0; a < nt; ++a) {
+    int32_t b = best_next[a];
+    if (b >= 0 && best_prev[b] == a) {
+      next[a] = b;
+      prev[b] = (int32_t)a;
+    }
+  }
+  /* chain heads: no predecessor; then the smallest index of each cycle */
+  uint8_t* head = (uint8_t*)calloc(nb, 1);
+  uint8_t* seen = (uint8_t*)calloc(nb, 1);
+  for (int64_t i = 0; i < nt; ++i)
+    if (prev[i] < 0) {
+      head[i] = 1;
+      for (int32_t j = (int32_t)i; j >= 0 && !seen[j]; j = next[j]) seen[j] = 1;
+    }
+  for (int64_t i = 0; i < nt; ++i)
+    if (!seen[i]) {
+      head[i] = 1;
+      for (int32_t j = (int32_t)i; j >= 0 && !seen[j]; j = next[j]) seen[j] = 1;
+    }
+  /* prolongation of (track, end) */
+  int32_t* pro_of = (int32_t*)malloc(sizeof(int32_t) * 2 * nb);
+  for (int64_t i = 0; i < 2 * nt; ++i) pro_of[i] = -1;
+  if (pro)
+    for (int32_t k = 0; k < pro->n; ++k) pro_of[2 * pro->meta[5 * k] + pro->meta[5 * k + 1]] = k;
+  /* lists, in head order */
+  int64_t n_m = 0, n_c = 0;
+  int32_t* list = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ev->n_clusters + 1));
+  for (int pass = 0; pass < 2; ++pass) {
+    n_m = 0;
+    n_c = 0;
+    int status_cap = pass == 1 && (mrg->n > mrg->cap || mrg->n_clusters > mrg->cap_clusters);
+    for (int64_t h = 0; h < nt; ++h) {
+      if (!head[h]) continue;
+      int32_t len = 0, nseg = 0, lastseg = (int32_t)h;
+      int32_t k = pro_of[2 * h];
+      if (k >= 0)
+        for (int32_t j = pro->meta[5 * k + 3] - 1; j >= 0; --j)
+          list[len++] = pro->cluster[pro->meta[5 * k + 4] + j];
+      int32_t j = (int32_t)h;
+      do {
+        const int32_t* m = trk->track_meta + 4 * j;
+        for (int32_t q = 0; q < m[1]; ++q) list[len++] = trk->track_cluster[m[2] + q];
+        if (pass == 1 && !status_cap) mrg->track_merged[j] = (int32_t)n_m;
+        ++nseg;
+        lastseg = j;
+        j = next[j];
+      } while (j >= 0 && j != h);
+      k = pro_of[2 * lastseg + 1];
+      if (k >= 0)
+        for (int32_t q = 0; q < pro->meta[5 * k + 3]; ++q)
+          list[len++] = pro->cluster[pro->meta[5 * k + 4] + q];
+      if (pass == 1 && !status_cap) {
+        refit_res rr;
+        refit_list(ev, geo, bz, prm, len, list, &rr);
+        double* P = mrg->par + 8 * n_m;
+        for (int i = 0; i < 8; ++i) P[i] = rr.par[i];
+        int32_t* M = mrg->meta + 5 * n_m;
+        M[0] = rr.frame >= 0 ? rr.frame : ev->sector_id[slot_of[h]];
+        M[1] = nseg;
+        M[2] = len;
+        M[3] = (int32_t)n_c;
+        M[4] = (int32_t)h;
+        memcpy(mrg->cluster + n_c, list, sizeof(int32_t) * (size_t)len);
+      }
+      ++n_m;
+      n_c += len;
+    }
+    if (pass == 0) {
+      mrg->n = (int32_t)n_m;
+      mrg->n_clusters = (int32_t)n_c;
+    }
+  }
+  int status = (mrg->n > mrg->cap || mrg->n_clusters > mrg->cap_clusters) ? 1 : 0;
+  free(list); free(pro_of); free(head); free(seen); free(next); free(prev);
+  free(best_next); free(best_prev); free(chi_next); free(chi_prev);
+  free(first_of_slot); free(slot_of); free(e_in); free(e_out);
+  return status;
+}
+
+int orc_refit(const orc_event* ev, const orc_geometry* geo, double bz, const orc_params* prm,
+              int32_t n_lists, const int32_t* offsets, const int32_t* clusters, double* par,
+              int32_t* frame_sector) {
+  if (check_event(ev, geo) || !prm || n_lists < 0 || (n_lists > 0 && (!offsets || !par)))
+    return -1;
+  for (int32_t i = 0; i < n_lists; ++i) {
+    refit_res rr;
+    refit_list(ev, geo, bz, prm, offsets[i + 1] - offsets[i], clusters + offsets[i], &rr);
+    for (int k = 0; k < 8; ++k) par[8 * i + k] = rr.par[k];
+    if (frame_sector) frame_sector[i] = rr.frame;
+  }
   return 0;
 }
 

@@ -109,6 +109,35 @@ int orc_track_event_global(const orc_event* ev, const orc_geometry* geo, double 
                            const orc_params* prm, orc_tracks* out,
                            orc_prolongations* pro, int n_threads);
 
+/* ---- track merger with refit ---------------------------------------------
+ * Joins the sector tracks of one particle (outer end of one to the inner end
+ * of a track in a neighbouring or membrane-partner sector) and refits every
+ * joined track from its cluster list alone (reading in tpc_oracle.c). */
+typedef struct {
+  int32_t cap, cap_clusters;   /* in: capacities */
+  int32_t n, n_clusters;       /* out: sizes (also when too small) */
+  double* par;        /* [cap][8]: x, y, z, sinphi, tanl, qpt at the innermost fitted
+                         cluster (frame of its sector), chi2, ndf (0: refit failed) */
+  int32_t* meta;      /* [cap][5]: sector_id of that frame, tracks joined, n_clusters,
+                         first, first track of the chain */
+  int32_t* cluster;   /* [cap_clusters]: clusters in path order */
+  int32_t* track_merged;  /* [cap_tracks of the tracks]: joined track of each track */
+} orc_merged;
+
+/* orc_track_event_global (pro may be NULL: no prolongations), then the
+ * merger.  Joined tracks are ordered by their first track.  Returns 1 if a
+ * capacity is too small. */
+int orc_track_event_merged(const orc_event* ev, const orc_geometry* geo, double bz,
+                           const orc_params* prm, double merge_chi2, orc_tracks* out,
+                           orc_prolongations* pro, orc_merged* mrg, int n_threads);
+
+/* The merger's refit of cluster lists: list i is clusters[offsets[i] ..
+ * offsets[i+1]) in path order; par [n_lists][8] as orc_merged.par,
+ * frame_sector [n_lists] (may be NULL) the sector_id of par's frame or -1. */
+int orc_refit(const orc_event* ev, const orc_geometry* geo, double bz, const orc_params* prm,
+              int32_t n_lists, const int32_t* offsets, const int32_t* clusters, double* par,
+              int32_t* frame_sector);
+
 /* Rotation of a state (and covariance, may be NULL) at x into a frame turned
  * by d radians.  Returns 1 if the direction would not point along the new
  * x axis. */
