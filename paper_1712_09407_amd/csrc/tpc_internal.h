@@ -111,6 +111,7 @@ struct GlobalScratch {
   int32_t* nslot;      // [2T] sector slot entered
   float* par;          // [2T][8] x, state at the last collected cluster, chi2, ndf
   int32_t* hit;        // [2T][kHitStride] clusters in the order met
+  int32_t* act;        // [2T] slots of the kept tracklets, in track order
   int32_t *owned, *kept, *idx, *off;  // [2T] clusters owned, reported, output index/offset
   int32_t* span_sum;   // scan partials
 };

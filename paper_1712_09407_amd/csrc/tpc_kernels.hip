@@ -762,9 +762,11 @@ __device__ __forceinline__ void load_end(const float* E, KState& s) {
   C.c44 = f.x;
 }
 
-// ENDS: also record the two end states global tracking starts from -- the
-// outward filter at the outermost collected cluster and the inward fit at
-// the innermost one -- overwritten at every update of the respective pass.
+// ENDS: also record what global tracking starts from: the outward filter at
+// the outermost collected cluster and the inward fit at the innermost one.
+// Rows without a cluster do not update the state, so each is stored once,
+// when its pass ends (the state then sits some miss rows beyond its cluster),
+// and k_prolong carries it back to that cluster's row with one helix step.
 template <bool ENDS>
 struct Lane {
   KState s;
@@ -821,7 +823,6 @@ struct Lane {
     seed3(s, s_x[k0], ev.y[start], ev.z[start], s_x[k0 + m / 2], ev.y[bmid], s_x[k0 + m - 1],
           ev.y[last], ev.z[last], kp);
     dropped = fabsf(s.sp) > kp.max_sinphi;
-    if constexpr (ENDS) store_end(sc.ends + ((size_t)tt * 2 + 1) * kEndStride, s);
     last_row = k0;
     l_sp = s.sp; l_tl = s.tl; l_q = s.qpt; l_y = s.y; l_z = s.z;
     HY[k0] = make_float2(s.y, s.z);
@@ -840,6 +841,7 @@ struct Lane {
 
   // Inward refit set-up from the outermost collected cluster.
   __device__ void begin_refit(const KParams& kp, const Scratch& sc, const float* s_x) {
+    if constexpr (ENDS) store_end(sc.ends + ((size_t)t * 2 + 1) * kEndStride, s);
     s.x = s_x[last_row];
     s.y = l_y;
     s.z = l_z;
@@ -851,7 +853,6 @@ struct Lane {
     inner = last_row;
     chi2 = 0.f;
     o0 = s.x; o1 = s.y; o2 = s.z; o3 = s.sp; o4 = s.tl; o5 = s.qpt;
-    if constexpr (ENDS) store_end(sc.ends + (size_t)t * 2 * kEndStride, s);
     phase = P_REFIT;
     r = last_row - 1;
     prefetch_refit();
@@ -929,7 +930,6 @@ struct Lane {
       if (st == 0) {
         last_row = r;
         l_sp = s.sp; l_tl = s.tl; l_q = s.qpt; l_y = my; l_z = mz;
-        if constexpr (ENDS) store_end(sc.ends + ((size_t)t * 2 + 1) * kEndStride, s);
       }
       if (st != 2) {  // H[r] = hit, HY[r] = (my, mz) if a cluster was taken
         pend_r = r;
@@ -961,7 +961,6 @@ struct Lane {
         ++n;
         inner = r;
         o0 = s.x; o1 = s.y; o2 = s.z; o3 = s.sp; o4 = s.tl; o5 = s.qpt;
-        if constexpr (ENDS) store_end(sc.ends + (size_t)t * 2 * kEndStride, s);
       }
       if (phase == P_DOWN) {
         if (st != 2) {  // H[r] = hit
@@ -993,6 +992,9 @@ struct Lane {
   // Tracklet outputs; the lane is done.
   __device__ void emit(const Scratch& sc) {
     flush();
+    if constexpr (ENDS) {
+      if (!dropped) store_end(sc.ends + (size_t)t * 2 * kEndStride, s);
+    }
     if (dropped) {
       sc.row_lo[t] = 0;
       sc.row_hi[t] = -1;
@@ -1614,8 +1616,18 @@ __global__ __launch_bounds__(kGridBlock) void k_pro_init(DevEvent ev, Scratch sc
                                                          GlobalScratch gs) {
   __shared__ int s_p2s[kLayoutSectors];
   const int n_cl = ev.n_dev ? *ev.n_dev : ev.n_clusters;
-  for (int i = blockIdx.x * kGridBlock + threadIdx.x; i < n_cl; i += gridDim.x * kGridBlock)
+  const int stride = gridDim.x * kGridBlock;
+  for (int i = blockIdx.x * kGridBlock + threadIdx.x; i < n_cl; i += stride)
     gs.claim[i] = 0x7fffffff;
+  if (!event_bad(sc.counters)) {  // the slots of the tracks, in track order
+    const int n_tl = min(sc.counters[C_SEEDS], sc.cap_tl);
+    for (int t = blockIdx.x * kGridBlock + threadIdx.x; t < n_tl; t += stride)
+      if (sc.kept[t]) {
+        const int i = sc.trk_idx[t];
+        gs.act[2 * i] = 2 * t;
+        gs.act[2 * i + 1] = 2 * t + 1;
+      }
+  }
   if (blockIdx.x != 0) return;
   if (threadIdx.x < kLayoutSectors) s_p2s[threadIdx.x] = 0x7fffffff;
   __syncthreads();
@@ -1682,6 +1694,30 @@ __device__ __forceinline__ bool rotate(KState& s, float ca, float sa, const KPar
   return true;
 }
 
+// The helix parameters alone, stepped to x2 with the same formulas as
+// propagate (no Jacobian): for checks along a path whose covariance is
+// needed only at its end.
+struct HelixPar {
+  float x, y, z, sp, tl, qpt;
+};
+__device__ __forceinline__ bool step_par(HelixPar& h, float x2, const KParams& kp) {
+  const float dx = x2 - h.x;
+  const float kap = kp.k_curv * h.qpt;
+  const float s1 = h.sp, s2 = s1 - kap * dx;
+  if (fabsf(s1) > kp.max_sinphi || fabsf(s2) > kp.max_sinphi) return false;
+  const float c1 = (1.f - s1) * (1.f + s1) * frsq((1.f - s1) * (1.f + s1));
+  const float c2 = (1.f - s2) * (1.f + s2) * frsq((1.f - s2) * (1.f + s2));
+  const float T = (s1 + s2) * frcp(c1 + c2);
+  const float Q2 = 1.f + T * T;
+  const float Q = Q2 * frsq(Q2);
+  const float u = 0.5f * kap * dx * Q;
+  h.y += dx * T;
+  h.z += h.tl * dx * Q * asinc(u);
+  h.sp = s2;
+  h.x = x2;
+  return true;
+}
+
 struct FreeCluster {
   const int32_t* cluster_track;
   __device__ bool operator()(int c) const { return cluster_track[c] < 0; }
@@ -1692,30 +1728,35 @@ __device__ int prolong_slot(int q, const DevEvent& ev, const KParams& kp, const 
                             const GlobalScratch& gs, const int32_t* cluster_track,
                             const float* s_x) {
   const int t = q >> 1, e = q & 1, dir = e ? 1 : -1, nr = kp.n_rows;
+  const int row = e ? sc.row_hi[t] : sc.row_lo[t];
   KState s;
   load_end(sc.ends + (size_t)q * kEndStride, s);
-  KState last = s;
-  int r = (e ? sc.row_hi[t] : sc.row_lo[t]) + dir;
-  // 1. own sector, no search, until the track is outside the trapezoid
-  bool left = false;
+  // the end state: the stored one carried back over the pass's last misses
+  if (!propagate(s, s_x[row], kp)) return 0;
+  // 1. own sector, no search, until the track is outside the trapezoid: the
+  //    checks need only the parameters, the covariance is carried once, to
+  //    the last row inside
+  HelixPar h{s.x, s.y, s.z, s.sp, s.tl, s.qpt};
+  int r = row + dir, last_r = row;
+  bool left = false, up = false;
   for (; r >= 0 && r < nr; r += dir) {
-    if (!propagate(s, s_x[r], kp)) return 0;
-    if (fabsf(s.z) > kp.z_max) return 0;
-    if (fabsf(s.y) > s_x[r] * kp.tan_half) {
+    if (!step_par(h, s_x[r], kp)) return 0;
+    if (fabsf(h.z) > kp.z_max) return 0;
+    if (fabsf(h.y) > s_x[r] * kp.tan_half) {
       left = true;
+      up = h.y > 0.f;
       break;
     }
-    last = s;
+    last_r = r;
   }
   if (!left) return 0;
+  if (last_r != row && !propagate(s, s_x[last_r], kp)) return 0;
   // 2. the neighbour on that side
   const int phys = ev.sector_id[sc.seed_rs[t] / nr];
   if (phys < 0 || phys >= kLayoutSectors) return 0;
-  const bool up = s.y > 0.f;
   const int nphys = (phys / 18) * 18 + (phys % 18 + (up ? 1 : 17)) % 18;
   const int ns = gs.p2s[nphys];
   if (ns < 0) return 0;
-  s = last;
   if (!rotate(s, kp.rot_c, up ? kp.rot_s : -kp.rot_s, kp)) return 0;
   if (fabsf(s.sp) > kp.max_sinphi) return 0;
   // 3. extension in the neighbour from the first row beyond x
@@ -1730,16 +1771,17 @@ __device__ int prolong_slot(int q, const DevEvent& ev, const KParams& kp, const 
   Work wk;
   int misses = 0, n = 0;
   float chi2 = 0.f;
+  RowGrid gn;  // grid header of row r, loaded one step ahead
+  if (r >= 0 && r < nr) gn = sc.grid[ns * nr + r];
   for (; r >= 0 && r < nr; r += dir) {
+    const RowGrid g = gn;
+    if (r + dir >= 0 && r + dir < nr) gn = sc.grid[ns * nr + r + dir];
     if (!propagate(s, s_x[r], kp)) break;
     if (fabsf(s.z) > kp.z_max) break;
     int h = -1;
     float my = 0.f, mz = 0.f;
-    if (!(fabsf(s.y) > s_x[r] * kp.tan_half)) {
-      const int rs = ns * nr + r;
-      const RowGrid g = sc.grid[rs];
-      h = search_row(sc, g, g.bin_base - rs, s, kp, my, mz, wk, free_only);
-    }
+    if (!(fabsf(s.y) > s_x[r] * kp.tan_half))
+      h = search_row(sc, g, g.bin_base - (ns * nr + r), s, kp, my, mz, wk, free_only);
     if (h >= 0) {
       chi2 += kf_update(s, my, mz, kp);
       H[n++] = h;
@@ -1764,17 +1806,20 @@ __global__ __launch_bounds__(kGridBlock) void k_prolong(DevEvent ev, KParams kp,
   __shared__ float s_x[TPC_MAX_ROWS];
   for (int i = threadIdx.x; i < kp.n_rows; i += kGridBlock) s_x[i] = kp.row_x[i];
   __syncthreads();
-  if (event_bad(gs.counters)) return;
-  const int n_slots = gs.counters[C_SEEDS];
-  for (int q = blockIdx.x * kGridBlock + threadIdx.x; q < n_slots; q += gridDim.x * kGridBlock)
-    gs.n[q] = sc.kept[q >> 1] ? prolong_slot(q, ev, kp, sc, gs, cluster_track, s_x) : 0;
+  if (event_bad(gs.counters) || gs.counters[C_SEEDS] == 0) return;
+  // the kept tracklets' slots only (other slots are never read as collected)
+  const int n_act = 2 * sc.counters[C_TRACKS];
+  for (int i = blockIdx.x * kGridBlock + threadIdx.x; i < n_act; i += gridDim.x * kGridBlock) {
+    const int q = gs.act[i];
+    gs.n[q] = prolong_slot(q, ev, kp, sc, gs, cluster_track, s_x);
+  }
 }
 
-__global__ __launch_bounds__(kGridBlock) void k_pro_own(GlobalScratch gs) {
+__global__ __launch_bounds__(kGridBlock) void k_pro_own(Scratch sc, GlobalScratch gs) {
   if (event_bad(gs.counters)) return;
   const int n_slots = gs.counters[C_SEEDS];
   for (int q = blockIdx.x * kGridBlock + threadIdx.x; q < n_slots; q += gridDim.x * kGridBlock) {
-    const int n = gs.n[q];
+    const int n = sc.kept[q >> 1] ? gs.n[q] : 0;
     const int32_t* H = gs.hit + (size_t)q * kHitStride;
     int o = 0;
     for (int j = 0; j < n; ++j) o += gs.claim[H[j]] == q ? 1 : 0;
@@ -1987,7 +2032,7 @@ size_t global_bytes(int64_t N, int64_t T) {
   b += align_up(sizeof(int32_t) * Q) * 2;
   b += align_up(sizeof(float) * Q * 8);
   b += align_up(sizeof(int32_t) * Q * kHitStride);
-  b += align_up(sizeof(int32_t) * Q) * 4;
+  b += align_up(sizeof(int32_t) * Q) * 5;
   b += align_up(sizeof(int32_t) * (2 * ((Q + kSpan - 1) / kSpan) + 2));
   return b;
 }
@@ -2008,6 +2053,7 @@ void global_carve(void* base, int64_t N, int64_t T, float** ends, GlobalScratch*
   gs->nslot = (int32_t*)take(sizeof(int32_t) * Q);
   gs->par = (float*)take(sizeof(float) * Q * 8);
   gs->hit = (int32_t*)take(sizeof(int32_t) * Q * kHitStride);
+  gs->act = (int32_t*)take(sizeof(int32_t) * Q);
   gs->owned = (int32_t*)take(sizeof(int32_t) * Q);
   gs->kept = (int32_t*)take(sizeof(int32_t) * Q);
   gs->idx = (int32_t*)take(sizeof(int32_t) * Q);
@@ -2144,7 +2190,7 @@ hipError_t enqueue_global(const DevEvent& ev, const KParams& kp, const Scratch& 
                      (const int32_t*)out.cluster_track);
   post(K_PROLONG);
   pre(K_PRO_OWN);
-  hipLaunchKernelGGL(k_pro_own, dim3(qb), dim3(kGridBlock), 0, st, gs);
+  hipLaunchKernelGGL(k_pro_own, dim3(qb), dim3(kGridBlock), 0, st, sc, gs);
   post(K_PRO_OWN);
   // numbering of the slots that own clusters: the selection's scan over slots
   Scratch ps = sc;
