@@ -251,6 +251,67 @@ def global_section(tr, tpc, synth, geo, prm, e, dev_ev, steps, log_):
                 **q)
 
 
+def merge_section(tr, tpc, synth, geo, prm, e, dev_ev, steps, log_):
+    """The track merger with refit on the benchmark event: the whole path,
+    global tracking, joins and refits, against the plain and global paths;
+    quality of the joined tracks against MC truth with and without global
+    tracking (section 5's claim) and of the sector tracks; the oracle's
+    joined tracks (concordance) come from the cpu_baseline leg."""
+    import torch
+    from paper_1712_09407_amd import quality
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    plain = timed(lambda: tr.track_event(dev_ev, geo, e.bz, prm))
+    glob = timed(lambda: tr.track_event_global(dev_ev, geo, e.bz, prm))
+    merged = timed(lambda: tr.track_event_merged(dev_ev, geo, e.bz, prm))
+    merged0 = timed(lambda: tr.track_event_merged(dev_ev, geo, e.bz, prm, use_global=False))
+    tr.set_timing(None)
+    tr.reset_stats()
+    trk, pro, mg = tr.track_event_merged(dev_ev, geo, e.bz, prm)
+    st = tr.stats()
+    tr.set_timing([])
+    trk, mg = tpc.to_numpy(trk), tpc.to_numpy(mg)
+    _, _, mg0 = tr.track_event_merged(dev_ev, geo, e.bz, prm, use_global=False)
+    mg0 = tpc.to_numpy(mg0)
+    ORACLE_CHECKS["merger"] = dict(
+        ev=dict(y=e.y, z=e.z, row_offsets=e.row_offsets, sector_id=e.sector_id), bz=e.bz,
+        trk=trk, mg=mg)
+    ks = ("k_ends", "k_mrg_init", "k_mrg_match", "k_mrg_link", "k_mrg_chain", "k_mrg_reduce",
+          "k_mrg_scan", "k_mrg_write", "k_rowmap", "k_refit")
+
+    def q(rep):
+        out = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in rep.items()
+               if k != "resolution"}
+        out["resolution"] = {k: round(v, 6) for k, v in rep.get("resolution", {}).items()}
+        return out
+
+    sec = quality.evaluate(e, trk)
+    return dict(workload="benchmark central event: sector tracks joined across sector edges "
+                         "and the membrane, refitted from their cluster lists",
+                events_per_s=round(1.0 / merged, 2), ms_per_event=round(merged * 1e3, 4),
+                ms_per_event_without_global=round(merged0 * 1e3, 4),
+                global_ms_per_event=round(glob * 1e3, 4),
+                plain_ms_per_event=round(plain * 1e3, 4),
+                kernels_ms={k: round(st["kernel_ms"][k] / max(1, st["kernel_launches"][k]), 5)
+                            for k in ks},
+                tracks=int(trk["n_tracks"]), joined_tracks=int(mg["n"]),
+                joins=int(trk["n_tracks"] - mg["n"]),
+                quality_sector_tracks=dict(efficiency=round(sec["efficiency"], 6),
+                                           resolution={k: round(v, 6) for k, v in
+                                                       sec["resolution"].items()}),
+                quality_joined=q(quality.merged_report(e, mg0)),
+                quality_joined_with_global=q(quality.merged_report(e, mg)))
+
+
 def cpu_baseline_leg(tpc, prm, main_args, log_):
     """The oracle, on this host's cores: the headline baseline, then the
     comparisons the sections asked for (ORACLE_CHECKS).  Returns the baseline,
@@ -301,6 +362,18 @@ def cpu_baseline_leg(tpc, prm, main_args, log_):
                                    track_concordance=rep["track_concordance"],
                                    par_compared=rep["par_compared"], par_fail=rep["par_fail"],
                                    par_max_rel=rep["par_max_rel"])
+            elif name == "merger":
+                t1 = time.perf_counter()
+                rtr, _, rmg = oracle.track_event_merged(chk["ev"], geo_t, chk["bz"], op,
+                                                        merge_chi2=tpc.MERGE_CHI2,
+                                                        n_threads=cores)
+                t_orc = time.perf_counter() - t1
+                rep = concordance.compare_merged(rtr, rmg, chk["trk"], chk["mg"],
+                                                 len(chk["ev"]["y"]))
+                extra[name] = dict(oracle_s_per_event=round(t_orc, 4), oracle_cores=cores,
+                                   oracle_joined_tracks=int(rmg["n"]),
+                                   **{k: (round(v, 7) if isinstance(v, float) else v)
+                                      for k, v in rep.items()})
             elif name == "global_tracking":
                 t1 = time.perf_counter()
                 rtr, rpro = oracle.track_event_global(chk["ev"], geo_t, chk["bz"], op,
@@ -597,6 +670,8 @@ def main():
                     ("stress", lambda: stress_section(tr, tpc, synth, geo, 16, 3, log)),
                     ("global_tracking", lambda: global_section(tr, tpc, synth, geo, prm, e,
                                                                dev_ev, 20, log)),
+                    ("merger", lambda: merge_section(tr, tpc, synth, geo, prm, e, dev_ev, 20,
+                                                     log)),
                     ("alpha_scan", lambda: alpha_scan_section(tr, tpc, synth, geo, [2, 3, 4], log)))
         for name, fn in sections:
             log(f"{name} ...")

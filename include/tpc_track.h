@@ -196,6 +196,66 @@ int tpc_track_event_global(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry
                            float bz_tesla, const tpc_params* params, tpc_tracks* out,
                            tpc_prolongations* pro, void* hip_stream);
 
+/* ---- track merger with refit (section 1: the merger follows the sector
+ * tracker; section 3.3: it refits each track from its cluster list, so the
+ * same clusters give the same fit whatever the sector tracker computed).
+ * Reading of the paper, which describes no more:
+ *   - the outer end of track A (outward filter at its outermost cluster) is
+ *     joined to the inner end of track B (inward fit at its innermost
+ *     cluster) in a side neighbour of A's sector or in its membrane partner
+ *     (same index, other half of the 2 x 18 layout), if B's innermost cluster
+ *     is farther from the beam axis than A's outermost: A's end, rotated into
+ *     B's frame and propagated to B's x, and B's end are independent, so
+ *     chi^2 = d^T (C_A + C_B)^-1 d over the five parameters; A and B are
+ *     linked if chi^2 <= merge_chi2 and each is the other's best candidate
+ *     (smallest chi^2, then smallest track index); links form chains (a
+ *     closed one starts at its smallest track);
+ *   - a joined track's list in path order: the inner prolongation of its
+ *     first track (reversed), each track's own clusters, the outer
+ *     prolongation of its last track (prolongations only with global
+ *     tracking);
+ *   - the refit (also tpc_refit): seed circle of the first run of >= 3
+ *     consecutive clusters of one sector with increasing rows (first, middle,
+ *     last of its first min(m, seed_window)), outward Kalman filter to the end
+ *     of the list, inward fit from the last cluster with a fresh covariance
+ *     over the whole list; between sectors the state is rotated by whole
+ *     sector widths; a cluster whose step fails is skipped; fewer than three
+ *     fitted clusters, or a list over several sectors with an id outside
+ *     0-35, fail (par zero). */
+typedef struct {
+  int32_t cap;            /* rows of par / meta */
+  int32_t cap_clusters;   /* length of cluster */
+  int32_t* n;             /* HOST out: joined tracks (also on CAPACITY) */
+  int32_t* n_clusters;    /* HOST out: clusters in their lists (also on CAPACITY) */
+  float* par;             /* DEVICE [cap][8]: x, y, z, sinphi, tanl, q/pT at the innermost
+                             fitted cluster, in the frame of sector meta[0]; chi2; ndf
+                             (0 = the refit failed) */
+  int32_t* meta;          /* DEVICE [cap][5]: sector_id of par's frame, tracks joined,
+                             n_clusters, first (offset into cluster), first track */
+  int32_t* cluster;       /* DEVICE [cap_clusters]: cluster lists in path order */
+  int32_t* track_merged;  /* DEVICE [cap_tracks of the tracks]: joined track of each track */
+} tpc_merged;
+
+/* tpc_track_event (and global tracking if pro is not NULL), then the merger.
+ * Joined tracks are ordered by their first track.  TPC_ERR_CAPACITY with the
+ * sizes set when an output is too small (later stages report 0 then). */
+int tpc_track_event_merged(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo,
+                           float bz_tesla, const tpc_params* params, float merge_chi2,
+                           tpc_tracks* out, tpc_prolongations* pro, tpc_merged* mrg,
+                           void* hip_stream);
+
+/* The merger's refit of caller-given cluster lists of an event: list i is
+ * clusters[offsets[i] .. offsets[i+1]) (DEVICE offsets [n_lists + 1], DEVICE
+ * clusters [n_entries]; offsets are clamped to [0, n_entries], cluster
+ * indices outside the event fail that list).  par (DEVICE [n_lists][8]) and
+ * frame_sector (DEVICE [n_lists], may be NULL: sector_id of par's frame, -1
+ * if the refit failed) as in tpc_merged.  The event is validated as in
+ * tpc_track_event. */
+int tpc_refit(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float bz_tesla,
+              const tpc_params* params, int32_t n_lists, int32_t n_entries,
+              const int32_t* offsets, const int32_t* clusters, float* par,
+              int32_t* frame_sector, void* hip_stream);
+
 /* Stage-by-stage access for checks (same kernels as tpc_track_event).
  * Runs the neighbours finder and the evolution step and copies the link
  * arrays into DEVICE buffers of n_clusters int32 each (any may be NULL):

@@ -186,3 +186,58 @@ def compare_prolongations(tracks_a, pro_a, tracks_b, pro_b, n_clusters: int,
                 cluster_concordance_ba=same / max(1, tot_b),
                 identical=identical, other_seed=other_seed, par_compared=compared,
                 par_fail=fail)
+
+
+def compare_merged(tracks_a, merged_a, tracks_b, merged_b, n_clusters: int,
+                   rel_tol: float = 1e-3, chi2_tol: float = 1e-2) -> dict:
+    """Agreement of two runs' joined (merged) tracks.  A joined track of B
+    corresponds to the joined track of A that holds the partner of B's first
+    sector track (the tracks' one-to-one correspondence, as in compare).
+    joins_same: A's joined tracks whose sector tracks map one-to-one onto one
+    joined track of B; cluster_concordance_ab / _ba: the fraction of A's (B's)
+    list clusters that the corresponding list of the other run holds; for
+    identical lists, the refit parameters must agree within rel_tol relative
+    (absolute below 1), ndf exactly and chi2 within chi2_tol (the refit is a
+    function of the list alone, so only FP32/FP64 rounding separates them)."""
+    match_a, match_b = match_tracks(tracks_a, tracks_b, n_clusters)
+    ma, mb = np.asarray(merged_a["meta"]).reshape(-1, 5), np.asarray(merged_b["meta"]).reshape(-1, 5)
+    tma, tmb = np.asarray(merged_a["track_merged"]), np.asarray(merged_b["track_merged"])
+    la = [np.asarray(merged_a["cluster"][m[3]:m[3] + m[2]]) for m in ma]
+    lb = [np.asarray(merged_b["cluster"][m[3]:m[3] + m[2]]) for m in mb]
+    # joined track of B for each joined track of A, through A's first track
+    corr = np.full(len(la), -1, np.int64)
+    for k, m in enumerate(ma):
+        tb = match_a[m[4]]
+        if tb >= 0:
+            corr[k] = tmb[tb]
+    same_join = 0
+    for k in range(len(la)):
+        if corr[k] < 0:
+            continue
+        segs_a = np.nonzero(tma == k)[0]
+        segs_b = np.nonzero(tmb == corr[k])[0]
+        mapped = match_a[segs_a]
+        same_join += int(np.all(mapped >= 0) and np.array_equal(np.sort(mapped), segs_b))
+    shared = sum(np.intersect1d(la[k], lb[corr[k]]).size for k in range(len(la)) if corr[k] >= 0)
+    tot_a = sum(x.size for x in la)
+    tot_b = sum(x.size for x in lb)
+    pa_all = np.asarray(merged_a["par"], np.float64).reshape(-1, 8)
+    pb_all = np.asarray(merged_b["par"], np.float64).reshape(-1, 8)
+    identical = compared = fail = 0
+    for k in range(len(la)):
+        if corr[k] < 0 or not np.array_equal(la[k], lb[corr[k]]):
+            continue
+        identical += 1
+        pa, pb = pa_all[k], pb_all[corr[k]]
+        if pa[7] == 0 and pb[7] == 0:
+            continue  # both refits failed
+        compared += 1
+        ok = np.all(np.abs(pb[:6] - pa[:6]) <= rel_tol * np.maximum(1.0, np.abs(pa[:6])))
+        ok = ok and pb[7] == pa[7] and abs(pb[6] - pa[6]) <= chi2_tol * max(1.0, abs(pa[6]))
+        fail += 0 if ok else 1
+    return dict(n_a=len(la), n_b=len(lb), joins_same=same_join,
+                joins_same_frac=same_join / max(1, len(la)),
+                clusters_a=tot_a, clusters_b=tot_b,
+                cluster_concordance_ab=shared / max(1, tot_a),
+                cluster_concordance_ba=shared / max(1, tot_b),
+                identical=identical, par_compared=compared, par_fail=fail)

@@ -31,6 +31,8 @@ struct KParams {
   int32_t nf_dense;            // neighbours finder for dense rows (larger LDS stage)
   int32_t construct_lanes;     // lane schedule: lanes of a wave that take tracklets
   float rot_c, rot_s;          // cos, sin of one sector width (global tracking)
+  float rot_tab[18][2];        // cos, sin of k sector widths, k = -9 .. 8 at [k + 9]
+  float merge_chi2;            // track merger: chi^2(5) cut of a join
 };
 
 struct DevEvent {
@@ -116,6 +118,30 @@ struct GlobalScratch {
   int32_t* span_sum;   // scan partials
 };
 
+// Device scratch of the track merger, indexed by track (at most T tracks).
+struct MergeScratch {
+  int32_t* counters;    // [C_COUNT]: C_SEEDS = tracks, C_TRACKS / C_TRACK_CLUSTERS = joined
+                        // tracks / clusters, C_ERR from the sector tracker
+  int32_t* first;       // [S + 1] first track of each sector slot
+  float4* sum;          // [T][2] inner end of each track: x, y, tanl, q/pT; var tanl, var
+                        // q/pT, radius, valid
+  int32_t *next, *best; // [T]
+  unsigned long long* prev_key;  // [T] best predecessor: chi^2 bits << 32 | track
+  int32_t* prev;        // [T]
+  int32_t *cnt, *nseg, *kept, *idx, *off;  // [T] per chain head
+  int32_t* span_sum;
+  int32_t* loff;        // [T + 1] offsets of the joined tracks' lists
+  int32_t* rowslot;     // [N] row slot of each cluster (refit)
+};
+
+struct MergeOutputs {
+  int32_t cap, cap_clusters;
+  float* par;           // [cap][8]
+  int32_t* meta;        // [cap][5]: frame sector id, tracks joined, n_clusters, first, first track
+  int32_t* cluster;     // [cap_clusters]
+  int32_t* track_merged;  // [tracks]
+};
+
 struct ProOutputs {
   int32_t cap, cap_clusters;
   float* par;        // [cap][8]
@@ -182,7 +208,10 @@ enum KernelId {
   K_ZERO, K_GRID, K_NF, K_EVO, K_SCAN_ROWS, K_SEED_WRITE, K_CONSTRUCT, K_OWN,
   K_TL_REDUCE, K_TL_SCAN, K_OUTPUT,
   // global tracking
-  K_PRO_INIT, K_PROLONG, K_PRO_OWN, K_PRO_REDUCE, K_PRO_SCAN, K_PRO_OUTPUT, K_NUM
+  K_PRO_INIT, K_ENDS, K_PROLONG, K_PRO_OWN, K_PRO_REDUCE, K_PRO_SCAN, K_PRO_OUTPUT,
+  // track merger with refit
+  K_MRG_INIT, K_MRG_MATCH, K_MRG_LINK, K_MRG_CHAIN, K_MRG_REDUCE, K_MRG_SCAN, K_MRG_WRITE,
+  K_ROWMAP, K_REFIT, K_NUM
 };
 extern const char* const kKernelNames[K_NUM];
 
@@ -193,14 +222,30 @@ struct KernelTimer {
 };
 
 // Stage groups; each enqueues its kernels on `st` and returns the first error.
-enum Stage { STAGE_LINKS = 1, STAGE_SEEDS = 2, STAGE_TRACKLETS = 3, STAGE_ALL = 4 };
+enum Stage { STAGE_GRID = 0, STAGE_LINKS = 1, STAGE_SEEDS = 2, STAGE_TRACKLETS = 3, STAGE_ALL = 4 };
 hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& sc,
                          const Outputs& out, int upto, hipStream_t st,
                          const KernelTimer* timer = nullptr, bool zero_counters = true);
 // Global tracking after enqueue_event(STAGE_ALL) with Scratch::ends set:
-// prolongs the event's tracks (reads the tracker's cluster_track output).
+// prolongs the event's tracks (reads the tracker's cluster_track output);
+// with po == nullptr only the end states are prepared (for the merger).
 hipError_t enqueue_global(const DevEvent& ev, const KParams& kp, const Scratch& sc,
-                          const Outputs& out, const GlobalScratch& gs, const ProOutputs& po,
+                          const Outputs& out, const GlobalScratch& gs, const ProOutputs* po,
                           hipStream_t st, const KernelTimer* timer = nullptr);
+// The track merger with refit, after enqueue_global; po as given to it.
+size_t merge_bytes(int64_t n_clusters, int64_t n_sectors, int64_t cap_tl);
+void merge_carve(void* base, int64_t n_clusters, int64_t n_sectors, int64_t cap_tl,
+                 MergeScratch* ms);
+hipError_t enqueue_merge(const DevEvent& ev, const KParams& kp, const Scratch& sc,
+                         const Outputs& out, const GlobalScratch& gs, const ProOutputs* po,
+                         const MergeScratch& ms, const MergeOutputs& mo, hipStream_t st,
+                         const KernelTimer* timer = nullptr);
+// The merger's refit of caller-given cluster lists (after STAGE_GRID, which
+// validates the event): list i = clusters[offsets[i] .. offsets[i+1]),
+// offsets clamped to [0, n_entries].
+hipError_t enqueue_refit(const DevEvent& ev, const KParams& kp, const Scratch& sc,
+                         const MergeScratch& ms, int32_t n_lists, int32_t n_entries,
+                         const int32_t* offsets, const int32_t* clusters, float* par,
+                         int32_t* frame, hipStream_t st, const KernelTimer* timer = nullptr);
 
 }  // namespace tpc

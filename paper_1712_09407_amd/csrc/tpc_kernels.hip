@@ -749,6 +749,8 @@ __device__ __forceinline__ void store_end(float* E, const KState& s) {
   q[4] = make_float4(C.c40, C.c41, C.c42, C.c43);
   q[5] = make_float4(C.c44, 0.f, 0.f, 0.f);
 }
+// k_ends marks an end state valid (element 21) once it sits at its cluster's row.
+constexpr int kEndValid = 21;
 __device__ __forceinline__ void load_end(const float* E, KState& s) {
   const float4* q = reinterpret_cast<const float4*>(E);
   const float4 a = q[0], b = q[1], c = q[2], d = q[3], e = q[4], f = q[5];
@@ -1619,15 +1621,6 @@ __global__ __launch_bounds__(kGridBlock) void k_pro_init(DevEvent ev, Scratch sc
   const int stride = gridDim.x * kGridBlock;
   for (int i = blockIdx.x * kGridBlock + threadIdx.x; i < n_cl; i += stride)
     gs.claim[i] = 0x7fffffff;
-  if (!event_bad(sc.counters)) {  // the slots of the tracks, in track order
-    const int n_tl = min(sc.counters[C_SEEDS], sc.cap_tl);
-    for (int t = blockIdx.x * kGridBlock + threadIdx.x; t < n_tl; t += stride)
-      if (sc.kept[t]) {
-        const int i = sc.trk_idx[t];
-        gs.act[2 * i] = 2 * t;
-        gs.act[2 * i + 1] = 2 * t + 1;
-      }
-  }
   if (blockIdx.x != 0) return;
   if (threadIdx.x < kLayoutSectors) s_p2s[threadIdx.x] = 0x7fffffff;
   __syncthreads();
@@ -1648,6 +1641,29 @@ __global__ __launch_bounds__(kGridBlock) void k_pro_init(DevEvent ev, Scratch sc
     if (threadIdx.x == C_ERR) v = err;
     else if (threadIdx.x == C_SEEDS) v = err ? 0 : 2 * min(sc.counters[C_SEEDS], sc.cap_tl);
     gs.counters[threadIdx.x] = v;
+  }
+}
+
+// The end states of the tracks at their clusters' rows: each pass stored its
+// state when it ended, some rows without a cluster beyond its last cluster,
+// and one helix step carries it back.  Also lists the tracks' slots (two
+// per kept tracklet) in track order.
+__global__ __launch_bounds__(kGridBlock) void k_ends(KParams kp, Scratch sc, GlobalScratch gs) {
+  __shared__ float s_x[TPC_MAX_ROWS];
+  for (int i = threadIdx.x; i < kp.n_rows; i += kGridBlock) s_x[i] = kp.row_x[i];
+  __syncthreads();
+  if (event_bad(sc.counters) || __builtin_nontemporal_load(&gs.counters[C_SEEDS]) == 0) return;
+  const int n_tl = min(sc.counters[C_SEEDS], sc.cap_tl);
+  for (int q = blockIdx.x * kGridBlock + threadIdx.x; q < 2 * n_tl; q += gridDim.x * kGridBlock) {
+    const int t = q >> 1, e = q & 1;
+    if (!sc.kept[t]) continue;
+    gs.act[2 * sc.trk_idx[t] + e] = q;
+    float* E = sc.ends + (size_t)q * kEndStride;
+    KState s;
+    load_end(E, s);
+    const bool ok = propagate(s, s_x[e ? sc.row_hi[t] : sc.row_lo[t]], kp);
+    if (ok) store_end(E, s);
+    E[kEndValid] = ok ? 1.f : 0.f;
   }
 }
 
@@ -1729,10 +1745,10 @@ __device__ int prolong_slot(int q, const DevEvent& ev, const KParams& kp, const 
                             const float* s_x) {
   const int t = q >> 1, e = q & 1, dir = e ? 1 : -1, nr = kp.n_rows;
   const int row = e ? sc.row_hi[t] : sc.row_lo[t];
+  const float* E = sc.ends + (size_t)q * kEndStride;
+  if (E[kEndValid] == 0.f) return 0;
   KState s;
-  load_end(sc.ends + (size_t)q * kEndStride, s);
-  // the end state: the stored one carried back over the pass's last misses
-  if (!propagate(s, s_x[row], kp)) return 0;
+  load_end(E, s);
   // 1. own sector, no search, until the track is outside the trapezoid: the
   //    checks need only the parameters, the covariance is carried once, to
   //    the last row inside
@@ -1861,6 +1877,448 @@ __global__ __launch_bounds__(kGridBlock) void k_pro_output(DevEvent ev, Scratch 
       else v = gs.off[q];
       po.meta[(size_t)i * 5 + k] = v;
     }
+  }
+}
+
+// ------------------------------------------------------------------ track merger
+//
+// Section 1's chain: the sector tracks of one particle are joined and every
+// joined track is refitted from its cluster list alone, so that the same
+// clusters give the same fit whatever the sector tracker computed on the way
+// (section 3.3).  A join links the outer end of track A (the outward filter
+// at its outermost cluster) to the inner end of track B (the inward fit at
+// its innermost cluster) in a side neighbour of A's sector or in its
+// membrane partner, if B starts farther from the beam than A ends: A's end
+// is rotated into B's frame and propagated to B's x, and the two
+// independent estimates give chi^2 = d^T (C_A + C_B)^-1 d over the five
+// parameters; A and B are linked if each is the other's best candidate
+// under the cut (smallest chi^2, then smallest track).  One lane per track
+// A finds its best B and offers itself to every candidate B with a 64-bit
+// atomic minimum of (chi^2 bits, A).
+
+__device__ __forceinline__ int frame_steps(int p, int q) {
+  int k = (q % 18) - (p % 18);
+  if (k > 8) k -= 18;
+  if (k < -9) k += 18;
+  return k;
+}
+
+__device__ __forceinline__ bool rotate_steps(KState& s, int k, const KParams& kp) {
+  return k == 0 || rotate(s, kp.rot_tab[k + 9][0], kp.rot_tab[k + 9][1], kp);
+}
+
+// Track i's tracklet (its two slots were listed in track order by k_ends).
+__device__ __forceinline__ int tl_of_track(const GlobalScratch& gs, int i) {
+  return gs.act[2 * i] >> 1;
+}
+
+__global__ __launch_bounds__(kGridBlock) void k_mrg_init(DevEvent ev, KParams kp, Scratch sc,
+                                                         GlobalScratch gs, MergeScratch ms) {
+  if (event_bad(sc.counters)) return;
+  const int err = sc.counters[C_ERR];
+  const int nt = err ? 0 : sc.counters[C_TRACKS];
+  const int nr = kp.n_rows;
+  const int tid = blockIdx.x * kGridBlock + threadIdx.x, stride = gridDim.x * kGridBlock;
+  if (tid < C_COUNT) {
+    int v = 0;
+    if (tid == C_ERR) v = err;
+    else if (tid == C_SEEDS) v = nt;
+    ms.counters[tid] = v;
+  }
+  // first track of each slot: tracks follow the tracklets, in slot order
+  for (int sl = tid; sl <= ev.n_sectors; sl += stride) {
+    int lo = 0, hi = nt;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (sc.seed_rs[tl_of_track(gs, mid)] / nr < sl) lo = mid + 1;
+      else hi = mid;
+    }
+    ms.first[sl] = lo;
+  }
+  for (int i = tid; i < nt; i += stride) {
+    const float* E = sc.ends + (size_t)(2 * tl_of_track(gs, i)) * kEndStride;
+    const float4 a = reinterpret_cast<const float4*>(E)[0];
+    const float4 b = reinterpret_cast<const float4*>(E)[1];
+    ms.sum[2 * i] = make_float4(a.x, a.y, b.x, b.y);
+    // var tan(lambda) = C33 (element 15), var q/pT = C44 (element 20)
+    ms.sum[2 * i + 1] = make_float4(E[15], E[20], sqrtf(a.x * a.x + a.y * a.y), E[kEndValid]);
+    ms.prev_key[i] = ~0ull;
+    ms.prev[i] = -1;
+  }
+}
+
+// chi^2 of d^T S^-1 d for a symmetric positive-definite S (Cholesky), or -1.
+__device__ __forceinline__ float chi2_5(const float d[5], float S[5][5]) {
+  float L[5][5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      float v = S[i][j];
+#pragma unroll
+      for (int q = 0; q < j; ++q) v -= L[i][q] * L[j][q];
+      if (i == j) {
+        if (!(v > 0.f)) return -1.f;
+        L[i][i] = sqrtf(v);
+      } else {
+        L[i][j] = v / L[j][j];
+      }
+    }
+  float chi2 = 0.f, y[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    float v = d[i];
+#pragma unroll
+    for (int q = 0; q < i; ++q) v -= L[i][q] * y[q];
+    y[i] = v / L[i][i];
+    chi2 += y[i] * y[i];
+  }
+  return chi2;
+}
+
+__device__ __forceinline__ void cov_full(const Cov& C, float M[5][5]) {
+  M[0][0] = C.c00; M[1][0] = C.c10; M[1][1] = C.c11; M[2][0] = C.c20; M[2][1] = C.c21;
+  M[2][2] = C.c22; M[3][0] = C.c30; M[3][1] = C.c31; M[3][2] = C.c32; M[3][3] = C.c33;
+  M[4][0] = C.c40; M[4][1] = C.c41; M[4][2] = C.c42; M[4][3] = C.c43; M[4][4] = C.c44;
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = i + 1; j < 5; ++j) M[i][j] = M[j][i];
+}
+
+__global__ __launch_bounds__(kGridBlock) void k_mrg_match(DevEvent ev, KParams kp, Scratch sc,
+                                                          GlobalScratch gs, MergeScratch ms) {
+  if (event_bad(sc.counters)) return;
+  const int nt = ms.counters[C_SEEDS];
+  const int nr = kp.n_rows;
+  const float cut = kp.merge_chi2;
+  for (int a = blockIdx.x * kGridBlock + threadIdx.x; a < nt; a += gridDim.x * kGridBlock) {
+    int best = -1;
+    float best_c = INFINITY;
+    const int ta = tl_of_track(gs, a);
+    const int sa = sc.seed_rs[ta] / nr;
+    const int pa = ev.sector_id[sa];
+    const float* EA = sc.ends + (size_t)(2 * ta + 1) * kEndStride;
+    if (pa >= 0 && pa < kLayoutSectors && EA[kEndValid] != 0.f) {
+      KState A;
+      load_end(EA, A);
+      const float ra = sqrtf(A.x * A.x + A.y * A.y);
+      const int half = pa / 18, idx = pa % 18;
+      const int cand[3] = {gs.p2s[half * 18 + (idx + 1) % 18], gs.p2s[half * 18 + (idx + 17) % 18],
+                           gs.p2s[(pa + 18) % kLayoutSectors]};
+      for (int c = 0; c < 3; ++c) {
+        const int sb = cand[c];
+        if (sb < 0 || sb == sa || (c > 0 && cand[0] == sb) || (c > 1 && cand[1] == sb)) continue;
+        KState R = A;  // A's end in B's frame, once per slot
+        if (!rotate_steps(R, frame_steps(pa, ev.sector_id[sb]), kp)) continue;
+        for (int b = ms.first[sb]; b < ms.first[sb + 1]; ++b) {
+          const float4 u = ms.sum[2 * b], v = ms.sum[2 * b + 1];
+          // tan(lambda), q/pT and their variances do not change under rotation
+          // and propagation, and d_i^2 / S_ii <= chi^2: exact rejections
+          const float dt = u.z - A.tl, dq = u.w - A.qpt;
+          if (dt * dt > cut * (A.C.c33 + v.x) || dq * dq > cut * (A.C.c44 + v.y)) continue;
+          if (!(v.z > ra) || v.w == 0.f) continue;  // outward only; valid end
+          KState B;
+          load_end(sc.ends + (size_t)(2 * tl_of_track(gs, b)) * kEndStride, B);
+          KState T = R;
+          if (!propagate(T, B.x, kp)) continue;
+          float S[5][5], SB[5][5];
+          cov_full(T.C, S);
+          cov_full(B.C, SB);
+#pragma unroll
+          for (int i = 0; i < 5; ++i)
+#pragma unroll
+            for (int j = 0; j < 5; ++j) S[i][j] += SB[i][j];
+          const float d[5] = {B.y - T.y, B.z - T.z, B.sp - T.sp, B.tl - T.tl, B.qpt - T.qpt};
+          const float x2 = chi2_5(d, S);
+          if (!(x2 >= 0.f) || x2 > cut) continue;
+          if (x2 < best_c || (x2 == best_c && b < best)) {
+            best_c = x2;
+            best = b;
+          }
+          atomicMin(&ms.prev_key[b], ((unsigned long long)__float_as_uint(x2) << 32) |
+                                         (unsigned int)a);
+        }
+      }
+    }
+    ms.best[a] = best;
+  }
+}
+
+__global__ __launch_bounds__(kGridBlock) void k_mrg_link(Scratch sc, MergeScratch ms) {
+  if (event_bad(sc.counters)) return;
+  const int nt = ms.counters[C_SEEDS];
+  for (int a = blockIdx.x * kGridBlock + threadIdx.x; a < nt; a += gridDim.x * kGridBlock) {
+    const int b = ms.best[a];
+    const bool link = b >= 0 && (int)(ms.prev_key[b] & 0xffffffffull) == a;
+    ms.next[a] = link ? b : -1;
+    if (link) ms.prev[b] = a;  // b's best predecessor is unique
+  }
+}
+
+// Chain heads (no predecessor; in a closed chain, its smallest track) and
+// the clusters of each chain: the inner prolongation of its first track,
+// the tracks' own clusters, the outer prolongation of its last track.
+__global__ __launch_bounds__(kGridBlock) void k_mrg_chain(Scratch sc, GlobalScratch gs,
+                                                          MergeScratch ms, Outputs out,
+                                                          int use_pro) {
+  if (event_bad(sc.counters)) return;
+  const int nt = ms.counters[C_SEEDS];
+  // prolongations whose outputs did not fit were not written: not used
+  if (use_pro && gs.counters[C_ERR] != 0) use_pro = 0;
+  for (int i = blockIdx.x * kGridBlock + threadIdx.x; i < nt; i += gridDim.x * kGridBlock) {
+    bool head = ms.prev[i] < 0;
+    if (!head) {
+      int j = ms.prev[i], mn = i;
+      for (int k = 0; k < nt && j >= 0 && j != i; ++k) {
+        mn = min(mn, j);
+        j = ms.prev[j];
+      }
+      head = j == i && mn == i;
+    }
+    int cnt = 0, nseg = 0;
+    if (head) {
+      int j = i, last = i;
+      do {
+        cnt += out.track_meta[(size_t)j * 4 + 1];
+        ++nseg;
+        last = j;
+        j = ms.next[j];
+      } while (j >= 0 && j != i && nseg < nt);
+      if (use_pro) {
+        const int qi = 2 * tl_of_track(gs, i), qo = 2 * tl_of_track(gs, last) + 1;
+        if (gs.kept[qi]) cnt += gs.owned[qi];
+        if (gs.kept[qo]) cnt += gs.owned[qo];
+      }
+    }
+    ms.cnt[i] = cnt;
+    ms.nseg[i] = nseg;
+  }
+}
+
+// One wave per chain: its list in path order, meta, and the joined index of
+// its tracks.
+__global__ __launch_bounds__(kGridBlock) void k_mrg_write(DevEvent ev, KParams kp, Scratch sc,
+                                                          GlobalScratch gs, MergeScratch ms,
+                                                          Outputs out, ProOutputs po, int use_pro,
+                                                          MergeOutputs mo) {
+  if (__builtin_nontemporal_load(&ms.counters[C_ERR]) != 0) return;
+  const int nt = ms.counters[C_SEEDS];
+  const int lane = threadIdx.x & 63;
+  const int wpb = kGridBlock / 64;
+  if (use_pro && gs.counters[C_ERR] != 0) use_pro = 0;  // as in k_mrg_chain
+  if (blockIdx.x == 0 && threadIdx.x == 0) ms.loff[ms.counters[C_TRACKS]] =
+      ms.counters[C_TRACK_CLUSTERS];
+  for (int i = blockIdx.x * wpb + (threadIdx.x >> 6); i < nt; i += gridDim.x * wpb) {
+    if (!ms.kept[i]) continue;  // wave-uniform
+    const int k = ms.idx[i];
+    int off = ms.off[i];
+    const int first = off;
+    int last = i;
+    {  // the last track of the chain
+      int j = ms.next[i], n = 1;
+      while (j >= 0 && j != i && n < nt) {
+        last = j;
+        j = ms.next[j];
+        ++n;
+      }
+    }
+    if (use_pro) {
+      const int q = 2 * tl_of_track(gs, i);
+      if (gs.kept[q]) {  // inner prolongation, reversed into path order
+        const int pi = gs.idx[q];
+        const int n = po.meta[(size_t)pi * 5 + 3], f = po.meta[(size_t)pi * 5 + 4];
+        for (int j = lane; j < n; j += 64) mo.cluster[off + j] = po.cluster[f + n - 1 - j];
+        off += n;
+      }
+    }
+    int j = i, nseg = 0;
+    do {
+      const int n = out.track_meta[(size_t)j * 4 + 1], f = out.track_meta[(size_t)j * 4 + 2];
+      for (int q = lane; q < n; q += 64) mo.cluster[off + q] = out.track_cluster[f + q];
+      if (lane == 0) mo.track_merged[j] = k;
+      off += n;
+      ++nseg;
+      j = ms.next[j];
+    } while (j >= 0 && j != i && nseg < nt);
+    if (use_pro) {
+      const int q = 2 * tl_of_track(gs, last) + 1;
+      if (gs.kept[q]) {
+        const int pi = gs.idx[q];
+        const int n = po.meta[(size_t)pi * 5 + 3], f = po.meta[(size_t)pi * 5 + 4];
+        for (int j2 = lane; j2 < n; j2 += 64) mo.cluster[off + j2] = po.cluster[f + j2];
+        off += n;
+      }
+    }
+    if (lane < 5) {
+      int v;
+      if (lane == 0) v = ev.sector_id[sc.seed_rs[tl_of_track(gs, i)] / kp.n_rows];
+      else if (lane == 1) v = nseg;
+      else if (lane == 2) v = off - first;
+      else if (lane == 3) v = first;
+      else v = i;
+      mo.meta[(size_t)k * 5 + lane] = v;
+    }
+    if (lane == 0) ms.loff[k] = first;
+  }
+}
+
+// Row slot of every cluster (one workgroup per row slot); -1 where no row
+// holds a cluster index (the offsets were validated by k_grid).
+__global__ __launch_bounds__(kGridBlock) void k_rowmap(DevEvent ev, KParams kp, Scratch sc,
+                                                      MergeScratch ms) {
+  if (event_bad(sc.counters)) return;
+  const int rs = blockIdx.x;
+  const int a = ev.ro[rs], b = ev.ro[rs + 1];
+  for (int c = a + threadIdx.x; c < b; c += kGridBlock) ms.rowslot[c] = rs;
+}
+
+// The refit of one list (path order): the seed circle of the first run of
+// three or more consecutive clusters of one sector with increasing rows (its
+// first min(m, seed_window)), an outward filter to the end of the list, an
+// inward fit from the last cluster with a fresh covariance over the whole
+// list; frames change by rotations of whole sector widths; a cluster whose
+// step fails is skipped.  P = x, state at the innermost fitted cluster,
+// chi^2, ndf (all 0 and frame -1 if the refit fails).
+__device__ void refit_list(const int32_t* L, int n, const DevEvent& ev, const KParams& kp,
+                           const MergeScratch& ms, const float* s_x, float* P, int32_t* frame) {
+  const int nr = kp.n_rows, N = ev.n_clusters;
+  for (int i = 0; i < 8; ++i) P[i] = 0.f;
+  *frame = -1;
+  if (n < 3) return;
+  auto slot_row = [&](int j, int& sl, int& row) {
+    const int c = L[j];
+    const int rs = (c >= 0 && c < N) ? ms.rowslot[c] : -1;
+    sl = rs >= 0 ? rs / nr : -1;
+    row = rs >= 0 ? rs - sl * nr : -1;
+  };
+  // all clusters known; several sectors need ids of the 2 x 18 layout
+  int s0, r0;
+  slot_row(0, s0, r0);
+  bool ok = s0 >= 0, multi = false;
+  for (int j = 1; j < n && ok; ++j) {
+    int sl, row;
+    slot_row(j, sl, row);
+    ok = sl >= 0;
+    multi |= sl != s0;
+  }
+  if (ok && multi)
+    for (int j = 0; j < n && ok; ++j) {
+      int sl, row;
+      slot_row(j, sl, row);
+      const int ph = ev.sector_id[sl];
+      ok = ph >= 0 && ph < kLayoutSectors;
+    }
+  if (!ok) return;
+  // the seed run
+  int i0 = -1;
+  {
+    int sa, ra, sb, rb;
+    slot_row(0, sa, ra);
+    slot_row(1, sb, rb);
+    for (int i = 0; i + 2 < n; ++i) {
+      int sc2, rc;
+      slot_row(i + 2, sc2, rc);
+      if (sb == sa && sc2 == sa && ra < rb && rb < rc) {
+        i0 = i;
+        break;
+      }
+      sa = sb; ra = rb; sb = sc2; rb = rc;
+    }
+  }
+  if (i0 < 0) return;
+  int sl0, rw0;
+  slot_row(i0, sl0, rw0);
+  int m = 1, prow = rw0;
+  while (i0 + m < n && m < kp.seed_window) {
+    int sl, row;
+    slot_row(i0 + m, sl, row);
+    if (sl != sl0 || !(row > prow)) break;
+    prow = row;
+    ++m;
+  }
+  const int ia = i0, ib = i0 + m / 2, ie = i0 + m - 1;
+  int sx, ra_, rb_, re_;
+  slot_row(ia, sx, ra_);
+  slot_row(ib, sx, rb_);
+  slot_row(ie, sx, re_);
+  KState s;
+  seed3(s, s_x[ra_], ev.y[L[ia]], ev.z[L[ia]], s_x[rb_], ev.y[L[ib]], s_x[re_], ev.y[L[ie]],
+        ev.z[L[ie]], kp);
+  if (fabsf(s.sp) > kp.max_sinphi) return;
+  // outward filter
+  int fr = sl0, last = i0;
+  for (int j = i0 + 1; j < n; ++j) {
+    int sl, row;
+    slot_row(j, sl, row);
+    KState t = s;
+    if (sl != fr && !rotate_steps(t, frame_steps(ev.sector_id[fr], ev.sector_id[sl]), kp)) continue;
+    if (!propagate(t, s_x[row], kp)) continue;
+    kf_update(t, ev.y[L[j]], ev.z[L[j]], kp);
+    s = t;
+    fr = sl;
+    last = j;
+  }
+  // inward fit from the last cluster, fresh covariance
+  int sl_l, row_l;
+  slot_row(last, sl_l, row_l);
+  KState w;
+  w.x = s_x[row_l];
+  w.y = ev.y[L[last]];
+  w.z = ev.z[L[last]];
+  w.sp = s.sp;
+  w.tl = s.tl;
+  w.qpt = s.qpt;
+  reset_cov(w.C, kp);
+  float chi2 = 0.f;
+  int nn = 1, ifr = sl_l;
+  float o[6] = {w.x, w.y, w.z, w.sp, w.tl, w.qpt};
+  for (int j = last - 1; j >= 0; --j) {
+    int sl, row;
+    slot_row(j, sl, row);
+    KState t = w;
+    if (sl != fr && !rotate_steps(t, frame_steps(ev.sector_id[fr], ev.sector_id[sl]), kp)) continue;
+    if (!propagate(t, s_x[row], kp)) continue;
+    chi2 += kf_update(t, ev.y[L[j]], ev.z[L[j]], kp);
+    w = t;
+    fr = sl;
+    ++nn;
+    ifr = sl;
+    o[0] = w.x; o[1] = w.y; o[2] = w.z; o[3] = w.sp; o[4] = w.tl; o[5] = w.qpt;
+  }
+  if (nn < 3) return;
+  for (int i = 0; i < 6; ++i) P[i] = o[i];
+  P[6] = chi2;
+  P[7] = (float)(2 * nn - 5);
+  *frame = ev.sector_id[ifr];
+}
+
+// One lane per list.  n_lists is read from n_dev if given (the merger's own
+// lists), else n_host with list entries clamped to [0, n_entries).
+__global__ __launch_bounds__(kGridBlock) void k_refit(DevEvent ev, KParams kp, Scratch sc,
+                                                      MergeScratch ms, const int32_t* n_dev,
+                                                      int n_host, int n_entries,
+                                                      const int32_t* offsets,
+                                                      const int32_t* clusters, float* par,
+                                                      int32_t* frame, int32_t* meta_frame) {
+  __shared__ float s_x[TPC_MAX_ROWS];
+  for (int i = threadIdx.x; i < kp.n_rows; i += kGridBlock) s_x[i] = kp.row_x[i];
+  __syncthreads();
+  if (event_bad(sc.counters)) return;
+  if (n_dev && __builtin_nontemporal_load(&ms.counters[C_ERR]) != 0) return;
+  const int n = n_dev ? *n_dev : n_host;
+  for (int k = blockIdx.x * kGridBlock + threadIdx.x; k < n; k += gridDim.x * kGridBlock) {
+    int a = offsets[k], b = offsets[k + 1];
+    if (!n_dev) {
+      a = clampi(a, 0, n_entries);
+      b = clampi(b, a, n_entries);
+    }
+    float P[8];
+    int32_t f;
+    refit_list(clusters + a, b - a, ev, kp, ms, s_x, P, &f);
+    for (int i = 0; i < 8; ++i) par[(size_t)k * 8 + i] = P[i];
+    if (frame) frame[k] = f;
+    if (meta_frame && f >= 0) meta_frame[(size_t)k * 5] = f;
   }
 }
 
@@ -2095,8 +2553,10 @@ static inline int wave_blocks(int64_t T) {
 
 const char* const kKernelNames[K_NUM] = {
     "k_zero", "k_grid", "k_nf", "k_evo", "k_scan_rows", "k_seed_write", "k_construct",
-    "k_own", "k_tl_reduce", "k_tl_scan", "k_output", "k_pro_init", "k_prolong", "k_pro_own",
-    "k_pro_reduce", "k_pro_scan", "k_pro_output"};
+    "k_own", "k_tl_reduce", "k_tl_scan", "k_output", "k_pro_init", "k_ends", "k_prolong",
+    "k_pro_own", "k_pro_reduce", "k_pro_scan", "k_pro_output", "k_mrg_init", "k_mrg_match",
+    "k_mrg_link", "k_mrg_chain", "k_mrg_reduce", "k_mrg_scan", "k_mrg_write", "k_rowmap",
+    "k_refit"};
 
 hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& sc,
                          const Outputs& out, int upto, hipStream_t st, const KernelTimer* tm,
@@ -2114,6 +2574,7 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
   pre(K_GRID);
   hipLaunchKernelGGL(k_grid, dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc, out.cluster_track);
   post(K_GRID);
+  if (upto <= STAGE_GRID) return hipGetLastError();
   pre(K_NF);
   if (kp.nf_dense)
     hipLaunchKernelGGL((k_nf<kNfCapLarge, kNfListLarge>), dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc);
@@ -2169,7 +2630,7 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
 }
 
 hipError_t enqueue_global(const DevEvent& ev, const KParams& kp, const Scratch& sc,
-                          const Outputs& out, const GlobalScratch& gs, const ProOutputs& po,
+                          const Outputs& out, const GlobalScratch& gs, const ProOutputs* po,
                           hipStream_t st, const KernelTimer* tm) {
   auto pre = [&](int k) {
     if (tm && (tm->mask >> k & 1u)) (void)hipEventRecord(tm->ev[k][0], st);
@@ -2185,6 +2646,10 @@ hipError_t enqueue_global(const DevEvent& ev, const KParams& kp, const Scratch& 
   pre(K_PRO_INIT);
   hipLaunchKernelGGL(k_pro_init, dim3(cb), dim3(kGridBlock), 0, st, ev, sc, gs);
   post(K_PRO_INIT);
+  pre(K_ENDS);
+  hipLaunchKernelGGL(k_ends, dim3(qb), dim3(kGridBlock), 0, st, kp, sc, gs);
+  post(K_ENDS);
+  if (!po) return hipGetLastError();
   pre(K_PROLONG);
   hipLaunchKernelGGL(k_prolong, dim3(qb), dim3(kGridBlock), 0, st, ev, kp, sc, gs,
                      (const int32_t*)out.cluster_track);
@@ -2206,12 +2671,135 @@ hipError_t enqueue_global(const DevEvent& ev, const KParams& kp, const Scratch& 
   hipLaunchKernelGGL(k_tl_reduce, dim3(spans), dim3(kScanBlock), 0, st, ps, 1);
   post(K_PRO_REDUCE);
   pre(K_PRO_SCAN);
-  hipLaunchKernelGGL(k_tl_scan, dim3(spans), dim3(kScanBlock), 0, st, ps, 1, po.cap,
-                     po.cap_clusters);
+  hipLaunchKernelGGL(k_tl_scan, dim3(spans), dim3(kScanBlock), 0, st, ps, 1, po->cap,
+                     po->cap_clusters);
   post(K_PRO_SCAN);
   pre(K_PRO_OUTPUT);
-  hipLaunchKernelGGL(k_pro_output, dim3(wave_blocks(Q)), dim3(kGridBlock), 0, st, ev, sc, gs, po);
+  hipLaunchKernelGGL(k_pro_output, dim3(wave_blocks(Q)), dim3(kGridBlock), 0, st, ev, sc, gs,
+                     *po);
   post(K_PRO_OUTPUT);
+  return hipGetLastError();
+}
+
+size_t merge_bytes(int64_t N, int64_t S, int64_t T) {
+  size_t b = 0;
+  b += align_up(sizeof(int32_t) * C_COUNT);
+  b += align_up(sizeof(int32_t) * (S + 1));
+  b += align_up(sizeof(float4) * 2 * T);
+  b += align_up(sizeof(int32_t) * T) * 2;
+  b += align_up(sizeof(unsigned long long) * T);
+  b += align_up(sizeof(int32_t) * T) * 6;
+  b += align_up(sizeof(int32_t) * (2 * ((T + kSpan - 1) / kSpan) + 2));
+  b += align_up(sizeof(int32_t) * (T + 1));
+  b += align_up(sizeof(int32_t) * (N > 0 ? N : 1));
+  return b;
+}
+
+void merge_carve(void* base, int64_t N, int64_t S, int64_t T, MergeScratch* ms) {
+  char* p = (char*)base;
+  auto take = [&](size_t bytes) {
+    void* r = p;
+    p += align_up(bytes);
+    return r;
+  };
+  ms->counters = (int32_t*)take(sizeof(int32_t) * C_COUNT);
+  ms->first = (int32_t*)take(sizeof(int32_t) * (S + 1));
+  ms->sum = (float4*)take(sizeof(float4) * 2 * T);
+  ms->next = (int32_t*)take(sizeof(int32_t) * T);
+  ms->best = (int32_t*)take(sizeof(int32_t) * T);
+  ms->prev_key = (unsigned long long*)take(sizeof(unsigned long long) * T);
+  ms->prev = (int32_t*)take(sizeof(int32_t) * T);
+  ms->cnt = (int32_t*)take(sizeof(int32_t) * T);
+  ms->nseg = (int32_t*)take(sizeof(int32_t) * T);
+  ms->kept = (int32_t*)take(sizeof(int32_t) * T);
+  ms->idx = (int32_t*)take(sizeof(int32_t) * T);
+  ms->off = (int32_t*)take(sizeof(int32_t) * T);
+  ms->span_sum = (int32_t*)take(sizeof(int32_t) * (2 * ((T + kSpan - 1) / kSpan) + 2));
+  ms->loff = (int32_t*)take(sizeof(int32_t) * (T + 1));
+  ms->rowslot = (int32_t*)take(sizeof(int32_t) * (N > 0 ? N : 1));
+}
+
+hipError_t enqueue_merge(const DevEvent& ev, const KParams& kp, const Scratch& sc,
+                         const Outputs& out, const GlobalScratch& gs, const ProOutputs* po,
+                         const MergeScratch& ms, const MergeOutputs& mo, hipStream_t st,
+                         const KernelTimer* tm) {
+  auto pre = [&](int k) {
+    if (tm && (tm->mask >> k & 1u)) (void)hipEventRecord(tm->ev[k][0], st);
+  };
+  auto post = [&](int k) {
+    if (tm && (tm->mask >> k & 1u)) (void)hipEventRecord(tm->ev[k][1], st);
+  };
+  const int64_t T = sc.cap_tl;
+  const int tb = (int)std::min<int64_t>(std::max<int64_t>((T + kGridBlock - 1) / kGridBlock, 1),
+                                        65535);
+  const int R = ev.n_sectors * kp.n_rows;
+  pre(K_MRG_INIT);
+  hipLaunchKernelGGL(k_mrg_init, dim3(tb), dim3(kGridBlock), 0, st, ev, kp, sc, gs, ms);
+  post(K_MRG_INIT);
+  pre(K_MRG_MATCH);
+  hipLaunchKernelGGL(k_mrg_match, dim3(tb), dim3(kGridBlock), 0, st, ev, kp, sc, gs, ms);
+  post(K_MRG_MATCH);
+  pre(K_MRG_LINK);
+  hipLaunchKernelGGL(k_mrg_link, dim3(tb), dim3(kGridBlock), 0, st, sc, ms);
+  post(K_MRG_LINK);
+  pre(K_MRG_CHAIN);
+  hipLaunchKernelGGL(k_mrg_chain, dim3(tb), dim3(kGridBlock), 0, st, sc, gs, ms, out,
+                     po ? 1 : 0);
+  post(K_MRG_CHAIN);
+  // numbering of the chains: the selection's scan over tracks
+  Scratch ps = sc;
+  ps.counters = ms.counters;
+  ps.owned = ms.cnt;
+  ps.kept = ms.kept;
+  ps.trk_idx = ms.idx;
+  ps.trk_off = ms.off;
+  ps.span_sum = ms.span_sum;
+  const int spans = (int)((T + kSpan - 1) / kSpan);
+  pre(K_MRG_REDUCE);
+  hipLaunchKernelGGL(k_tl_reduce, dim3(spans), dim3(kScanBlock), 0, st, ps, 1);
+  post(K_MRG_REDUCE);
+  pre(K_MRG_SCAN);
+  hipLaunchKernelGGL(k_tl_scan, dim3(spans), dim3(kScanBlock), 0, st, ps, 1, mo.cap,
+                     mo.cap_clusters);
+  post(K_MRG_SCAN);
+  const ProOutputs pz{0, 0, nullptr, nullptr, nullptr};
+  pre(K_MRG_WRITE);
+  hipLaunchKernelGGL(k_mrg_write, dim3(wave_blocks(T)), dim3(kGridBlock), 0, st, ev, kp, sc, gs,
+                     ms, out, po ? *po : pz, po ? 1 : 0, mo);
+  post(K_MRG_WRITE);
+  pre(K_ROWMAP);
+  hipLaunchKernelGGL(k_rowmap, dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc, ms);
+  post(K_ROWMAP);
+  pre(K_REFIT);
+  hipLaunchKernelGGL(k_refit, dim3(tb), dim3(kGridBlock), 0, st, ev, kp, sc, ms,
+                     (const int32_t*)&ms.counters[C_TRACKS], 0, 0, (const int32_t*)ms.loff,
+                     (const int32_t*)mo.cluster, mo.par, (int32_t*)nullptr, mo.meta);
+  post(K_REFIT);
+  return hipGetLastError();
+}
+
+hipError_t enqueue_refit(const DevEvent& ev, const KParams& kp, const Scratch& sc,
+                         const MergeScratch& ms, int32_t n_lists, int32_t n_entries,
+                         const int32_t* offsets, const int32_t* clusters, float* par,
+                         int32_t* frame, hipStream_t st, const KernelTimer* tm) {
+  auto pre = [&](int k) {
+    if (tm && (tm->mask >> k & 1u)) (void)hipEventRecord(tm->ev[k][0], st);
+  };
+  auto post = [&](int k) {
+    if (tm && (tm->mask >> k & 1u)) (void)hipEventRecord(tm->ev[k][1], st);
+  };
+  const int R = ev.n_sectors * kp.n_rows;
+  pre(K_ROWMAP);
+  hipLaunchKernelGGL(k_rowmap, dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc, ms);
+  post(K_ROWMAP);
+  if (n_lists > 0) {
+    const int lb = std::min((n_lists + kGridBlock - 1) / kGridBlock, 65535);
+    pre(K_REFIT);
+    hipLaunchKernelGGL(k_refit, dim3(lb), dim3(kGridBlock), 0, st, ev, kp, sc, ms,
+                       (const int32_t*)nullptr, n_lists, n_entries, offsets, clusters, par,
+                       frame, (int32_t*)nullptr);
+    post(K_REFIT);
+  }
   return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ struct tpc_ctx {
   size_t budget = 0;        // 0 = unlimited
   void* arena = nullptr;
   size_t arena_bytes = 0;
-  int32_t* h_counters = nullptr;  // pinned: sector tracker's, then global tracking's counters
+  int32_t* h_counters = nullptr;  // pinned: sector tracker's, global tracking's, merger's counters
   void* glob_arena = nullptr;     // global tracking scratch
   size_t glob_bytes = 0;
   int64_t learned_tl = 0;   // tracklet reservation learned from overflows
@@ -218,8 +218,9 @@ int ensure_arena(tpc_ctx* ctx, int64_t N, int64_t R, int64_t T, hipStream_t st) 
   return TPC_OK;
 }
 
-int ensure_glob(tpc_ctx* ctx, int64_t N, int64_t T, hipStream_t st) {
-  size_t need = global_bytes(N, T);
+// Global tracking scratch, followed by the merger's when with_merge.
+int ensure_glob(tpc_ctx* ctx, int64_t N, int64_t S, int64_t T, bool with_merge, hipStream_t st) {
+  size_t need = global_bytes(N, T) + (with_merge ? merge_bytes(N, S, T) : 0);
   if (need <= ctx->glob_bytes) return TPC_OK;
   size_t want = need + need / 4;
   if (ctx->budget && ctx->arena_bytes + want > ctx->budget) want = need;
@@ -250,7 +251,8 @@ int ensure_glob(tpc_ctx* ctx, int64_t N, int64_t T, hipStream_t st) {
 // the event is run once more (results do not depend on the reservation).
 int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float bz,
               const tpc_params* p, const Outputs& out, int upto, hipStream_t st,
-              Scratch* sc_out, const ProOutputs* po = nullptr) {
+              Scratch* sc_out, const ProOutputs* po = nullptr, const MergeOutputs* mo = nullptr,
+              float merge_chi2 = 0.f) {
   int rc = validate(ev, geo, p);
   if (rc) return rc;
   if (!std::isfinite(bz)) return fail(TPC_ERR_INVALID_ARG, "bz must be finite");
@@ -267,7 +269,12 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
     const double w = 2.0 * std::atan((double)geo->tan_half_angle);
     kp.rot_c = (float)std::cos(w);
     kp.rot_s = (float)std::sin(w);
+    for (int k = -9; k <= 8; ++k) {
+      kp.rot_tab[k + 9][0] = (float)std::cos(k * w);
+      kp.rot_tab[k + 9][1] = (float)std::sin(k * w);
+    }
   }
+  kp.merge_chi2 = merge_chi2;
   const DevEvent dev = make_devevent(ev);
   int64_t T = default_tracklets(ctx, N, p);
   for (int attempt = 0; attempt < 2; ++attempt) {
@@ -276,18 +283,28 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
     Scratch sc;
     scratch_carve(ctx->arena, N, R, T, &sc);
     GlobalScratch gs{};
-    if (po) {
-      rc = ensure_glob(ctx, N, T, st);
+    MergeScratch ms{};
+    if (po || mo) {
+      rc = ensure_glob(ctx, N, ev->n_sectors, T, mo != nullptr, st);
       if (rc) return rc;
       global_carve(ctx->glob_arena, N, T, &sc.ends, &gs);
+      if (mo)
+        merge_carve((char*)ctx->glob_arena + global_bytes(N, T), N, ev->n_sectors, T, &ms);
     }
     const bool timed = ctx->timer.mask != 0;
     e = enqueue_event(dev, kp, sc, out, upto, st, timed ? &ctx->timer : nullptr);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
-    if (po) {
-      e = enqueue_global(dev, kp, sc, out, gs, *po, st, timed ? &ctx->timer : nullptr);
+    if (po || mo) {
+      e = enqueue_global(dev, kp, sc, out, gs, po, st, timed ? &ctx->timer : nullptr);
       if (e != hipSuccess) return hip_fail(e, "kernel launch (global tracking)");
       e = hipMemcpyAsync(ctx->h_counters + C_COUNT, gs.counters, sizeof(int32_t) * C_COUNT,
+                         hipMemcpyDeviceToHost, st);
+      if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(counters)");
+    }
+    if (mo) {
+      e = enqueue_merge(dev, kp, sc, out, gs, po, ms, *mo, st, timed ? &ctx->timer : nullptr);
+      if (e != hipSuccess) return hip_fail(e, "kernel launch (merger)");
+      e = hipMemcpyAsync(ctx->h_counters + 2 * C_COUNT, ms.counters, sizeof(int32_t) * C_COUNT,
                          hipMemcpyDeviceToHost, st);
       if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(counters)");
     }
@@ -312,7 +329,8 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
       continue;
     }
     if (timed) {
-      const int last = po ? K_PRO_OUTPUT
+      const int last = mo ? K_REFIT
+                       : po ? K_PRO_OUTPUT
                        : upto >= STAGE_ALL ? K_OUTPUT
                        : upto >= STAGE_TRACKLETS ? K_CONSTRUCT
                        : upto >= STAGE_SEEDS ? K_SEED_WRITE : K_EVO;
@@ -651,7 +669,7 @@ int tpc_ctx_create(int device, size_t hbm_budget_bytes, tpc_ctx** out) {
   c->device = device;
   c->budget = hbm_budget_bytes;
   tpc_tuning_default(&c->tuning);
-  e = hipHostMalloc((void**)&c->h_counters, sizeof(int32_t) * 2 * C_COUNT, hipHostMallocDefault);
+  e = hipHostMalloc((void**)&c->h_counters, sizeof(int32_t) * 3 * C_COUNT, hipHostMallocDefault);
   if (e != hipSuccess) {
     delete c;
     return hip_fail(e, "hipHostMalloc");
@@ -768,24 +786,18 @@ int tpc_track_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, 
   return TPC_OK;
 }
 
-int tpc_track_event_global(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo,
-                           float bz_tesla, const tpc_params* params, tpc_tracks* out,
-                           tpc_prolongations* pro, void* hip_stream) {
-  if (!ctx) return fail(TPC_ERR_INVALID_ARG, "ctx is null");
-  int rc0 = check_outputs(ev, out);
-  if (rc0) return rc0;
+static int check_pro(const tpc_prolongations* pro) {
   if (!pro || !pro->n || !pro->n_clusters)
     return fail(TPC_ERR_INVALID_ARG, "pro or its size pointers are null");
   if (pro->cap < 0 || pro->cap_clusters < 0)
     return fail(TPC_ERR_INVALID_ARG, "negative prolongation capacity");
   if ((pro->cap > 0 && (!pro->par || !pro->meta)) || (pro->cap_clusters > 0 && !pro->cluster))
     return fail(TPC_ERR_INVALID_ARG, "prolongation output array is null");
-  Outputs o{out->cap_tracks, out->cap_track_clusters, out->track_par, out->track_meta,
-            out->track_cluster, out->cluster_track};
-  ProOutputs po{pro->cap, pro->cap_clusters, pro->par, pro->meta, pro->cluster};
-  hipStream_t st = (hipStream_t)hip_stream;
-  int rc = run_event(ctx, ev, geo, bz_tesla, params, o, STAGE_ALL, st, nullptr, &po);
-  if (rc) return rc;
+  return TPC_OK;
+}
+
+// Sizes of the tracks and prolongations after global tracking.
+static int global_sizes(tpc_ctx* ctx, tpc_tracks* out, tpc_prolongations* pro) {
   const int32_t* c = ctx->h_counters;
   const int32_t* g = ctx->h_counters + C_COUNT;
   *out->n_tracks = c[C_TRACKS];
@@ -800,6 +812,130 @@ int tpc_track_event_global(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry
   if (g[C_ERR] & E_CAPACITY)
     return fail(TPC_ERR_CAPACITY, "need %d prolongations / %d clusters, have %d / %d",
                 g[C_TRACKS], g[C_TRACK_CLUSTERS], pro->cap, pro->cap_clusters);
+  return TPC_OK;
+}
+
+int tpc_track_event_global(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo,
+                           float bz_tesla, const tpc_params* params, tpc_tracks* out,
+                           tpc_prolongations* pro, void* hip_stream) {
+  if (!ctx) return fail(TPC_ERR_INVALID_ARG, "ctx is null");
+  int rc0 = check_outputs(ev, out);
+  if (rc0) return rc0;
+  rc0 = check_pro(pro);
+  if (rc0) return rc0;
+  Outputs o{out->cap_tracks, out->cap_track_clusters, out->track_par, out->track_meta,
+            out->track_cluster, out->cluster_track};
+  ProOutputs po{pro->cap, pro->cap_clusters, pro->par, pro->meta, pro->cluster};
+  hipStream_t st = (hipStream_t)hip_stream;
+  int rc = run_event(ctx, ev, geo, bz_tesla, params, o, STAGE_ALL, st, nullptr, &po);
+  if (rc) return rc;
+  return global_sizes(ctx, out, pro);
+}
+
+int tpc_track_event_merged(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo,
+                           float bz_tesla, const tpc_params* params, float merge_chi2,
+                           tpc_tracks* out, tpc_prolongations* pro, tpc_merged* mrg,
+                           void* hip_stream) {
+  if (!ctx) return fail(TPC_ERR_INVALID_ARG, "ctx is null");
+  int rc0 = check_outputs(ev, out);
+  if (rc0) return rc0;
+  if (pro) {
+    rc0 = check_pro(pro);
+    if (rc0) return rc0;
+  }
+  if (!mrg || !mrg->n || !mrg->n_clusters)
+    return fail(TPC_ERR_INVALID_ARG, "mrg or its size pointers are null");
+  if (mrg->cap < 0 || mrg->cap_clusters < 0)
+    return fail(TPC_ERR_INVALID_ARG, "negative merged-track capacity");
+  if ((mrg->cap > 0 && (!mrg->par || !mrg->meta)) || (mrg->cap_clusters > 0 && !mrg->cluster) ||
+      (out->cap_tracks > 0 && !mrg->track_merged))
+    return fail(TPC_ERR_INVALID_ARG, "merged-track output array is null");
+  if (!(merge_chi2 >= 0.f) || !std::isfinite(merge_chi2))
+    return fail(TPC_ERR_INVALID_ARG, "merge_chi2 must be finite and >= 0");
+  Outputs o{out->cap_tracks, out->cap_track_clusters, out->track_par, out->track_meta,
+            out->track_cluster, out->cluster_track};
+  ProOutputs po{pro ? pro->cap : 0, pro ? pro->cap_clusters : 0, pro ? pro->par : nullptr,
+                pro ? pro->meta : nullptr, pro ? pro->cluster : nullptr};
+  MergeOutputs mo{mrg->cap, mrg->cap_clusters, mrg->par, mrg->meta, mrg->cluster,
+                  mrg->track_merged};
+  hipStream_t st = (hipStream_t)hip_stream;
+  int rc = run_event(ctx, ev, geo, bz_tesla, params, o, STAGE_ALL, st, nullptr,
+                     pro ? &po : nullptr, &mo, merge_chi2);
+  if (rc) return rc;
+  *mrg->n = 0;
+  *mrg->n_clusters = 0;
+  if (pro) {
+    rc = global_sizes(ctx, out, pro);
+    if (rc) return rc;
+  } else {
+    const int32_t* c = ctx->h_counters;
+    *out->n_tracks = c[C_TRACKS];
+    *out->n_track_clusters = c[C_TRACK_CLUSTERS];
+    if (c[C_ERR] & E_CAPACITY)
+      return fail(TPC_ERR_CAPACITY, "need %d tracks / %d track clusters, have %d / %d",
+                  c[C_TRACKS], c[C_TRACK_CLUSTERS], out->cap_tracks, out->cap_track_clusters);
+  }
+  const int32_t* m = ctx->h_counters + 2 * C_COUNT;
+  *mrg->n = m[C_TRACKS];
+  *mrg->n_clusters = m[C_TRACK_CLUSTERS];
+  if (m[C_ERR] & E_CAPACITY)
+    return fail(TPC_ERR_CAPACITY, "need %d merged tracks / %d clusters, have %d / %d",
+                m[C_TRACKS], m[C_TRACK_CLUSTERS], mrg->cap, mrg->cap_clusters);
+  return TPC_OK;
+}
+
+int tpc_refit(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float bz_tesla,
+              const tpc_params* params, int32_t n_lists, int32_t n_entries,
+              const int32_t* offsets, const int32_t* clusters, float* par,
+              int32_t* frame_sector, void* hip_stream) {
+  if (!ctx) return fail(TPC_ERR_INVALID_ARG, "ctx is null");
+  int rc = validate(ev, geo, params);
+  if (rc) return rc;
+  if (!std::isfinite(bz_tesla)) return fail(TPC_ERR_INVALID_ARG, "bz must be finite");
+  if (n_lists < 0 || n_entries < 0) return fail(TPC_ERR_INVALID_ARG, "negative list sizes");
+  if (n_lists > 0 && (!offsets || !par || (n_entries > 0 && !clusters)))
+    return fail(TPC_ERR_INVALID_ARG, "offsets, clusters or par is null");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  const int64_t N = ev->n_clusters, R = (int64_t)ev->n_sectors * geo->n_rows, T = 1;
+  hipStream_t st = (hipStream_t)hip_stream;
+  rc = ensure_arena(ctx, N, R, T, st);
+  if (rc) return rc;
+  rc = ensure_glob(ctx, N, ev->n_sectors, T, true, st);
+  if (rc) return rc;
+  KParams kp = make_kparams(geo, bz_tesla, params);
+  kp.bin_occupancy = ctx->tuning.bin_occupancy;
+  {
+    const double w = 2.0 * std::atan((double)geo->tan_half_angle);
+    for (int k = -9; k <= 8; ++k) {
+      kp.rot_tab[k + 9][0] = (float)std::cos(k * w);
+      kp.rot_tab[k + 9][1] = (float)std::sin(k * w);
+    }
+  }
+  Scratch sc;
+  scratch_carve(ctx->arena, N, R, T, &sc);
+  GlobalScratch gs{};
+  MergeScratch ms{};
+  global_carve(ctx->glob_arena, N, T, &sc.ends, &gs);
+  merge_carve((char*)ctx->glob_arena + global_bytes(N, T), N, ev->n_sectors, T, &ms);
+  const DevEvent dev = make_devevent(ev);
+  Outputs o{0, 0, nullptr, nullptr, nullptr, nullptr};
+  e = enqueue_event(dev, kp, sc, o, STAGE_GRID, st);
+  if (e == hipSuccess)
+    e = enqueue_refit(dev, kp, sc, ms, n_lists, n_entries, offsets, clusters, par, frame_sector,
+                      st);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch (refit)");
+  e = hipMemcpyAsync(ctx->h_counters, sc.counters, sizeof(int32_t) * C_COUNT,
+                     hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(counters)");
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  const int32_t* c = ctx->h_counters;
+  if (c[C_ERR] & E_OFFSETS)
+    return fail(TPC_ERR_INVALID_ARG, "row_offsets are not a valid non-decreasing partition "
+                                     "of [0, n_clusters]");
+  if (c[C_ERR] & E_NONFINITE)
+    return fail(TPC_ERR_INVALID_ARG, "%d clusters have non-finite coordinates", c[C_NONFINITE]);
   return TPC_OK;
 }
 

@@ -184,3 +184,63 @@ def prolongation_report(e: synth.Event, res: dict, pro: dict, min_clusters: int 
                 short_piece_clusters=n_short,
                 short_piece_recovered=got / max(1, n_short),
                 prolongation_purity=right / max(1, total_pro))
+
+
+def merged_report(e: synth.Event, merged: dict, min_clusters: int = 30,
+                  purity: float = 0.9) -> dict:
+    """Quality of joined (merged) tracks against the truth.
+
+    A particle is findable if it has at least `min_clusters` clusters in the
+    event; it is found if a joined track with at least `purity` of its list
+    on the particle carries it; further such tracks are split tracks.
+    Resolution: for the first joined track of each found particle whose
+    refit succeeded and whose list starts on the particle, its parameters
+    (at the innermost fitted cluster, the list's first, in that sector's
+    frame) minus the truth there, as half-widths of the central 68%."""
+    mc = np.asarray(e.mc_track)
+    sig = mc >= 0
+    lab_all, cnt_all = np.unique(mc[sig], return_counts=True)
+    findable = set(lab_all[cnt_all >= min_clusters].tolist())
+    meta = np.asarray(merged["meta"]).reshape(-1, 5)
+    par = np.asarray(merged["par"], np.float64).reshape(-1, 8)
+    cl_all = np.asarray(merged["cluster"])
+    slot = e.row_of() // synth.N_ROWS
+    rows = e.row_of() % synth.N_ROWS
+    found, first = set(), []
+    splits = fakes = 0
+    for k in range(meta.shape[0]):
+        cl = cl_all[meta[k, 3]:meta[k, 3] + meta[k, 2]]
+        lab, c = np.unique(mc[cl], return_counts=True)
+        j = int(np.argmax(c))
+        if lab[j] < 0 or c[j] < purity * cl.shape[0]:
+            fakes += 1
+            continue
+        if lab[j] in found:
+            splits += 1
+            continue
+        found.add(int(lab[j]))
+        c0 = int(cl[0])
+        if par[k, 7] > 0 and mc[c0] == lab[j] and \
+                par[k, 0] == np.float32(synth.ROW_X[rows[c0]]) and \
+                meta[k, 0] == e.sector_id[slot[c0]]:
+            first.append((k, c0))
+    n_found = len(found & findable)
+    out = dict(findable=len(findable), found=n_found,
+               efficiency=n_found / max(1, len(findable)), split=splits,
+               split_rate=splits / max(1, len(found)), fakes=fakes,
+               fake_rate=fakes / max(1, meta.shape[0]), tracks=int(meta.shape[0]),
+               mean_clusters=float(np.mean(meta[:, 2])) if meta.shape[0] else 0.0)
+    if first:
+        k = np.array([a for a, _ in first])
+        c0 = np.array([b for _, b in first])
+        p = mc[c0]
+        q_pt = e.track_q[p] / e.track_pt[p]
+        out["resolution"] = dict(
+            tracks=int(k.shape[0]),
+            y_cm=_w68(par[k, 1] - e.y_true[c0]),
+            z_cm=_w68(par[k, 2] - e.z_true[c0]),
+            sinphi=_w68(par[k, 3] - _true_sinphi(e, c0, slot[c0])),
+            tanl=_w68(par[k, 4] - e.track_tanl[p]),
+            qpt_rel=_w68((par[k, 5] - q_pt) / q_pt),
+            charge_wrong=float(np.mean(np.sign(par[k, 5]) != np.sign(q_pt))))
+    return out

@@ -76,8 +76,16 @@ class Prolongations(C.Structure):
                 ("cluster", C.c_void_p)]
 
 
+class Merged(C.Structure):
+    _fields_ = [("cap", C.c_int32), ("cap_clusters", C.c_int32), ("n", C.POINTER(C.c_int32)),
+                ("n_clusters", C.POINTER(C.c_int32)), ("par", C.c_void_p), ("meta", C.c_void_p),
+                ("cluster", C.c_void_p), ("track_merged", C.c_void_p)]
+
+
+MERGE_CHI2 = 25.0   # joins: chi^2(5) <= 25, a 1e-4 tail for the same particle
+
 EXPORTS = ["tpc_params_default", "tpc_validate", "tpc_ctx_create", "tpc_ctx_destroy",
-           "tpc_track_event", "tpc_track_event_global", "tpc_track_batch", "tpc_debug_links", "tpc_debug_tracklets", "tpc_last_error",
+           "tpc_track_event", "tpc_track_event_global", "tpc_track_event_merged", "tpc_refit", "tpc_track_batch", "tpc_debug_links", "tpc_debug_tracklets", "tpc_last_error",
            "tpc_kernel_count", "tpc_kernel_name", "tpc_ctx_set_timing", "tpc_ctx_get_stats",
            "tpc_ctx_reset_stats", "tpc_tuning_default", "tpc_ctx_set_tuning",
            "tpc_ctx_graph_launches", "tpc_server_config_default", "tpc_server_create",
@@ -100,6 +108,12 @@ def _load():
                                   P(Tracks), C.c_void_p]
     L.tpc_track_event_global.argtypes = [C.c_void_p, P(Event), P(Geometry), C.c_float,
                                          P(Params), P(Tracks), P(Prolongations), C.c_void_p]
+    L.tpc_track_event_merged.argtypes = [C.c_void_p, P(Event), P(Geometry), C.c_float,
+                                         P(Params), C.c_float, P(Tracks), P(Prolongations),
+                                         P(Merged), C.c_void_p]
+    L.tpc_refit.argtypes = [C.c_void_p, P(Event), P(Geometry), C.c_float, P(Params), C.c_int32,
+                            C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                            C.c_void_p]
     L.tpc_track_batch.argtypes = [C.c_void_p, P(Event), C.c_int, P(Geometry), C.c_float,
                                   P(Params), P(Tracks), C.c_void_p]
     L.tpc_debug_links.argtypes = [C.c_void_p, P(Event), P(Geometry), P(Params), C.c_void_p,
@@ -298,6 +312,87 @@ class Tracker:
         pro = dict(n=npr.value, n_clusters=npc.value, par=po["par"][:npr.value],
                    meta=po["meta"][:npr.value], cluster=po["cluster"][:npc.value])
         return tracks, pro
+
+    def track_event_merged(self, ev: DeviceEvent, geo: Geometry, bz: float,
+                           params: Params = None, merge_chi2: float = MERGE_CHI2,
+                           use_global: bool = True, cap_merged: int = None,
+                           cap_merged_clusters: int = None, stream=None):
+        """The whole path (with global tracking if use_global), then the track
+        merger with refit.  Returns (tracks, prolongations or None, merged):
+        merged has n, n_clusters, par [n][8], meta [n][5], cluster and
+        track_merged [n_tracks] (device tensors)."""
+        import torch
+        n = ev.n_clusters
+        dev = ev.y.device
+        ct, cc = max(16, n // 40), max(16, n)
+        cp, cpc = max(16, ct), max(16, n // 8)
+        cm = cap_merged if cap_merged is not None else ct
+        cmc = cap_merged_clusters if cap_merged_clusters is not None else max(16, n + n // 8)
+        auto = cap_merged is None and cap_merged_clusters is None
+        for _ in range(3):
+            f32 = dict(dtype=torch.float32, device=dev)
+            i32 = dict(dtype=torch.int32, device=dev)
+            out = dict(track_par=torch.empty((ct, 8), **f32),
+                       track_meta=torch.empty((ct, 4), **i32),
+                       track_cluster=torch.empty(cc, **i32),
+                       cluster_track=torch.empty(max(n, 1), **i32))
+            po = dict(par=torch.empty((cp, 8), **f32), meta=torch.empty((cp, 5), **i32),
+                      cluster=torch.empty(cpc, **i32))
+            mo = dict(par=torch.empty((max(cm, 1), 8), **f32),
+                      meta=torch.empty((max(cm, 1), 5), **i32),
+                      cluster=torch.empty(max(cmc, 1), **i32),
+                      track_merged=torch.empty(ct, **i32))
+            sz = [C.c_int32(0) for _ in range(6)]
+            tr = Tracks(ct, cc, C.pointer(sz[0]), C.pointer(sz[1]), out["track_par"].data_ptr(),
+                        out["track_meta"].data_ptr(), out["track_cluster"].data_ptr(),
+                        out["cluster_track"].data_ptr())
+            pr = Prolongations(cp, cpc, C.pointer(sz[2]), C.pointer(sz[3]), po["par"].data_ptr(),
+                               po["meta"].data_ptr(), po["cluster"].data_ptr())
+            mg = Merged(cm, cmc, C.pointer(sz[4]), C.pointer(sz[5]), mo["par"].data_ptr(),
+                        mo["meta"].data_ptr(), mo["cluster"].data_ptr(),
+                        mo["track_merged"].data_ptr())
+            e = ev.cstruct()
+            rc = lib.tpc_track_event_merged(self._h, C.byref(e), C.byref(geo), float(bz),
+                                            C.byref(params or default_params()),
+                                            float(merge_chi2), C.byref(tr),
+                                            C.byref(pr) if use_global else None, C.byref(mg),
+                                            _stream_handle(stream))
+            if rc == TPC_ERR_CAPACITY and auto:
+                v = [x.value for x in sz]
+                ct, cc = max(ct, v[0] + 16), max(cc, v[1] + 16)
+                cp, cpc = max(cp, v[2] + 16), max(cpc, v[3] + 16)
+                cm, cmc = max(cm, v[4] + 16, ct), max(cmc, v[5] + 16)
+                continue
+            _check(rc)
+            v = [x.value for x in sz]
+            tracks = dict(n_tracks=v[0], n_track_clusters=v[1], track_par=out["track_par"][:v[0]],
+                          track_meta=out["track_meta"][:v[0]],
+                          track_cluster=out["track_cluster"][:v[1]],
+                          cluster_track=out["cluster_track"][:n])
+            pro = dict(n=v[2], n_clusters=v[3], par=po["par"][:v[2]], meta=po["meta"][:v[2]],
+                       cluster=po["cluster"][:v[3]]) if use_global else None
+            merged = dict(n=v[4], n_clusters=v[5], par=mo["par"][:v[4]], meta=mo["meta"][:v[4]],
+                          cluster=mo["cluster"][:v[5]], track_merged=mo["track_merged"][:v[0]])
+            return tracks, pro, merged
+        raise TpcError(TPC_ERR_CAPACITY, "capacity retry failed")
+
+    def refit(self, ev: DeviceEvent, geo: Geometry, bz: float, offsets, clusters,
+              params: Params = None, stream=None):
+        """The merger's refit of cluster lists (device int32 tensors: offsets
+        [n + 1], clusters).  Returns (par [n][8], frame sector_id [n])."""
+        import torch
+        n = int(offsets.shape[0]) - 1
+        dev = ev.y.device
+        par = torch.empty((max(n, 1), 8), dtype=torch.float32, device=dev)
+        fr = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        for a in (offsets, clusters):
+            assert a.is_cuda and a.is_contiguous() and a.dtype == torch.int32
+        e = ev.cstruct()
+        _check(lib.tpc_refit(self._h, C.byref(e), C.byref(geo), float(bz),
+                             C.byref(params or default_params()), n, int(clusters.shape[0]),
+                             offsets.data_ptr(), clusters.data_ptr(), par.data_ptr(),
+                             fr.data_ptr(), _stream_handle(stream)))
+        return par[:n], fr[:n]
 
     def set_tuning(self, **kw):
         """Speed knobs (results never change): use_graph, construct_blocks,

@@ -175,7 +175,8 @@ def test_oracle_and_gpu_library_share_nothing():
 STRUCTS = {  # C type name -> ctypes mirror in the binding
     "tpc_geometry": "Geometry", "tpc_event": "Event", "tpc_params": "Params",
     "tpc_tracks": "Tracks", "tpc_tuning": "Tuning", "tpc_server_config": "ServerConfig",
-    "tpc_server_done": "ServerDone", "tpc_prolongations": "Prolongations"}
+    "tpc_server_done": "ServerDone", "tpc_prolongations": "Prolongations",
+    "tpc_merged": "Merged"}
 
 
 def test_struct_layouts_match_the_header(tmp_path):

@@ -1,0 +1,224 @@
+"""Track merger with refit through the C ABI against the FP64 oracle.
+
+Joined tracks are matched through the sector tracks' one-to-one
+correspondence.  Noiseless tracks that cross a sector edge or the membrane
+must be joined exactly as the oracle joins them, with identical lists and
+refits within 1e-3.  On central events >= 99.5% of the joined tracks must
+join the same sector tracks and >= 99.9% of the list clusters agree both
+ways; refits of identical lists agree within 1e-3 (chi2 within 1e-2).  The
+refit is a function of the cluster list alone (section 3.3): tpc_refit of the
+same list gives bitwise the merger's result, whichever run found the list.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from conftest import event_dict, f32
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import concordance  # noqa: E402
+from paper_1712_09407_amd import synth, tpc  # noqa: E402
+
+THREADS = min(16, os.cpu_count() or 1)
+GEO_T = (synth.ROW_X, synth.TAN_HALF, synth.Z_MAX)
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def tracker():
+    t = tpc.Tracker(0)
+    yield t
+    t.close()
+
+
+@pytest.fixture(scope="module")
+def geo():
+    return tpc.make_geometry(*GEO_T)
+
+
+def params_pair(orc, sigma):
+    g = tpc.default_params(sigma_y=sigma, sigma_z=sigma)
+    o = orc.default_params(**{k: f32(getattr(g, k)) if isinstance(getattr(g, k), float)
+                              else getattr(g, k) for k, _ in orc.Params._fields_})
+    return g, o
+
+
+def dev_event(e):
+    return tpc.DeviceEvent.from_host(e.y, e.z, e.row_offsets, e.sector_id, device="cuda:0")
+
+
+def run_both(orc, tracker, geo, e, use_global=True):
+    pg, po = params_pair(orc, e.config.sigma if e.config.sigma > 0 else 0.1)
+    tr, pr, mg = tracker.track_event_merged(dev_event(e), geo, e.bz, pg, use_global=use_global)
+    gpu = (tpc.to_numpy(tr), tpc.to_numpy(pr) if pr else None, tpc.to_numpy(mg))
+    ref = orc.track_event_merged(event_dict(e), GEO_T, e.bz, po, merge_chi2=tpc.MERGE_CHI2,
+                                 use_global=use_global, n_threads=THREADS)
+    return gpu, ref
+
+
+def crossing(kind, seed):
+    if kind == "side":
+        cfg = synth.EventConfig(n_tracks=8, sectors=tuple(range(18)), phi_range_deg=(16.0, 18.0),
+                                sigma=0.0, noise_frac=0.0, pt_min=1.9, pt_mean=1e-9, eta_max=0.5)
+    else:
+        cfg = synth.EventConfig(n_tracks=8, sectors=tuple(range(36)), phi_range_deg=(7.0, 13.0),
+                                sigma=0.0, noise_frac=0.0, pt_min=4.0, pt_mean=1e-9,
+                                eta_max=0.012, vertex_sigma_z=1.0)
+    return synth.make_event(cfg, seed)
+
+
+@pytest.mark.parametrize("kind", ["side", "membrane"])
+def test_crossing_joins_match_the_oracle(orc, tracker, geo, kind):
+    joined = 0
+    for seed in range(40, 48):
+        e = crossing(kind, seed)
+        say("merge crossing", kind, seed, e.n_clusters)
+        (tr, _, mg), (rtr, _, rmg) = run_both(orc, tracker, geo, e)
+        rep = concordance.compare_merged(rtr, rmg, tr, mg, e.n_clusters)
+        assert rep["n_a"] == rep["n_b"] == rep["joins_same"] == rep["identical"], rep
+        assert rep["par_fail"] == 0, rep
+        joined += int(np.sum(rmg["meta"][:, 1] > 1))
+    assert joined >= 3
+
+
+@pytest.mark.parametrize("seed", [2, 3])
+def test_central_event_merged_tracks(orc, tracker, geo, seed):
+    e = synth.make_preset("c2_central", seed)
+    say("merge central", seed, e.n_clusters)
+    (tr, pr, mg), (rtr, rpr, rmg) = run_both(orc, tracker, geo, e)
+    rep = concordance.compare_merged(rtr, rmg, tr, mg, e.n_clusters)
+    say(rep)
+    assert rep["n_a"] > 7000 and abs(rep["n_b"] - rep["n_a"]) <= 0.005 * rep["n_a"]
+    assert rep["joins_same_frac"] >= 0.995
+    assert rep["cluster_concordance_ab"] >= 0.999 and rep["cluster_concordance_ba"] >= 0.999
+    assert rep["par_fail"] <= max(2, 2e-3 * rep["par_compared"])
+    # output invariants of the GPU side
+    tm, meta = mg["track_merged"], mg["meta"]
+    assert np.all((tm >= 0) & (tm < mg["n"]))
+    assert np.array_equal(np.bincount(tm, minlength=mg["n"]), meta[:, 1])
+    assert np.all(np.diff(meta[:, 4]) > 0)
+    assert np.array_equal(meta[:, 3], np.concatenate([[0], np.cumsum(meta[:-1, 2])]))
+    assert np.unique(mg["cluster"]).shape[0] == mg["cluster"].shape[0]
+    # every list: inner prolongation of its first track (reversed), the
+    # tracks' own clusters in chain order, outer prolongation of its last
+    pro_of = {(int(t), int(end)): (int(f), int(n)) for t, end, _, n, f in pr["meta"]}
+    ct = tr["cluster_track"]
+    for k in range(mg["n"]):
+        m = meta[k]
+        cl = mg["cluster"][m[3]:m[3] + m[2]]
+        segs = np.nonzero(tm == k)[0]
+        order = list(dict.fromkeys(ct[cl[np.isin(ct[cl], segs)]].tolist()))
+        assert order[0] == m[4] and sorted(order) == sorted(segs.tolist())
+        want = []
+        if (order[0], 0) in pro_of:
+            f, n = pro_of[(order[0], 0)]
+            want += pr["cluster"][f:f + n][::-1].tolist()
+        for t in order:
+            a = tr["track_meta"][t]
+            want += tr["track_cluster"][a[2]:a[2] + a[1]].tolist()
+        if (order[-1], 1) in pro_of:
+            f, n = pro_of[(order[-1], 1)]
+            want += pr["cluster"][f:f + n].tolist()
+        assert cl.tolist() == want, k
+
+
+def test_refit_depends_on_the_list_alone(orc, tracker, geo):
+    """tpc_refit of the merger's own lists reproduces its refits bitwise; the
+    oracle's lists, refitted on the GPU, equal the GPU merger's refit bitwise
+    wherever the two lists are identical (the same clusters give the same
+    fit, section 3.3), and agree with the oracle's FP64 refit within 1e-3."""
+    e = synth.make_preset("c2_central", 2)
+    (tr, pr, mg), (rtr, rpr, rmg) = run_both(orc, tracker, geo, e)
+    dev = dev_event(e)
+    off = torch.from_numpy(np.ascontiguousarray(
+        np.concatenate([mg["meta"][:, 3], [mg["n_clusters"]]]), np.int32)).cuda()
+    cl = torch.from_numpy(np.ascontiguousarray(mg["cluster"], np.int32)).cuda()
+    par, fr = tracker.refit(dev, geo, e.bz, off, cl, params_pair(orc, 0.1)[0])
+    par, fr = par.cpu().numpy(), fr.cpu().numpy()
+    assert np.array_equal(par.view(np.uint32), mg["par"].view(np.uint32))
+    ok = par[:, 7] > 0
+    assert np.array_equal(fr[ok], mg["meta"][ok, 0]) and np.all(fr[~ok] == -1)
+    # the oracle's lists
+    roff = torch.from_numpy(np.ascontiguousarray(
+        np.concatenate([rmg["meta"][:, 3], [rmg["n_clusters"]]]), np.int32)).cuda()
+    rcl = torch.from_numpy(np.ascontiguousarray(rmg["cluster"], np.int32)).cuda()
+    rpar_gpu, _ = tracker.refit(dev, geo, e.bz, roff, rcl, params_pair(orc, 0.1)[0])
+    rpar_gpu = rpar_gpu.cpu().numpy()
+    gl = {tuple(mg["cluster"][m[3]:m[3] + m[2]].tolist()): k for k, m in enumerate(mg["meta"])}
+    same = bad = 0
+    for k, m in enumerate(rmg["meta"]):
+        key = tuple(rmg["cluster"][m[3]:m[3] + m[2]].tolist())
+        if key in gl:
+            same += 1
+            assert np.array_equal(rpar_gpu[k].view(np.uint32), mg["par"][gl[key]].view(np.uint32))
+        P, Q = rpar_gpu[k].astype(np.float64), rmg["par"][k]
+        if Q[7] > 0:
+            bad += not (np.all(np.abs(P[:6] - Q[:6]) <= 1e-3 * np.maximum(1.0, np.abs(Q[:6]))) and
+                        P[7] == Q[7] and abs(P[6] - Q[6]) <= 1e-2 * max(1.0, Q[6]))
+    say("identical lists", same, "of", rmg["n"], "refit parameter misses", bad)
+    assert same >= 0.99 * rmg["n"]
+    assert bad <= max(2, 2e-3 * rmg["n"])
+
+
+def test_merger_without_global_tracking(orc, tracker, geo):
+    e = synth.make_event(synth.EventConfig(n_tracks=1500), 8)
+    (tr, pr, mg), (rtr, _, rmg) = run_both(orc, tracker, geo, e, use_global=False)
+    assert pr is None and mg["n_clusters"] == tr["n_track_clusters"]
+    rep = concordance.compare_merged(rtr, rmg, tr, mg, e.n_clusters)
+    assert rep["joins_same_frac"] >= 0.99 and rep["cluster_concordance_ab"] >= 0.999
+
+
+def test_refit_edge_cases(tracker, geo):
+    e = synth.make_preset("c1_sector", 1)
+    dev = dev_event(e)
+    n = e.n_clusters
+    row = e.row_of()
+    # three consecutive clusters of one particle
+    p = next(int(e.mc_track[c]) for c in np.nonzero(row == 5)[0] if e.mc_track[c] >= 0 and
+             all(np.any((e.mc_track == e.mc_track[c]) & (row == r)) for r in (6, 7)))
+    first_row = [int(np.nonzero((e.mc_track == p) & (row == r))[0][0]) for r in (5, 6, 7)]
+    lists = [[], [0, 1], [n + 5, 0, 1, 2], first_row, [-1] + first_row]
+    off = np.zeros(len(lists) + 1, np.int32)
+    np.cumsum([len(l) for l in lists], out=off[1:])
+    cl = np.concatenate([np.asarray(l, np.int32) for l in lists])
+    par, fr = tracker.refit(dev, geo, e.bz, torch.from_numpy(off).cuda(),
+                            torch.from_numpy(cl).cuda())
+    par, fr = par.cpu().numpy(), fr.cpu().numpy()
+    assert np.all(par[[0, 1, 2, 4]] == 0) and np.all(fr[[0, 1, 2, 4]] == -1)
+    assert par[3, 7] == 1 and fr[3] == e.sector_id[0]                  # three clusters: ndf 1
+    # offsets beyond the list array are clamped to it
+    off2 = torch.tensor([0, 10**6], dtype=torch.int32, device="cuda")
+    par2, _ = tracker.refit(dev, geo, e.bz, off2, torch.from_numpy(cl).cuda())
+    assert par2.shape[0] == 1
+    # an invalid event is refused
+    ro = e.row_offsets.copy()
+    ro[10], ro[11] = ro[11], ro[10] - 1
+    bad = tpc.DeviceEvent.from_host(e.y, e.z, ro, e.sector_id)
+    with pytest.raises(tpc.TpcError):
+        tracker.refit(bad, geo, e.bz, torch.from_numpy(off).cuda(), torch.from_numpy(cl).cuda())
+
+
+def test_merger_capacity_and_empty_event(tracker, geo):
+    e = synth.make_event(synth.EventConfig(n_tracks=1500), 8)
+    dev = dev_event(e)
+    tr, pr, mg = tracker.track_event_merged(dev, geo, e.bz)
+    with pytest.raises(tpc.TpcError) as ex:
+        tracker.track_event_merged(dev, geo, e.bz, cap_merged=5, cap_merged_clusters=10**6)
+    assert ex.value.code == tpc.TPC_ERR_CAPACITY
+    assert f"need {mg['n']} merged tracks / {mg['n_clusters']} clusters" in str(ex.value)
+    tr2, pr2, mg2 = tracker.track_event_merged(dev, geo, e.bz)
+    for k in ("par", "meta", "cluster", "track_merged"):
+        assert np.array_equal(mg[k].cpu().numpy(), mg2[k].cpu().numpy()), k
+    ro = np.zeros(36 * 159 + 1, np.int32)
+    empty = tpc.DeviceEvent.from_host(np.zeros(0), np.zeros(0), ro, np.arange(36))
+    tr, pr, mg = tracker.track_event_merged(empty, geo, 0.5)
+    assert tr["n_tracks"] == 0 and mg["n"] == 0 and mg["n_clusters"] == 0

@@ -177,3 +177,27 @@ def test_merged_output_partitions_the_tracks(orc, geo):
     assert joined > 50
     assert np.sum(mg["par"][:, 7] == 0) <= 2                        # refits that failed
     assert mg["n_clusters"] == mg["cluster"].shape[0] and nt == tm.shape[0]
+
+
+def test_merged_comparison_detects_differences(orc, geo):
+    from oracle import concordance
+    e = synth.make_event(synth.EventConfig(n_tracks=1500), 8)
+    tr, _, mg = orc.track_event_merged(event_dict(e), geo, e.bz, n_threads=4)
+    rep = concordance.compare_merged(tr, mg, tr, mg, e.n_clusters)
+    assert rep["joins_same_frac"] == 1.0 and rep["cluster_concordance_ab"] == 1.0
+    assert rep["identical"] == mg["n"] and rep["par_fail"] == 0
+    # B splits the first joined track of two and shifts the q/pT of another
+    k = int(np.nonzero(mg["meta"][:, 1] == 2)[0][0])
+    b = {key: (v.copy() if hasattr(v, "copy") else v) for key, v in mg.items()}
+    segs = np.nonzero(mg["track_merged"] == k)[0]
+    b["track_merged"][segs[1]] = mg["n"]                  # a joined track of its own
+    m = b["meta"][k].copy()
+    first_len = tr["track_meta"][segs[0], 1]
+    b["meta"] = np.vstack([b["meta"], [m[0], 1, 0, 0, segs[1]]])
+    b["par"] = np.vstack([b["par"], b["par"][k]])
+    j = (k + 1) % mg["n"]
+    b["par"][j, 5] *= 1.01
+    rep = concordance.compare_merged(tr, mg, tr, b, e.n_clusters)
+    assert rep["joins_same"] == mg["n"] - 1
+    assert rep["par_fail"] == 1 and rep["identical"] == mg["n"]
+    assert first_len > 0

@@ -145,3 +145,57 @@ def test_prolongation_report_on_known_answers(event):
     wrong["meta"][:, 0] = (pro["meta"][:, 0] + 1) % res["n_tracks"]
     r = quality.prolongation_report(event, res, wrong)
     assert r["prolongation_purity"] == 0.0 and r["short_piece_recovered"] == 0.0
+
+
+def test_merged_report_on_known_answers(event):
+    """One perfect joined track per particle (its clusters in path order, the
+    truth at the first one): efficiency 1, no splits or fakes, zero
+    resolution; a copy of one is a split track, a list of noise a fake."""
+    slot = event.row_of() // synth.N_ROWS
+    rows = event.row_of() % synth.N_ROWS
+    mc = event.mc_track
+    par, meta, cl = [], [], []
+    for p in np.unique(mc[mc >= 0]):
+        c = np.nonzero(mc == p)[0]
+        if c.shape[0] < 30:
+            continue
+        x = synth.ROW_X[rows[c]].astype(np.float64)
+        c = c[np.argsort(np.hypot(x, event.y_true[c]), kind="stable")]
+        c0 = c[:1]
+        par.append([synth.ROW_X[rows[c0[0]]], event.y_true[c0[0]], event.z_true[c0[0]],
+                    quality._true_sinphi(event, c0, slot[c0])[0], event.track_tanl[p],
+                    event.track_q[p] / event.track_pt[p], 0.0, 2.0 * c.shape[0] - 5])
+        meta.append([int(event.sector_id[slot[c0[0]]]), 1, c.shape[0], len(cl), 0])
+        cl.extend(c.tolist())
+    m = dict(par=np.array(par), meta=np.array(meta, np.int32), cluster=np.array(cl, np.int32))
+    r = quality.merged_report(event, m)
+    assert r["efficiency"] == 1.0 and r["split"] == 0 and r["fakes"] == 0
+    assert r["resolution"]["tracks"] == len(par) > 100
+    for k in ("y_cm", "z_cm", "sinphi", "tanl", "qpt_rel"):
+        assert abs(r["resolution"][k]) < 1e-9, k
+    noise = np.nonzero(mc < 0)[0][:40]
+    m2 = dict(par=np.vstack([m["par"], m["par"][:1], m["par"][:1]]),
+              meta=np.vstack([m["meta"], [m["meta"][0, 0], 1, m["meta"][0, 2], len(cl), 0],
+                              [0, 1, 40, len(cl) + m["meta"][0, 2], 0]]).astype(np.int32),
+              cluster=np.concatenate([m["cluster"], m["cluster"][:m["meta"][0, 2]], noise]))
+    r = quality.merged_report(event, m2)
+    assert r["split"] == 1 and r["fakes"] == 1 and r["efficiency"] == 1.0
+
+
+def test_global_tracking_keeps_efficiency_and_improves_resolution(orc, geo):
+    """Section 5: with global tracking the joined tracks are found as before
+    (efficiency, splits and fakes within 1e-3: a short track that gains a few
+    clusters of another particle can fall below the 90% purity of a found
+    track) and, holding more clusters, are measured better (q/pT and
+    sin(phi) resolution)."""
+    e = synth.make_event(synth.EventConfig(n_tracks=3000), 31)
+    ev = event_dict(e)
+    _, _, with_g = orc.track_event_merged(ev, geo, e.bz, n_threads=4)
+    _, _, without = orc.track_event_merged(ev, geo, e.bz, use_global=False, n_threads=4)
+    a, b = quality.merged_report(e, without), quality.merged_report(e, with_g)
+    assert a["efficiency"] > 0.99 and abs(b["efficiency"] - a["efficiency"]) <= 1e-3
+    assert abs(b["split_rate"] - a["split_rate"]) <= 1e-3
+    assert abs(b["fake_rate"] - a["fake_rate"]) <= 1e-3
+    assert b["mean_clusters"] > a["mean_clusters"] + 2
+    assert b["resolution"]["qpt_rel"] < a["resolution"]["qpt_rel"]
+    assert b["resolution"]["sinphi"] < a["resolution"]["sinphi"]
