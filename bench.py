@@ -518,6 +518,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-extra", dest="extra", action="store_false",
                     help="skip the single-sector, ten-event concordance and stress sections")
+    ap.add_argument("--path", choices=("plain", "global", "merged"), default="plain",
+                    help="the timed step: the sector tracker (default), plus global tracking, "
+                         "plus the track merger with refit")
     ap.add_argument("--serve-events", type=int, default=1000,
                     help="events per arrival rate in the serving measurement (0 = skip)")
     args = ap.parse_args()
@@ -560,9 +563,29 @@ def main():
                         out["track_meta"].data_ptr(), out["track_cluster"].data_ptr(),
                         out["cluster_track"].data_ptr())
     cev = dev_ev.cstruct()
+    # outputs of the global and merged paths, allocated once
+    i32 = dict(dtype=torch.int32, device=dev)
+    f32 = dict(dtype=torch.float32, device=dev)
+    pbuf = dict(par=torch.empty((cap_t, 8), **f32), meta=torch.empty((cap_t, 5), **i32),
+                cluster=torch.empty(max(16, N // 8), **i32))
+    mbuf = dict(par=torch.empty((cap_t, 8), **f32), meta=torch.empty((cap_t, 5), **i32),
+                cluster=torch.empty(N, **i32), track_merged=torch.empty(cap_t, **i32))
+    psz = [C.c_int32(0) for _ in range(4)]
+    pro = tpc.Prolongations(cap_t, int(pbuf["cluster"].shape[0]), C.pointer(psz[0]),
+                            C.pointer(psz[1]), pbuf["par"].data_ptr(), pbuf["meta"].data_ptr(),
+                            pbuf["cluster"].data_ptr())
+    mg = tpc.Merged(cap_t, N, C.pointer(psz[2]), C.pointer(psz[3]), mbuf["par"].data_ptr(),
+                    mbuf["meta"].data_ptr(), mbuf["cluster"].data_ptr(),
+                    mbuf["track_merged"].data_ptr())
 
     def step():
-        rc = tr.track_event_raw(cev, geo, e.bz, prm, tracks, sh)
+        if args.path == "plain":
+            rc = tr.track_event_raw(cev, geo, e.bz, prm, tracks, sh)
+        elif args.path == "global":
+            rc = tr.track_event_global_raw(cev, geo, e.bz, prm, tracks, pro, sh)
+        else:
+            rc = tr.track_event_merged_raw(cev, geo, e.bz, prm, tpc.MERGE_CHI2, tracks, pro, mg,
+                                           sh)
         if rc != 0:
             raise tpc.TpcError(rc, tpc.last_error())
 
@@ -643,8 +666,13 @@ def main():
                 steps=args.steps, warmup=args.warmup, ms_per_step=round(ms, 4),
                 higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
                 data="synthetic",
-                config=dict(workload="central Pb-Pb-like event, plain per-event path: 36 sectors "
-                                     "x 159 rows, 8000 primary helix tracks, 5% noise clusters",
+                config=dict(workload="central Pb-Pb-like event, " + {
+                                "plain": "plain per-event path",
+                                "global": "per-event path with global tracking",
+                                "merged": "per-event path with global tracking and the track "
+                                          "merger with refit"}[args.path] +
+                                     ": 36 sectors x 159 rows, 8000 primary helix tracks, "
+                                     "5% noise clusters",
                             n_clusters=N, seed=args.seed, bz_tesla=e.bz),
                 clusters_per_s=round(N * args.steps / el, 1),
                 latency_ms=dict(p50=round(p(0.5), 4), p99=round(p(0.99), 4)),

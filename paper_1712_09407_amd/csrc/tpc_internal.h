@@ -132,6 +132,8 @@ struct MergeScratch {
   int32_t* span_sum;
   int32_t* loff;        // [T + 1] offsets of the joined tracks' lists
   int32_t* rowslot;     // [N] row slot of each cluster (refit)
+  float4* rec;          // [cap_rec] list entries gathered for the refit: y, z, row slot
+  int32_t cap_rec;
 };
 
 struct MergeOutputs {
@@ -211,7 +213,7 @@ enum KernelId {
   K_PRO_INIT, K_ENDS, K_PROLONG, K_PRO_OWN, K_PRO_REDUCE, K_PRO_SCAN, K_PRO_OUTPUT,
   // track merger with refit
   K_MRG_INIT, K_MRG_MATCH, K_MRG_LINK, K_MRG_CHAIN, K_MRG_REDUCE, K_MRG_SCAN, K_MRG_WRITE,
-  K_ROWMAP, K_REFIT, K_NUM
+  K_ROWMAP, K_REFIT_GATHER, K_REFIT, K_NUM
 };
 extern const char* const kKernelNames[K_NUM];
 
@@ -233,9 +235,9 @@ hipError_t enqueue_global(const DevEvent& ev, const KParams& kp, const Scratch& 
                           const Outputs& out, const GlobalScratch& gs, const ProOutputs* po,
                           hipStream_t st, const KernelTimer* timer = nullptr);
 // The track merger with refit, after enqueue_global; po as given to it.
-size_t merge_bytes(int64_t n_clusters, int64_t n_sectors, int64_t cap_tl);
+size_t merge_bytes(int64_t n_clusters, int64_t n_sectors, int64_t cap_tl, int64_t cap_rec);
 void merge_carve(void* base, int64_t n_clusters, int64_t n_sectors, int64_t cap_tl,
-                 MergeScratch* ms);
+                 int64_t cap_rec, MergeScratch* ms);
 hipError_t enqueue_merge(const DevEvent& ev, const KParams& kp, const Scratch& sc,
                          const Outputs& out, const GlobalScratch& gs, const ProOutputs* po,
                          const MergeScratch& ms, const MergeOutputs& mo, hipStream_t st,

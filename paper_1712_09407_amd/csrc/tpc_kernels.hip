@@ -1896,6 +1896,8 @@ __global__ __launch_bounds__(kGridBlock) void k_pro_output(DevEvent ev, Scratch 
 // A finds its best B and offers itself to every candidate B with a 64-bit
 // atomic minimum of (chi^2 bits, A).
 
+// Whole sector widths from the frame of sector id p to that of q (both in
+// the 2 x 18 layout), in [-9, 8].
 __device__ __forceinline__ int frame_steps(int p, int q) {
   int k = (q % 18) - (p % 18);
   if (k > 8) k -= 18;
@@ -1986,20 +1988,23 @@ __device__ __forceinline__ void cov_full(const Cov& C, float M[5][5]) {
     for (int j = i + 1; j < 5; ++j) M[i][j] = M[j][i];
 }
 
+// One wave per track A: the lanes take A's candidates in turn; the wave's
+// best is the minimum of (chi^2 bits, candidate) over its lanes.
 __global__ __launch_bounds__(kGridBlock) void k_mrg_match(DevEvent ev, KParams kp, Scratch sc,
                                                           GlobalScratch gs, MergeScratch ms) {
   if (event_bad(sc.counters)) return;
   const int nt = ms.counters[C_SEEDS];
   const int nr = kp.n_rows;
   const float cut = kp.merge_chi2;
-  for (int a = blockIdx.x * kGridBlock + threadIdx.x; a < nt; a += gridDim.x * kGridBlock) {
-    int best = -1;
-    float best_c = INFINITY;
+  const int lane = threadIdx.x & 63;
+  const int wpb = kGridBlock / 64;
+  for (int a = blockIdx.x * wpb + (threadIdx.x >> 6); a < nt; a += gridDim.x * wpb) {
+    unsigned long long best = ~0ull;  // (chi^2 bits << 32) | candidate
     const int ta = tl_of_track(gs, a);
     const int sa = sc.seed_rs[ta] / nr;
     const int pa = ev.sector_id[sa];
     const float* EA = sc.ends + (size_t)(2 * ta + 1) * kEndStride;
-    if (pa >= 0 && pa < kLayoutSectors && EA[kEndValid] != 0.f) {
+    if (pa >= 0 && pa < kLayoutSectors && EA[kEndValid] != 0.f) {  // wave-uniform
       KState A;
       load_end(EA, A);
       const float ra = sqrtf(A.x * A.x + A.y * A.y);
@@ -2011,7 +2016,7 @@ __global__ __launch_bounds__(kGridBlock) void k_mrg_match(DevEvent ev, KParams k
         if (sb < 0 || sb == sa || (c > 0 && cand[0] == sb) || (c > 1 && cand[1] == sb)) continue;
         KState R = A;  // A's end in B's frame, once per slot
         if (!rotate_steps(R, frame_steps(pa, ev.sector_id[sb]), kp)) continue;
-        for (int b = ms.first[sb]; b < ms.first[sb + 1]; ++b) {
+        for (int b = ms.first[sb] + lane; b < ms.first[sb + 1]; b += 64) {
           const float4 u = ms.sum[2 * b], v = ms.sum[2 * b + 1];
           // tan(lambda), q/pT and their variances do not change under rotation
           // and propagation, and d_i^2 / S_ii <= chi^2: exact rejections
@@ -2032,16 +2037,17 @@ __global__ __launch_bounds__(kGridBlock) void k_mrg_match(DevEvent ev, KParams k
           const float d[5] = {B.y - T.y, B.z - T.z, B.sp - T.sp, B.tl - T.tl, B.qpt - T.qpt};
           const float x2 = chi2_5(d, S);
           if (!(x2 >= 0.f) || x2 > cut) continue;
-          if (x2 < best_c || (x2 == best_c && b < best)) {
-            best_c = x2;
-            best = b;
-          }
-          atomicMin(&ms.prev_key[b], ((unsigned long long)__float_as_uint(x2) << 32) |
-                                         (unsigned int)a);
+          const unsigned long long hi = (unsigned long long)__float_as_uint(x2) << 32;
+          best = min(best, hi | (unsigned int)b);
+          atomicMin(&ms.prev_key[b], hi | (unsigned int)a);
         }
       }
     }
-    ms.best[a] = best;
+    for (int d = 32; d >= 1; d >>= 1) {
+      const unsigned long long o = __shfl_xor(best, d, 64);
+      best = min(best, o);
+    }
+    if (lane == 0) ms.best[a] = best == ~0ull ? -1 : (int)(best & 0xffffffffull);
   }
 }
 
@@ -2173,113 +2179,131 @@ __global__ __launch_bounds__(kGridBlock) void k_rowmap(DevEvent ev, KParams kp, 
   for (int c = a + threadIdx.x; c < b; c += kGridBlock) ms.rowslot[c] = rs;
 }
 
-// The refit of one list (path order): the seed circle of the first run of
-// three or more consecutive clusters of one sector with increasing rows (its
-// first min(m, seed_window)), an outward filter to the end of the list, an
-// inward fit from the last cluster with a fresh covariance over the whole
-// list; frames change by rotations of whole sector widths; a cluster whose
-// step fails is skipped.  P = x, state at the innermost fitted cluster,
-// chi^2, ndf (all 0 and frame -1 if the refit fails).
-__device__ void refit_list(const int32_t* L, int n, const DevEvent& ev, const KParams& kp,
-                           const MergeScratch& ms, const float* s_x, float* P, int32_t* frame) {
-  const int nr = kp.n_rows, N = ev.n_clusters;
+// A list entry as the refit reads it: coordinates and row slot of the
+// cluster (row slot -1: not a cluster of the event).
+__device__ __forceinline__ float4 list_rec(const DevEvent& ev, const MergeScratch& ms, int c) {
+  const int rs = (c >= 0 && c < ev.n_clusters) ? ms.rowslot[c] : -1;
+  return rs >= 0 ? make_float4(ev.y[c], ev.z[c], __int_as_float(rs), 0.f)
+                 : make_float4(0.f, 0.f, __int_as_float(-1), 0.f);
+}
+
+// The entries of the lists, gathered once (all entries in parallel), so that
+// the refit walks a contiguous 16-byte record per cluster.
+__global__ __launch_bounds__(kGridBlock) void k_refit_gather(DevEvent ev, Scratch sc,
+                                                             MergeScratch ms, const int32_t* n_dev,
+                                                             int n_host, const int32_t* clusters) {
+  if (event_bad(sc.counters)) return;
+  if (n_dev && __builtin_nontemporal_load(&ms.counters[C_ERR]) != 0) return;
+  const int n = min(n_dev ? *n_dev : n_host, ms.cap_rec);
+  for (int e = blockIdx.x * kGridBlock + threadIdx.x; e < n; e += gridDim.x * kGridBlock)
+    ms.rec[e] = list_rec(ev, ms, clusters[e]);
+}
+
+// The refit of one list (path order, records R[0 .. n)): the seed circle of
+// the first run of three or more consecutive clusters of one sector with
+// increasing rows (its first min(m, seed_window)), an outward filter to the
+// end of the list, an inward fit from the last cluster with a fresh
+// covariance over the whole list; frames change by rotations of whole sector
+// widths; a cluster whose step fails is skipped.  A list with an entry that
+// is not a cluster of the event, or over several sectors one of which has an
+// id outside the 2 x 18 layout, fails; the passes check their entries as they
+// go (together they see every entry).  P = x, state at the innermost fitted
+// cluster, chi^2, ndf (all 0 and frame -1 if the refit fails).  The next
+// record is loaded a step ahead.
+__device__ void refit_list(const float4* R, int n, const DevEvent& ev, const KParams& kp,
+                           const float* s_x, float* P, int32_t* frame) {
+  const int nr = kp.n_rows;
   for (int i = 0; i < 8; ++i) P[i] = 0.f;
   *frame = -1;
   if (n < 3) return;
-  auto slot_row = [&](int j, int& sl, int& row) {
-    const int c = L[j];
-    const int rs = (c >= 0 && c < N) ? ms.rowslot[c] : -1;
-    sl = rs >= 0 ? rs / nr : -1;
-    row = rs >= 0 ? rs - sl * nr : -1;
+  bool bad = false, multi = false, bad_id = false;
+  int s_first = -1;
+  auto note = [&](int rs) {  // validity and the sectors seen
+    if (rs < 0) {
+      bad = true;
+      return;
+    }
+    const int sl = rs / nr;
+    if (s_first < 0) s_first = sl;
+    multi |= sl != s_first;
+    const int ph = ev.sector_id[sl];
+    bad_id |= ph < 0 || ph >= kLayoutSectors;
   };
-  // all clusters known; several sectors need ids of the 2 x 18 layout
-  int s0, r0;
-  slot_row(0, s0, r0);
-  bool ok = s0 >= 0, multi = false;
-  for (int j = 1; j < n && ok; ++j) {
-    int sl, row;
-    slot_row(j, sl, row);
-    ok = sl >= 0;
-    multi |= sl != s0;
-  }
-  if (ok && multi)
-    for (int j = 0; j < n && ok; ++j) {
-      int sl, row;
-      slot_row(j, sl, row);
-      const int ph = ev.sector_id[sl];
-      ok = ph >= 0 && ph < kLayoutSectors;
-    }
-  if (!ok) return;
-  // the seed run
+  // the seed run: sliding window of three records
   int i0 = -1;
-  {
-    int sa, ra, sb, rb;
-    slot_row(0, sa, ra);
-    slot_row(1, sb, rb);
-    for (int i = 0; i + 2 < n; ++i) {
-      int sc2, rc;
-      slot_row(i + 2, sc2, rc);
-      if (sb == sa && sc2 == sa && ra < rb && rb < rc) {
-        i0 = i;
-        break;
-      }
-      sa = sb; ra = rb; sb = sc2; rb = rc;
+  float4 ra = R[0], rb = R[1];
+  note(__float_as_int(ra.z));
+  note(__float_as_int(rb.z));
+  for (int i = 0; i + 2 < n; ++i) {
+    const float4 rc = R[i + 2];
+    note(__float_as_int(rc.z));
+    const int xa = __float_as_int(ra.z), xb = __float_as_int(rb.z), xc = __float_as_int(rc.z);
+    if (xa >= 0 && xb >= 0 && xc >= 0 && xb / nr == xa / nr && xc / nr == xa / nr && xa < xb &&
+        xb < xc) {
+      i0 = i;
+      break;
     }
+    ra = rb;
+    rb = rc;
   }
-  if (i0 < 0) return;
-  int sl0, rw0;
-  slot_row(i0, sl0, rw0);
-  int m = 1, prow = rw0;
+  if (i0 < 0 || bad) return;
+  const int rs0 = __float_as_int(R[i0].z), sl0 = rs0 / nr;
+  int m = 1, prs = rs0;
   while (i0 + m < n && m < kp.seed_window) {
-    int sl, row;
-    slot_row(i0 + m, sl, row);
-    if (sl != sl0 || !(row > prow)) break;
-    prow = row;
+    const int rs = __float_as_int(R[i0 + m].z);
+    if (rs < 0 || rs / nr != sl0 || !(rs > prs)) break;
+    prs = rs;
     ++m;
   }
   const int ia = i0, ib = i0 + m / 2, ie = i0 + m - 1;
-  int sx, ra_, rb_, re_;
-  slot_row(ia, sx, ra_);
-  slot_row(ib, sx, rb_);
-  slot_row(ie, sx, re_);
+  const float4 A = R[ia], B = R[ib], E = R[ie];
   KState s;
-  seed3(s, s_x[ra_], ev.y[L[ia]], ev.z[L[ia]], s_x[rb_], ev.y[L[ib]], s_x[re_], ev.y[L[ie]],
-        ev.z[L[ie]], kp);
+  seed3(s, s_x[__float_as_int(A.z) - sl0 * nr], A.x, A.y, s_x[__float_as_int(B.z) - sl0 * nr], B.x,
+        s_x[__float_as_int(E.z) - sl0 * nr], E.x, E.y, kp);
   if (fabsf(s.sp) > kp.max_sinphi) return;
-  // outward filter
+  // outward filter (checks the entries after the seed window's start)
   int fr = sl0, last = i0;
+  float4 nx = i0 + 1 < n ? R[i0 + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
   for (int j = i0 + 1; j < n; ++j) {
-    int sl, row;
-    slot_row(j, sl, row);
+    const float4 cur = nx;
+    if (j + 1 < n) nx = R[j + 1];
+    const int rs = __float_as_int(cur.z);
+    note(rs);
+    if (rs < 0 || (multi && bad_id)) continue;
+    const int sl = rs / nr;
     KState t = s;
     if (sl != fr && !rotate_steps(t, frame_steps(ev.sector_id[fr], ev.sector_id[sl]), kp)) continue;
-    if (!propagate(t, s_x[row], kp)) continue;
-    kf_update(t, ev.y[L[j]], ev.z[L[j]], kp);
+    if (!propagate(t, s_x[rs - sl * nr], kp)) continue;
+    kf_update(t, cur.x, cur.y, kp);
     s = t;
     fr = sl;
     last = j;
   }
+  if (bad || (multi && bad_id)) return;
   // inward fit from the last cluster, fresh covariance
-  int sl_l, row_l;
-  slot_row(last, sl_l, row_l);
+  const float4 L = R[last];
+  const int rsl = __float_as_int(L.z);
   KState w;
-  w.x = s_x[row_l];
-  w.y = ev.y[L[last]];
-  w.z = ev.z[L[last]];
+  w.x = s_x[rsl - (rsl / nr) * nr];
+  w.y = L.x;
+  w.z = L.y;
   w.sp = s.sp;
   w.tl = s.tl;
   w.qpt = s.qpt;
   reset_cov(w.C, kp);
   float chi2 = 0.f;
-  int nn = 1, ifr = sl_l;
+  int nn = 1, ifr = rsl / nr;
   float o[6] = {w.x, w.y, w.z, w.sp, w.tl, w.qpt};
+  nx = last > 0 ? R[last - 1] : make_float4(0.f, 0.f, 0.f, 0.f);
   for (int j = last - 1; j >= 0; --j) {
-    int sl, row;
-    slot_row(j, sl, row);
+    const float4 cur = nx;
+    if (j > 0) nx = R[j - 1];
+    const int rs = __float_as_int(cur.z);
+    const int sl = rs / nr;
     KState t = w;
     if (sl != fr && !rotate_steps(t, frame_steps(ev.sector_id[fr], ev.sector_id[sl]), kp)) continue;
-    if (!propagate(t, s_x[row], kp)) continue;
-    chi2 += kf_update(t, ev.y[L[j]], ev.z[L[j]], kp);
+    if (!propagate(t, s_x[rs - sl * nr], kp)) continue;
+    chi2 += kf_update(t, cur.x, cur.y, kp);
     w = t;
     fr = sl;
     ++nn;
@@ -2293,13 +2317,13 @@ __device__ void refit_list(const int32_t* L, int n, const DevEvent& ev, const KP
   *frame = ev.sector_id[ifr];
 }
 
-// One lane per list.  n_lists is read from n_dev if given (the merger's own
-// lists), else n_host with list entries clamped to [0, n_entries).
+// One lane per list over the gathered records.  n_lists is read from n_dev
+// if given (the merger's own lists), else n_host with list entries clamped
+// to [0, min(n_entries, gathered records)).
 __global__ __launch_bounds__(kGridBlock) void k_refit(DevEvent ev, KParams kp, Scratch sc,
                                                       MergeScratch ms, const int32_t* n_dev,
                                                       int n_host, int n_entries,
-                                                      const int32_t* offsets,
-                                                      const int32_t* clusters, float* par,
+                                                      const int32_t* offsets, float* par,
                                                       int32_t* frame, int32_t* meta_frame) {
   __shared__ float s_x[TPC_MAX_ROWS];
   for (int i = threadIdx.x; i < kp.n_rows; i += kGridBlock) s_x[i] = kp.row_x[i];
@@ -2307,15 +2331,14 @@ __global__ __launch_bounds__(kGridBlock) void k_refit(DevEvent ev, KParams kp, S
   if (event_bad(sc.counters)) return;
   if (n_dev && __builtin_nontemporal_load(&ms.counters[C_ERR]) != 0) return;
   const int n = n_dev ? *n_dev : n_host;
+  const int lim = min(n_entries, ms.cap_rec);
   for (int k = blockIdx.x * kGridBlock + threadIdx.x; k < n; k += gridDim.x * kGridBlock) {
     int a = offsets[k], b = offsets[k + 1];
-    if (!n_dev) {
-      a = clampi(a, 0, n_entries);
-      b = clampi(b, a, n_entries);
-    }
+    a = clampi(a, 0, lim);
+    b = clampi(b, a, lim);
     float P[8];
     int32_t f;
-    refit_list(clusters + a, b - a, ev, kp, ms, s_x, P, &f);
+    refit_list(ms.rec + a, b - a, ev, kp, s_x, P, &f);
     for (int i = 0; i < 8; ++i) par[(size_t)k * 8 + i] = P[i];
     if (frame) frame[k] = f;
     if (meta_frame && f >= 0) meta_frame[(size_t)k * 5] = f;
@@ -2556,7 +2579,7 @@ const char* const kKernelNames[K_NUM] = {
     "k_own", "k_tl_reduce", "k_tl_scan", "k_output", "k_pro_init", "k_ends", "k_prolong",
     "k_pro_own", "k_pro_reduce", "k_pro_scan", "k_pro_output", "k_mrg_init", "k_mrg_match",
     "k_mrg_link", "k_mrg_chain", "k_mrg_reduce", "k_mrg_scan", "k_mrg_write", "k_rowmap",
-    "k_refit"};
+    "k_refit_gather", "k_refit"};
 
 hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& sc,
                          const Outputs& out, int upto, hipStream_t st, const KernelTimer* tm,
@@ -2681,7 +2704,7 @@ hipError_t enqueue_global(const DevEvent& ev, const KParams& kp, const Scratch& 
   return hipGetLastError();
 }
 
-size_t merge_bytes(int64_t N, int64_t S, int64_t T) {
+size_t merge_bytes(int64_t N, int64_t S, int64_t T, int64_t cap_rec) {
   size_t b = 0;
   b += align_up(sizeof(int32_t) * C_COUNT);
   b += align_up(sizeof(int32_t) * (S + 1));
@@ -2692,10 +2715,12 @@ size_t merge_bytes(int64_t N, int64_t S, int64_t T) {
   b += align_up(sizeof(int32_t) * (2 * ((T + kSpan - 1) / kSpan) + 2));
   b += align_up(sizeof(int32_t) * (T + 1));
   b += align_up(sizeof(int32_t) * (N > 0 ? N : 1));
+  b += align_up(sizeof(float4) * (cap_rec > 0 ? cap_rec : 1));
   return b;
 }
 
-void merge_carve(void* base, int64_t N, int64_t S, int64_t T, MergeScratch* ms) {
+void merge_carve(void* base, int64_t N, int64_t S, int64_t T, int64_t cap_rec,
+                 MergeScratch* ms) {
   char* p = (char*)base;
   auto take = [&](size_t bytes) {
     void* r = p;
@@ -2717,6 +2742,8 @@ void merge_carve(void* base, int64_t N, int64_t S, int64_t T, MergeScratch* ms) 
   ms->span_sum = (int32_t*)take(sizeof(int32_t) * (2 * ((T + kSpan - 1) / kSpan) + 2));
   ms->loff = (int32_t*)take(sizeof(int32_t) * (T + 1));
   ms->rowslot = (int32_t*)take(sizeof(int32_t) * (N > 0 ? N : 1));
+  ms->rec = (float4*)take(sizeof(float4) * (cap_rec > 0 ? cap_rec : 1));
+  ms->cap_rec = (int32_t)cap_rec;
 }
 
 hipError_t enqueue_merge(const DevEvent& ev, const KParams& kp, const Scratch& sc,
@@ -2737,7 +2764,8 @@ hipError_t enqueue_merge(const DevEvent& ev, const KParams& kp, const Scratch& s
   hipLaunchKernelGGL(k_mrg_init, dim3(tb), dim3(kGridBlock), 0, st, ev, kp, sc, gs, ms);
   post(K_MRG_INIT);
   pre(K_MRG_MATCH);
-  hipLaunchKernelGGL(k_mrg_match, dim3(tb), dim3(kGridBlock), 0, st, ev, kp, sc, gs, ms);
+  hipLaunchKernelGGL(k_mrg_match, dim3(wave_blocks(T)), dim3(kGridBlock), 0, st, ev, kp, sc, gs,
+                     ms);
   post(K_MRG_MATCH);
   pre(K_MRG_LINK);
   hipLaunchKernelGGL(k_mrg_link, dim3(tb), dim3(kGridBlock), 0, st, sc, ms);
@@ -2770,10 +2798,17 @@ hipError_t enqueue_merge(const DevEvent& ev, const KParams& kp, const Scratch& s
   pre(K_ROWMAP);
   hipLaunchKernelGGL(k_rowmap, dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc, ms);
   post(K_ROWMAP);
+  pre(K_REFIT_GATHER);
+  const int gb = (int)std::min<int64_t>(std::max<int64_t>((ms.cap_rec + kGridBlock - 1) /
+                                                              kGridBlock, 1), 4096);
+  hipLaunchKernelGGL(k_refit_gather, dim3(gb), dim3(kGridBlock), 0, st, ev, sc, ms,
+                     (const int32_t*)&ms.counters[C_TRACK_CLUSTERS], 0,
+                     (const int32_t*)mo.cluster);
+  post(K_REFIT_GATHER);
   pre(K_REFIT);
   hipLaunchKernelGGL(k_refit, dim3(tb), dim3(kGridBlock), 0, st, ev, kp, sc, ms,
-                     (const int32_t*)&ms.counters[C_TRACKS], 0, 0, (const int32_t*)ms.loff,
-                     (const int32_t*)mo.cluster, mo.par, (int32_t*)nullptr, mo.meta);
+                     (const int32_t*)&ms.counters[C_TRACKS], 0, ms.cap_rec,
+                     (const int32_t*)ms.loff, mo.par, (int32_t*)nullptr, mo.meta);
   post(K_REFIT);
   return hipGetLastError();
 }
@@ -2793,11 +2828,18 @@ hipError_t enqueue_refit(const DevEvent& ev, const KParams& kp, const Scratch& s
   hipLaunchKernelGGL(k_rowmap, dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc, ms);
   post(K_ROWMAP);
   if (n_lists > 0) {
+    if (n_entries > 0) {
+      const int gb = std::min((n_entries + kGridBlock - 1) / kGridBlock, 4096);
+      pre(K_REFIT_GATHER);
+      hipLaunchKernelGGL(k_refit_gather, dim3(gb), dim3(kGridBlock), 0, st, ev, sc, ms,
+                         (const int32_t*)nullptr, n_entries, clusters);
+      post(K_REFIT_GATHER);
+    }
     const int lb = std::min((n_lists + kGridBlock - 1) / kGridBlock, 65535);
     pre(K_REFIT);
     hipLaunchKernelGGL(k_refit, dim3(lb), dim3(kGridBlock), 0, st, ev, kp, sc, ms,
-                       (const int32_t*)nullptr, n_lists, n_entries, offsets, clusters, par,
-                       frame, (int32_t*)nullptr);
+                       (const int32_t*)nullptr, n_lists, n_entries, offsets, par, frame,
+                       (int32_t*)nullptr);
     post(K_REFIT);
   }
   return hipGetLastError();

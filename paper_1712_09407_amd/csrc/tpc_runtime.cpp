@@ -218,9 +218,11 @@ int ensure_arena(tpc_ctx* ctx, int64_t N, int64_t R, int64_t T, hipStream_t st) 
   return TPC_OK;
 }
 
-// Global tracking scratch, followed by the merger's when with_merge.
-int ensure_glob(tpc_ctx* ctx, int64_t N, int64_t S, int64_t T, bool with_merge, hipStream_t st) {
-  size_t need = global_bytes(N, T) + (with_merge ? merge_bytes(N, S, T) : 0);
+// Global tracking scratch, followed by the merger's (with room for cap_rec
+// list entries) when with_merge.
+int ensure_glob(tpc_ctx* ctx, int64_t N, int64_t S, int64_t T, bool with_merge, int64_t cap_rec,
+                hipStream_t st) {
+  size_t need = global_bytes(N, T) + (with_merge ? merge_bytes(N, S, T, cap_rec) : 0);
   if (need <= ctx->glob_bytes) return TPC_OK;
   size_t want = need + need / 4;
   if (ctx->budget && ctx->arena_bytes + want > ctx->budget) want = need;
@@ -285,11 +287,12 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
     GlobalScratch gs{};
     MergeScratch ms{};
     if (po || mo) {
-      rc = ensure_glob(ctx, N, ev->n_sectors, T, mo != nullptr, st);
+      // the joined tracks' lists hold distinct clusters: at most N entries
+      rc = ensure_glob(ctx, N, ev->n_sectors, T, mo != nullptr, N, st);
       if (rc) return rc;
       global_carve(ctx->glob_arena, N, T, &sc.ends, &gs);
       if (mo)
-        merge_carve((char*)ctx->glob_arena + global_bytes(N, T), N, ev->n_sectors, T, &ms);
+        merge_carve((char*)ctx->glob_arena + global_bytes(N, T), N, ev->n_sectors, T, N, &ms);
     }
     const bool timed = ctx->timer.mask != 0;
     e = enqueue_event(dev, kp, sc, out, upto, st, timed ? &ctx->timer : nullptr);
@@ -901,7 +904,7 @@ int tpc_refit(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
   hipStream_t st = (hipStream_t)hip_stream;
   rc = ensure_arena(ctx, N, R, T, st);
   if (rc) return rc;
-  rc = ensure_glob(ctx, N, ev->n_sectors, T, true, st);
+  rc = ensure_glob(ctx, N, ev->n_sectors, T, true, n_entries, st);
   if (rc) return rc;
   KParams kp = make_kparams(geo, bz_tesla, params);
   kp.bin_occupancy = ctx->tuning.bin_occupancy;
@@ -917,7 +920,7 @@ int tpc_refit(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
   GlobalScratch gs{};
   MergeScratch ms{};
   global_carve(ctx->glob_arena, N, T, &sc.ends, &gs);
-  merge_carve((char*)ctx->glob_arena + global_bytes(N, T), N, ev->n_sectors, T, &ms);
+  merge_carve((char*)ctx->glob_arena + global_bytes(N, T), N, ev->n_sectors, T, n_entries, &ms);
   const DevEvent dev = make_devevent(ev);
   Outputs o{0, 0, nullptr, nullptr, nullptr, nullptr};
   e = enqueue_event(dev, kp, sc, o, STAGE_GRID, st);

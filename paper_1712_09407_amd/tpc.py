@@ -479,6 +479,22 @@ class Tracker:
         return lib.tpc_track_event(self._h, C.byref(e), C.byref(geo), float(bz),
                                    C.byref(params), C.byref(tr), stream_handle)
 
+    def track_event_global_raw(self, e: Event, geo: Geometry, bz: float, params: Params,
+                               tr: Tracks, pro: Prolongations, stream_handle) -> int:
+        """tpc_track_event_global on prebuilt structs (no allocation)."""
+        return lib.tpc_track_event_global(self._h, C.byref(e), C.byref(geo), float(bz),
+                                          C.byref(params), C.byref(tr), C.byref(pro),
+                                          stream_handle)
+
+    def track_event_merged_raw(self, e: Event, geo: Geometry, bz: float, params: Params,
+                               merge_chi2: float, tr: Tracks, pro, mg: Merged,
+                               stream_handle) -> int:
+        """tpc_track_event_merged on prebuilt structs (pro may be None)."""
+        return lib.tpc_track_event_merged(self._h, C.byref(e), C.byref(geo), float(bz),
+                                          C.byref(params), float(merge_chi2), C.byref(tr),
+                                          C.byref(pro) if pro is not None else None,
+                                          C.byref(mg), stream_handle)
+
     def links(self, ev: DeviceEvent, geo: Geometry, params: Params = None, stream=None):
         import torch
         n = max(ev.n_clusters, 1)
