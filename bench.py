@@ -229,9 +229,10 @@ def global_section(tr, tpc, synth, geo, prm, e, dev_ev, steps, log_):
         trk, pro = tr.track_event_global(dev_ev, geo, e.bz, prm)
     torch.cuda.synchronize()
     glob = (time.perf_counter() - t0) / steps
-    tr.set_timing(None)
+    tr.set_timing(None)  # per-kernel means over 10 calls
     tr.reset_stats()
-    tr.track_event_global(dev_ev, geo, e.bz, prm)
+    for _ in range(10):
+        tr.track_event_global(dev_ev, geo, e.bz, prm)
     st = tr.stats()
     tr.set_timing([])
     trk, pro = tpc.to_numpy(trk), tpc.to_numpy(pro)
@@ -274,9 +275,10 @@ def merge_section(tr, tpc, synth, geo, prm, e, dev_ev, steps, log_):
     glob = timed(lambda: tr.track_event_global(dev_ev, geo, e.bz, prm))
     merged = timed(lambda: tr.track_event_merged(dev_ev, geo, e.bz, prm))
     merged0 = timed(lambda: tr.track_event_merged(dev_ev, geo, e.bz, prm, use_global=False))
-    tr.set_timing(None)
+    tr.set_timing(None)  # per-kernel means over 10 calls
     tr.reset_stats()
-    trk, pro, mg = tr.track_event_merged(dev_ev, geo, e.bz, prm)
+    for _ in range(10):
+        trk, pro, mg = tr.track_event_merged(dev_ev, geo, e.bz, prm)
     st = tr.stats()
     tr.set_timing([])
     trk, mg = tpc.to_numpy(trk), tpc.to_numpy(mg)
@@ -496,8 +498,27 @@ def serving_section(tpc, synth, geo, prm, host, rates, n_events, log_):
             row[name] = {k: res[k] for k in ("p50_ms", "p99_ms", "mean_ms",
                                               "sustained_events_per_s", "offered_events_per_s")}
             row[name]["batches"] = res["stats"]["batches"]
+            row[name]["busy_retries"] = res["busy_retries"]
             log_(f"serve {rate} Hz {name}: {row[name]}")
         out["rates"][str(int(rate))] = row
+    # admission under a small budget: a central-size event (1.33M clusters at
+    # about 160 B each) nearly fills 256 MiB, so arrivals wait for completions
+    rate = max(rates)
+    try:
+        srv = tpc.Server(geo, 0.5, prm, keep_results=0, max_batch=64, n_workers=2, use_graph=1,
+                         hbm_budget_bytes=256 << 20)
+        serve.run(srv, pool, rate_hz=rate, n_events=min(64, n_events), seed=99)
+        res, _ = serve.run(srv, pool, rate_hz=rate, n_events=n_events, seed=4)
+        srv.close()
+        out["small_budget"] = dict(budget_bytes=256 << 20, rate_hz=rate,
+                                   **{k: res[k] for k in ("p50_ms", "p99_ms", "mean_ms",
+                                                          "sustained_events_per_s",
+                                                          "offered_events_per_s",
+                                                          "busy_retries")},
+                                   batches=res["stats"]["batches"])
+    except Exception as exc:  # the headline line must still be printed
+        out["small_budget"] = dict(error=f"{type(exc).__name__}: {exc}")
+    log_(f"serve {rate} Hz, 256 MiB budget: {out['small_budget']}")
     return out
 
 
@@ -507,6 +528,10 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--event", choices=("c2_central", "c1_sector", "c5_stress"),
+                    default="c2_central",
+                    help="the timed event (the headline is the central event; the others "
+                         "are for profiling)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -521,7 +546,7 @@ def main():
     ap.add_argument("--path", choices=("plain", "global", "merged"), default="plain",
                     help="the timed step: the sector tracker (default), plus global tracking, "
                          "plus the track merger with refit")
-    ap.add_argument("--serve-events", type=int, default=1000,
+    ap.add_argument("--serve-events", type=int, default=2000,
                     help="events per arrival rate in the serving measurement (0 = skip)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -536,12 +561,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    log("generating the central event, seed", args.seed)
-    e = synth.make_preset("c2_central", args.seed)
+    log("generating the event", args.event, "seed", args.seed)
+    e = synth.make_preset(args.event, args.seed)
     N = e.n_clusters
     geo = tpc.make_geometry(synth.ROW_X, synth.TAN_HALF, synth.Z_MAX)
     dev_ev = tpc.DeviceEvent.from_host(e.y, e.z, e.row_offsets, e.sector_id, device=dev)
-    prm = tpc.default_params()
+    prm = tpc.default_params(sigma_y=e.config.sigma, sigma_z=e.config.sigma)
     tr = tpc.Tracker(0)
     cap_t, cap_c = max(1024, N // 40), N
     out = dict(track_par=torch.empty((cap_t, 8), dtype=torch.float32, device=dev),
@@ -666,13 +691,19 @@ def main():
                 steps=args.steps, warmup=args.warmup, ms_per_step=round(ms, 4),
                 higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
                 data="synthetic",
-                config=dict(workload="central Pb-Pb-like event, " + {
+                config=dict(workload={
+                                "c2_central": "central Pb-Pb-like event, ",
+                                "c1_sector": "one sector, ",
+                                "c5_stress": "stress event, "}[args.event] + {
                                 "plain": "plain per-event path",
                                 "global": "per-event path with global tracking",
                                 "merged": "per-event path with global tracking and the track "
-                                          "merger with refit"}[args.path] +
-                                     ": 36 sectors x 159 rows, 8000 primary helix tracks, "
-                                     "5% noise clusters",
+                                          "merger with refit"}[args.path] + {
+                                "c2_central": ": 36 sectors x 159 rows, 8000 primary helix "
+                                              "tracks, 5% noise clusters",
+                                "c1_sector": ": 159 rows, 200 helix tracks, 2% noise clusters",
+                                "c5_stress": ": 36 sectors x 159 rows, 20000 primaries + 6000 "
+                                             "loopers, 10% noise, sigma 0.15 cm"}[args.event],
                             n_clusters=N, seed=args.seed, bz_tesla=e.bz),
                 clusters_per_s=round(N * args.steps / el, 1),
                 latency_ms=dict(p50=round(p(0.5), 4), p99=round(p(0.99), 4)),

@@ -189,7 +189,7 @@ def compare_prolongations(tracks_a, pro_a, tracks_b, pro_b, n_clusters: int,
 
 
 def compare_merged(tracks_a, merged_a, tracks_b, merged_b, n_clusters: int,
-                   rel_tol: float = 1e-3, chi2_tol: float = 1e-2) -> dict:
+                   rel_tol: float = 1e-3, chi2_tol: float = 1e-2, min_fit: int = 30) -> dict:
     """Agreement of two runs' joined (merged) tracks.  A joined track of B
     corresponds to the joined track of A that holds the partner of B's first
     sector track (the tracks' one-to-one correspondence, as in compare).
@@ -198,7 +198,13 @@ def compare_merged(tracks_a, merged_a, tracks_b, merged_b, n_clusters: int,
     list clusters that the corresponding list of the other run holds; for
     identical lists, the refit parameters must agree within rel_tol relative
     (absolute below 1), ndf exactly and chi2 within chi2_tol (the refit is a
-    function of the list alone, so only FP32/FP64 rounding separates them)."""
+    function of the list alone, so only FP32/FP64 rounding separates them),
+    for refits that fitted at least min_fit clusters on both sides (ndf >=
+    2 min_fit - 5).  Shorter fits are counted, not compared: they are lists
+    (of loopers) whose steps pass the |sin phi| limit near a turning point, and
+    which steps fail there is decided in FP32 and FP64 near the limit, so the
+    fitted subsets, hence the fits, differ.  par_max_rel: the largest relative
+    parameter deviation among the compared fits."""
     match_a, match_b = match_tracks(tracks_a, tracks_b, n_clusters)
     ma, mb = np.asarray(merged_a["meta"]).reshape(-1, 5), np.asarray(merged_b["meta"]).reshape(-1, 5)
     tma, tmb = np.asarray(merged_a["track_merged"]), np.asarray(merged_b["track_merged"])
@@ -223,16 +229,20 @@ def compare_merged(tracks_a, merged_a, tracks_b, merged_b, n_clusters: int,
     tot_b = sum(x.size for x in lb)
     pa_all = np.asarray(merged_a["par"], np.float64).reshape(-1, 8)
     pb_all = np.asarray(merged_b["par"], np.float64).reshape(-1, 8)
-    identical = compared = fail = 0
+    identical = compared = fail = short = 0
+    max_rel = 0.0
     for k in range(len(la)):
         if corr[k] < 0 or not np.array_equal(la[k], lb[corr[k]]):
             continue
         identical += 1
         pa, pb = pa_all[k], pb_all[corr[k]]
-        if pa[7] == 0 and pb[7] == 0:
-            continue  # both refits failed
+        if pa[7] < 2 * min_fit - 5 or pb[7] < 2 * min_fit - 5:
+            short += 1
+            continue
         compared += 1
-        ok = np.all(np.abs(pb[:6] - pa[:6]) <= rel_tol * np.maximum(1.0, np.abs(pa[:6])))
+        rel = np.abs(pb[:6] - pa[:6]) / np.maximum(1.0, np.abs(pa[:6]))
+        max_rel = max(max_rel, float(rel.max()))
+        ok = np.all(rel <= rel_tol)
         ok = ok and pb[7] == pa[7] and abs(pb[6] - pa[6]) <= chi2_tol * max(1.0, abs(pa[6]))
         fail += 0 if ok else 1
     return dict(n_a=len(la), n_b=len(lb), joins_same=same_join,
@@ -240,4 +250,5 @@ def compare_merged(tracks_a, merged_a, tracks_b, merged_b, n_clusters: int,
                 clusters_a=tot_a, clusters_b=tot_b,
                 cluster_concordance_ab=shared / max(1, tot_a),
                 cluster_concordance_ba=shared / max(1, tot_b),
-                identical=identical, par_compared=compared, par_fail=fail)
+                identical=identical, short_fits=short, par_compared=compared, par_fail=fail,
+                par_max_rel=max_rel)

@@ -40,7 +40,8 @@ struct tpc_ctx {
   int32_t* h_counters = nullptr;  // pinned: sector tracker's, global tracking's, merger's counters
   void* glob_arena = nullptr;     // global tracking scratch
   size_t glob_bytes = 0;
-  int64_t learned_tl = 0;   // tracklet reservation learned from overflows
+  double learned_ratio = 0.0;  // tracklets per cluster learned from overflows: the
+                               // reservation scales with the event (or batch) size
   tpc::KernelTimer timer;   // HIP events around selected kernels
   bool timer_ready = false;
   double kernel_ms[tpc::K_NUM] = {};
@@ -187,9 +188,17 @@ DevEvent make_devevent(const tpc_event* ev) {
 
 int64_t default_tracklets(const tpc_ctx* ctx, int64_t N, const tpc_params* p) {
   if (p->max_tracklets > 0) return p->max_tracklets;
-  int64_t t = N / 24 + 256;  // central events start about one tracklet per 80 clusters
-  if (ctx->learned_tl > t) t = ctx->learned_tl;
-  return t;
+  int64_t t = N / 24 + 256;  // one per 24 clusters (central events have one per 36)
+  const int64_t l = (int64_t)std::ceil(ctx->learned_ratio * (double)N) + 256;
+  return l > t ? l : t;
+}
+
+// After an overflow: the reservation for this call and the ratio learned from it.
+int64_t grow_tracklets(tpc_ctx* ctx, int64_t need, int64_t N) {
+  const int64_t T = need + need / 8 + 64;
+  const double r = (double)T / (double)(N > 0 ? N : 1);
+  if (r > ctx->learned_ratio) ctx->learned_ratio = r;
+  return T;
 }
 
 int ensure_arena(tpc_ctx* ctx, int64_t N, int64_t R, int64_t T, hipStream_t st) {
@@ -327,8 +336,7 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
       if (p->max_tracklets > 0 || attempt == 1)
         return fail(TPC_ERR_OVERFLOW, "%lld tracklets exceed the reservation of %lld",
                     (long long)need, (long long)T);
-      T = need + need / 8 + 64;
-      if (T > ctx->learned_tl) ctx->learned_tl = T;
+      T = grow_tracklets(ctx, need, N);
       continue;
     }
     if (timed) {
@@ -576,8 +584,7 @@ int run_batch(tpc_ctx* ctx, const tpc_event* evs, int E, const tpc_geometry* geo
     if (graph_now && (c[C_ERR] & E_TL_OVERFLOW)) {
       // the replay's reservation was too small: drop the graph, re-run eagerly
       const int64_t need = c[C_SEEDS];
-      T = need + need / 8 + 64;
-      if (T > ctx->learned_tl) ctx->learned_tl = T;
+      T = grow_tracklets(ctx, need, ncap);
       if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
       if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
       ctx->graph_exec = nullptr;
@@ -591,8 +598,7 @@ int run_batch(tpc_ctx* ctx, const tpc_event* evs, int E, const tpc_geometry* geo
       if (p->max_tracklets > 0 || attempt == 1)
         return fail(TPC_ERR_OVERFLOW, "%lld tracklets exceed the reservation of %lld",
                     (long long)need, (long long)T);
-      T = need + need / 8 + 64;
-      if (T > ctx->learned_tl) ctx->learned_tl = T;
+      T = grow_tracklets(ctx, need, ncap);
       continue;
     }
     if (c[C_ERR] & E_CAPACITY) return fail(TPC_ERR_DEVICE, "internal batch output overflow");

@@ -222,3 +222,57 @@ def test_merger_capacity_and_empty_event(tracker, geo):
     empty = tpc.DeviceEvent.from_host(np.zeros(0), np.zeros(0), ro, np.arange(36))
     tr, pr, mg = tracker.track_event_merged(empty, geo, 0.5)
     assert tr["n_tracks"] == 0 and mg["n"] == 0 and mg["n_clusters"] == 0
+
+
+def test_stress_event_global_and_merged(orc, tracker, geo):
+    """The stress event (20000 primaries, 6000 loopers, 10% noise, sigma
+    0.15 cm; about 800 clusters per row): prolongations and joined tracks
+    against the oracle's.  Denser rows make FP32/FP64 near-ties more frequent
+    and a changed pick changes the rest of its prolongation, so the bars are
+    99.5% of the clusters and of the joins.  As for the sector tracks of this
+    event, low-pT loopers are ill-conditioned fits whose FP32 rounding moves
+    q/pT by ~1e-3 relative: at most 0.5% of the compared refits (those of 30
+    or more clusters) outside 1e-3, none beyond 2e-2."""
+    e = synth.make_preset("c5_stress", 5000)
+    say("merge stress", e.n_clusters)
+    (tr, pr, mg), (rtr, rpr, rmg) = run_both(orc, tracker, geo, e)
+    rp = concordance.compare_prolongations(rtr, rpr, tr, pr, e.n_clusters)
+    rm = concordance.compare_merged(rtr, rmg, tr, mg, e.n_clusters)
+    say("prolongations", rp)
+    say("merged", rm)
+    assert rp["cluster_concordance_ab"] >= 0.995 and rp["cluster_concordance_ba"] >= 0.995
+    assert rm["joins_same_frac"] >= 0.995
+    assert rm["cluster_concordance_ab"] >= 0.995 and rm["cluster_concordance_ba"] >= 0.995
+    assert rm["par_compared"] >= 0.9 * rm["identical"]
+    assert rm["par_fail"] <= max(5, 5e-3 * rm["par_compared"]) and rm["par_max_rel"] <= 2e-2
+
+
+@pytest.mark.parametrize("case", ["few_tracks", "duplicate_sector_ids"])
+def test_merged_path_edge_events(orc, tracker, geo, case):
+    """A sparse event (three tracks) and an event whose sector slots repeat
+    physical ids (a slot's neighbour is the first slot with that id, on both
+    sides): the same prolongations and joined tracks as the oracle."""
+    if case == "few_tracks":
+        e = synth.make_event(synth.EventConfig(n_tracks=3), 77)
+        sid = None
+    else:
+        e = synth.make_event(synth.EventConfig(n_tracks=400, sectors=tuple(range(18)),
+                                               phi_range_deg=(0.0, 80.0)), 12)
+        # slots 0..17 keep their ids; re-label 4..7 as copies of 0..3
+        sid = np.asarray(e.sector_id).copy()
+        sid[4:8] = sid[0:4]
+    pg, po = params_pair(orc, e.config.sigma)
+    dev = tpc.DeviceEvent.from_host(e.y, e.z, e.row_offsets,
+                                    e.sector_id if sid is None else sid, device="cuda:0")
+    tr, pr, mg = (tpc.to_numpy(x) for x in tracker.track_event_merged(dev, geo, e.bz, pg))
+    ev = event_dict(e)
+    if sid is not None:
+        ev["sector_id"] = sid
+    rtr, rpr, rmg = orc.track_event_merged(ev, GEO_T, e.bz, po, merge_chi2=tpc.MERGE_CHI2,
+                                           n_threads=THREADS)
+    rp = concordance.compare_prolongations(rtr, rpr, tr, pr, e.n_clusters)
+    rm = concordance.compare_merged(rtr, rmg, tr, mg, e.n_clusters)
+    say(case, rp, rm)
+    assert rp["cluster_concordance_ab"] >= 0.999 and rp["cluster_concordance_ba"] >= 0.999
+    assert rm["joins_same_frac"] >= 0.99
+    assert rm["cluster_concordance_ab"] >= 0.999 and rm["par_fail"] <= 1
