@@ -344,6 +344,11 @@ __global__ __launch_bounds__(kGridBlock) void k_nf(DevEvent ev, KParams kp, Scra
     }
     return;
   }
+  // the thread's first cluster record, loaded together with the neighbour
+  // rows' headers: it is needed only after the staging, and one level of
+  // global-load latency fewer is on the workgroup's path
+  GridRec me_first = {};
+  if (tid < e - b) me_first = sc.g_rec[b + tid];
   const RowGrid gd = sc.grid[rs - 1], gu = sc.grid[rs + 1];
   const int bd_ = ev.ro[rs - 1], bu_ = ev.ro[rs + 1];
   const bool stage = gd.n <= CAP && gu.n <= CAP;
@@ -373,7 +378,7 @@ __global__ __launch_bounds__(kGridBlock) void k_nf(DevEvent ev, KParams kp, Scra
   // lanes take the row's clusters in grid order: neighbouring lanes sit at
   // nearby positions and visit similar bins, so a wave diverges less
   for (int ii = tid; ii < e - b; ii += kGridBlock) {
-    const GridRec me = sc.g_rec[b + ii];
+    const GridRec me = ii == tid ? me_first : sc.g_rec[b + ii];
     const int i = me.id;
     const float yc = me.y, zc = me.z;
     float best = INFINITY;
@@ -391,18 +396,22 @@ __global__ __launch_bounds__(kGridBlock) void k_nf(DevEvent ev, KParams kp, Scra
             const float2 pd = s_yz[0][j];
             const int idd = s_id[0][j];
             const float dyd = pd.x - yc, dzd = pd.y - zc;
+            // two pairs per iteration: their LDS loads overlap
+#pragma unroll 2
             for (int q = 0; q < nu; ++q) {
               const int k = s_ul[q][tid];
               const float2 pu = s_yz[1][k];
-              const int idu = s_id[1][k];
               const float ry = dyd + t * ((pu.x - yc) - dyd);
               const float rz = dzd + t * ((pu.y - zc) - dzd);
               const float chi2 = (ry * ry * isy2 + rz * rz * isz2) * inorm;
-              if (bd < 0 || chi2 < best ||
-                  (chi2 == best && (idd < bd || (idd == bd && idu < bu)))) {
-                best = chi2;
-                bd = idd;
-                bu = idu;
+              // the candidate's id only when it can win: most pairs do not
+              if (bd < 0 || chi2 <= best) {
+                const int idu = s_id[1][k];
+                if (bd < 0 || chi2 < best || idd < bd || (idd == bd && idu < bu)) {
+                  best = chi2;
+                  bd = idd;
+                  bu = idu;
+                }
               }
             }
           }
