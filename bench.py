@@ -297,6 +297,12 @@ def merge_section(tr, tpc, synth, geo, prm, e, dev_ev, steps, log_):
         return out
 
     sec = quality.evaluate(e, trk)
+    # the refit's algorithmic work: every list cluster is one helix step
+    # (174 FLOP) and one Kalman update (129 FLOP) in each of the two passes
+    # (FP32 vector ALU; the seed circle and rotations are negligible)
+    refit_ms = st["kernel_ms"]["k_refit"] / max(1, st["kernel_launches"]["k_refit"])
+    refit_flop = 2.0 * (174 + 129) * int(mg["n_clusters"])
+    refit_tf = refit_flop / (refit_ms * 1e-3) / 1e12 if refit_ms > 0 else 0.0
     return dict(workload="benchmark central event: sector tracks joined across sector edges "
                          "and the membrane, refitted from their cluster lists",
                 events_per_s=round(1.0 / merged, 2), ms_per_event=round(merged * 1e3, 4),
@@ -305,6 +311,13 @@ def merge_section(tr, tpc, synth, geo, prm, e, dev_ev, steps, log_):
                 plain_ms_per_event=round(plain * 1e3, 4),
                 kernels_ms={k: round(st["kernel_ms"][k] / max(1, st["kernel_launches"][k]), 5)
                             for k in ks},
+                roofline_refit=dict(bound="alu", achieved=round(refit_tf, 4),
+                                    peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                                    frac=round(refit_tf / PEAK_FP32_TFLOPS, 6),
+                                    kernel="k_refit", kernel_ms=round(refit_ms, 5),
+                                    algorithmic_per_launch=f"{refit_flop:.4g} FLOP",
+                                    note="latency-bound: the longest list is a chain of "
+                                         "dependent Kalman steps"),
                 tracks=int(trk["n_tracks"]), joined_tracks=int(mg["n"]),
                 joins=int(trk["n_tracks"] - mg["n"]),
                 quality_sector_tracks=dict(efficiency=round(sec["efficiency"], 6),
