@@ -231,17 +231,21 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
 // Global tracking after enqueue_event(STAGE_ALL) with Scratch::ends set:
 // prolongs the event's tracks (reads the tracker's cluster_track output);
 // with po == nullptr only the end states are prepared (for the merger).
+// part: 0 = the end states only, 1 = the prolongations only, -1 = both.
 hipError_t enqueue_global(const DevEvent& ev, const KParams& kp, const Scratch& sc,
                           const Outputs& out, const GlobalScratch& gs, const ProOutputs* po,
-                          hipStream_t st, const KernelTimer* timer = nullptr);
+                          hipStream_t st, const KernelTimer* timer = nullptr, int part = -1);
 // The track merger with refit, after enqueue_global; po as given to it.
 size_t merge_bytes(int64_t n_clusters, int64_t n_sectors, int64_t cap_tl, int64_t cap_rec);
 void merge_carve(void* base, int64_t n_clusters, int64_t n_sectors, int64_t cap_tl,
                  int64_t cap_rec, MergeScratch* ms);
+// part: 0 = the joins (need only the end states, so they may run beside the
+// prolongations), 1 = chains, lists and refits (need the prolongations),
+// -1 = both.
 hipError_t enqueue_merge(const DevEvent& ev, const KParams& kp, const Scratch& sc,
                          const Outputs& out, const GlobalScratch& gs, const ProOutputs* po,
                          const MergeScratch& ms, const MergeOutputs& mo, hipStream_t st,
-                         const KernelTimer* timer = nullptr);
+                         const KernelTimer* timer = nullptr, int part = -1);
 // The merger's refit of caller-given cluster lists (after STAGE_GRID, which
 // validates the event): list i = clusters[offsets[i] .. offsets[i+1]),
 // offsets clamped to [0, n_entries].

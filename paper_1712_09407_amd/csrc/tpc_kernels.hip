@@ -2663,7 +2663,7 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
 
 hipError_t enqueue_global(const DevEvent& ev, const KParams& kp, const Scratch& sc,
                           const Outputs& out, const GlobalScratch& gs, const ProOutputs* po,
-                          hipStream_t st, const KernelTimer* tm) {
+                          hipStream_t st, const KernelTimer* tm, int part) {
   auto pre = [&](int k) {
     if (tm && (tm->mask >> k & 1u)) (void)hipEventRecord(tm->ev[k][0], st);
   };
@@ -2675,13 +2675,15 @@ hipError_t enqueue_global(const DevEvent& ev, const KParams& kp, const Scratch& 
                                                               kGridBlock, 1), 2048);
   const int qb = (int)std::min<int64_t>(std::max<int64_t>((Q + kGridBlock - 1) / kGridBlock, 1),
                                         65535);
-  pre(K_PRO_INIT);
-  hipLaunchKernelGGL(k_pro_init, dim3(cb), dim3(kGridBlock), 0, st, ev, sc, gs);
-  post(K_PRO_INIT);
-  pre(K_ENDS);
-  hipLaunchKernelGGL(k_ends, dim3(qb), dim3(kGridBlock), 0, st, kp, sc, gs);
-  post(K_ENDS);
-  if (!po) return hipGetLastError();
+  if (part != 1) {
+    pre(K_PRO_INIT);
+    hipLaunchKernelGGL(k_pro_init, dim3(cb), dim3(kGridBlock), 0, st, ev, sc, gs);
+    post(K_PRO_INIT);
+    pre(K_ENDS);
+    hipLaunchKernelGGL(k_ends, dim3(qb), dim3(kGridBlock), 0, st, kp, sc, gs);
+    post(K_ENDS);
+  }
+  if (!po || part == 0) return hipGetLastError();
   pre(K_PROLONG);
   hipLaunchKernelGGL(k_prolong, dim3(qb), dim3(kGridBlock), 0, st, ev, kp, sc, gs,
                      (const int32_t*)out.cluster_track);
@@ -2758,7 +2760,7 @@ void merge_carve(void* base, int64_t N, int64_t S, int64_t T, int64_t cap_rec,
 hipError_t enqueue_merge(const DevEvent& ev, const KParams& kp, const Scratch& sc,
                          const Outputs& out, const GlobalScratch& gs, const ProOutputs* po,
                          const MergeScratch& ms, const MergeOutputs& mo, hipStream_t st,
-                         const KernelTimer* tm) {
+                         const KernelTimer* tm, int part) {
   auto pre = [&](int k) {
     if (tm && (tm->mask >> k & 1u)) (void)hipEventRecord(tm->ev[k][0], st);
   };
@@ -2769,16 +2771,23 @@ hipError_t enqueue_merge(const DevEvent& ev, const KParams& kp, const Scratch& s
   const int tb = (int)std::min<int64_t>(std::max<int64_t>((T + kGridBlock - 1) / kGridBlock, 1),
                                         65535);
   const int R = ev.n_sectors * kp.n_rows;
-  pre(K_MRG_INIT);
-  hipLaunchKernelGGL(k_mrg_init, dim3(tb), dim3(kGridBlock), 0, st, ev, kp, sc, gs, ms);
-  post(K_MRG_INIT);
-  pre(K_MRG_MATCH);
-  hipLaunchKernelGGL(k_mrg_match, dim3(wave_blocks(T)), dim3(kGridBlock), 0, st, ev, kp, sc, gs,
-                     ms);
-  post(K_MRG_MATCH);
-  pre(K_MRG_LINK);
-  hipLaunchKernelGGL(k_mrg_link, dim3(tb), dim3(kGridBlock), 0, st, sc, ms);
-  post(K_MRG_LINK);
+  if (part != 1) {  // the joins need only the end states (and the event)
+    pre(K_MRG_INIT);
+    hipLaunchKernelGGL(k_mrg_init, dim3(tb), dim3(kGridBlock), 0, st, ev, kp, sc, gs, ms);
+    post(K_MRG_INIT);
+    pre(K_MRG_MATCH);
+    hipLaunchKernelGGL(k_mrg_match, dim3(wave_blocks(T)), dim3(kGridBlock), 0, st, ev, kp, sc,
+                       gs, ms);
+    post(K_MRG_MATCH);
+    pre(K_MRG_LINK);
+    hipLaunchKernelGGL(k_mrg_link, dim3(tb), dim3(kGridBlock), 0, st, sc, ms);
+    post(K_MRG_LINK);
+    pre(K_ROWMAP);
+    hipLaunchKernelGGL(k_rowmap, dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc, ms);
+    post(K_ROWMAP);
+  }
+  if (part == 0) return hipGetLastError();
+  // the chains' lists need the prolongations
   pre(K_MRG_CHAIN);
   hipLaunchKernelGGL(k_mrg_chain, dim3(tb), dim3(kGridBlock), 0, st, sc, gs, ms, out,
                      po ? 1 : 0);
@@ -2804,9 +2813,6 @@ hipError_t enqueue_merge(const DevEvent& ev, const KParams& kp, const Scratch& s
   hipLaunchKernelGGL(k_mrg_write, dim3(wave_blocks(T)), dim3(kGridBlock), 0, st, ev, kp, sc, gs,
                      ms, out, po ? *po : pz, po ? 1 : 0, mo);
   post(K_MRG_WRITE);
-  pre(K_ROWMAP);
-  hipLaunchKernelGGL(k_rowmap, dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc, ms);
-  post(K_ROWMAP);
   pre(K_REFIT_GATHER);
   const int gb = (int)std::min<int64_t>(std::max<int64_t>((ms.cap_rec + kGridBlock - 1) /
                                                               kGridBlock, 1), 4096);

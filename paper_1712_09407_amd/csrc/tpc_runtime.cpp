@@ -40,6 +40,9 @@ struct tpc_ctx {
   int32_t* h_counters = nullptr;  // pinned: sector tracker's, global tracking's, merger's counters
   void* glob_arena = nullptr;     // global tracking scratch
   size_t glob_bytes = 0;
+  // the merger's joins run beside the prolongations on a second stream
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   double learned_ratio = 0.0;  // tracklets per cluster learned from overflows: the
                                // reservation scales with the event (or batch) size
   tpc::KernelTimer timer;   // HIP events around selected kernels
@@ -306,15 +309,35 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
     const bool timed = ctx->timer.mask != 0;
     e = enqueue_event(dev, kp, sc, out, upto, st, timed ? &ctx->timer : nullptr);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
-    if (po || mo) {
-      e = enqueue_global(dev, kp, sc, out, gs, po, st, timed ? &ctx->timer : nullptr);
+    const KernelTimer* tmr = timed ? &ctx->timer : nullptr;
+    if (po && mo) {
+      // end states; then the joins on the side stream while the
+      // prolongations run on st; the lists wait for both
+      if (!ctx->side) {
+        e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "side stream");
+      }
+      e = enqueue_global(dev, kp, sc, out, gs, po, st, tmr, 0);
+      if (e == hipSuccess) e = hipEventRecord(ctx->fork, st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(ctx->side, ctx->fork, 0);
+      if (e == hipSuccess) e = enqueue_merge(dev, kp, sc, out, gs, po, ms, *mo, ctx->side, tmr, 0);
+      if (e == hipSuccess) e = hipEventRecord(ctx->join, ctx->side);
+      if (e == hipSuccess) e = enqueue_global(dev, kp, sc, out, gs, po, st, tmr, 1);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, ctx->join, 0);
       if (e != hipSuccess) return hip_fail(e, "kernel launch (global tracking)");
+    } else if (po || mo) {
+      e = enqueue_global(dev, kp, sc, out, gs, po, st, tmr);
+      if (e != hipSuccess) return hip_fail(e, "kernel launch (global tracking)");
+    }
+    if (po || mo) {
       e = hipMemcpyAsync(ctx->h_counters + C_COUNT, gs.counters, sizeof(int32_t) * C_COUNT,
                          hipMemcpyDeviceToHost, st);
       if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(counters)");
     }
     if (mo) {
-      e = enqueue_merge(dev, kp, sc, out, gs, po, ms, *mo, st, timed ? &ctx->timer : nullptr);
+      e = enqueue_merge(dev, kp, sc, out, gs, po, ms, *mo, st, tmr, po ? 1 : -1);
       if (e != hipSuccess) return hip_fail(e, "kernel launch (merger)");
       e = hipMemcpyAsync(ctx->h_counters + 2 * C_COUNT, ms.counters, sizeof(int32_t) * C_COUNT,
                          hipMemcpyDeviceToHost, st);
@@ -771,6 +794,9 @@ void tpc_ctx_destroy(tpc_ctx* ctx) {
   if (ctx->arena) (void)hipFree(ctx->arena);
   if (ctx->batch_arena) (void)hipFree(ctx->batch_arena);
   if (ctx->glob_arena) (void)hipFree(ctx->glob_arena);
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
+  if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+  if (ctx->join) (void)hipEventDestroy(ctx->join);
   if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
   if (ctx->h_batch) (void)hipHostFree(ctx->h_batch);
   delete ctx;
