@@ -706,21 +706,31 @@ __device__ __forceinline__ int search_row(const Scratch& sc, const RowGrid& g, i
   const int iz0 = bin_z(g, s.z - wz), iz1 = bin_z(g, s.z + wz);
   float best = INFINITY;
   int bid = -1;
-  for (int iz = iz0; iz <= iz1; ++iz) {
-    const int j0 = sc.bins[g.bin_base + iz * g.ny + iy0];
-    const int j1 = sc.bins[g.bin_base + iz * g.ny + iy1 + 1];
-    wk.cands += j1 - j0;
-    for (int j = j0; j < j1; ++j) {
-      const GridRec v = sc.g_rec[rb + j];
-      const float ry = v.y - s.y, rz = v.z - s.z;
-      const float chi2 = (ry * ry * S11 - 2.f * ry * rz * S01 + rz * rz * S00) * idet;
-      if (chi2 <= kp.chi2_gate && (chi2 < best || (chi2 == best && v.id < bid)) &&
-          accept(v.id)) {
-        best = chi2;
-        bid = v.id;
-        by = v.y;
-        bz_ = v.z;
-      }
+  // the best is the smallest (chi^2, id) inside the gate, whatever the order
+  // of the candidates: two bin rows' ranges are loaded together and the
+  // records two at a time, so that one wait covers two loads
+  auto consider = [&](const GridRec& v) {
+    const float ry = v.y - s.y, rz = v.z - s.z;
+    const float chi2 = (ry * ry * S11 - 2.f * ry * rz * S01 + rz * rz * S00) * idet;
+    if (chi2 <= kp.chi2_gate && (chi2 < best || (chi2 == best && v.id < bid)) && accept(v.id)) {
+      best = chi2;
+      bid = v.id;
+      by = v.y;
+      bz_ = v.z;
+    }
+  };
+  for (int iz = iz0; iz <= iz1; iz += 2) {
+    const int ia = g.bin_base + iz * g.ny, ib = g.bin_base + min(iz + 1, iz1) * g.ny;
+    const int a0 = sc.bins[ia + iy0], a1 = sc.bins[ia + iy1 + 1];
+    const int b0 = sc.bins[ib + iy0], b1 = sc.bins[ib + iy1 + 1];
+    const int na = a1 - a0, n = na + (iz + 1 <= iz1 ? b1 - b0 : 0);
+    wk.cands += n;
+    for (int k = 0; k < n; k += 2) {
+      const int k2 = min(k + 1, n - 1);
+      const GridRec v = sc.g_rec[rb + (k < na ? a0 + k : b0 + (k - na))];
+      const GridRec w = sc.g_rec[rb + (k2 < na ? a0 + k2 : b0 + (k2 - na))];
+      consider(v);
+      if (k + 1 < n) consider(w);
     }
   }
   return bid;
