@@ -312,17 +312,261 @@ __device__ __forceinline__ int nf_collect(const RowView& V, float yc, float zc, 
   const int y0 = bin_y(V.g, yc - wy - m), y1 = bin_y(V.g, yc + wy + m);
   const int z0 = bin_z(V.g, zc - wz - m), z1 = bin_z(V.g, zc + wz + m);
   int cnt = 0;
-  for (int iz = z0; iz <= z1; ++iz) {
-    const int j0 = V.bins[iz * V.g.ny + y0], j1 = V.bins[iz * V.g.ny + y1 + 1];
-    for (int j = j0; j < j1; ++j) {
-      const float2 p = V.yz[j];
-      if (in_window(p, yc, zc, wy, wz)) {
-        if (cnt < LIST) list[cnt][lane] = (uint16_t)j;
-        ++cnt;
+  auto take = [&](int j, float2 p) {
+    if (in_window(p, yc, zc, wy, wz)) {
+      if (cnt < LIST) list[cnt][lane] = (uint16_t)j;
+      ++cnt;
+    }
+  };
+  // two bin rows' ranges are read together and the records four at a time,
+  // so that one wait covers several LDS reads; the list keeps bin order
+  for (int iz = z0; iz <= z1; iz += 2) {
+    const int ib = min(iz + 1, z1) * V.g.ny;
+    const int a0 = V.bins[iz * V.g.ny + y0], a1 = V.bins[iz * V.g.ny + y1 + 1];
+    const int b0 = V.bins[ib + y0], b1 = V.bins[ib + y1 + 1];
+    const int na = a1 - a0, n = na + (iz + 1 <= z1 ? b1 - b0 : 0);
+    for (int k = 0; k < n; k += 4) {
+      int j[4];
+      float2 p[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int kk = min(k + u, n - 1);
+        j[u] = kk < na ? a0 + kk : b0 + (kk - na);
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) p[u] = V.yz[j[u]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (k + u < n) take(j[u], p[u]);
     }
   }
   return cnt;
+}
+
+// Pair bookkeeping of one wave: its clusters' first pair, candidate counts
+// in the upper row, coordinates, and best pair keys.
+struct NfPairs {
+  int off[64];
+  int nu[64];
+  float2 c[64];
+  unsigned long long key[64];
+};
+
+// LDS written by other lanes of the wave is visible after this.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Window candidates of one neighbour row for ONE cluster (yc, zc the same in
+// every lane), listed by the whole wave into its columns of list: entry e
+// sits at list[e / 64][col0 + e % 64], in bin order.  Returns the count
+// (the list is incomplete beyond cap entries).
+__device__ __forceinline__ int nf_wave_collect(const RowView& V, float yc, float zc, float wy,
+                                               float wz, uint16_t (*list)[kGridBlock], int cap,
+                                               int col0, int lane) {
+  const float m = 1e-3f;
+  const int y0 = bin_y(V.g, yc - wy - m), y1 = bin_y(V.g, yc + wy + m);
+  const int z0 = bin_z(V.g, zc - wz - m), z1 = bin_z(V.g, zc + wz + m);
+  int cnt = 0;
+  for (int iz = z0; iz <= z1; ++iz) {
+    const int j0 = V.bins[iz * V.g.ny + y0], j1 = V.bins[iz * V.g.ny + y1 + 1];
+    for (int jb = j0; jb < j1; jb += 64) {
+      const int j = jb + lane;
+      const bool in = j < j1 && in_window(V.yz[min(j, j1 - 1)], yc, zc, wy, wz);
+      const unsigned long long bal = __ballot(in);
+      const int pos = cnt + __popcll(bal & ((1ull << lane) - 1ull));
+      if (in && pos < cap) list[pos >> 6][col0 + (pos & 63)] = (uint16_t)j;
+      cnt += __popcll(bal);
+    }
+  }
+  return cnt;
+}
+
+// The best pair key (chi^2 bits, d, u positions; ~0 if none) of ONE cluster
+// at c, searched by the whole wave: both candidate lists, then the pairs
+// dealt out over the lanes and a 64-bit minimum.  *fits is false if a list
+// exceeded cap (the key is then not valid).
+template <int CAP>
+__device__ __forceinline__ unsigned long long nf_wave_pairs(
+    const RowView& D, const RowView& U, float2 c, float t, float inorm, float isy2, float isz2,
+    float wy, float wz, int bd_, int bu_, const int32_t (*s_id)[CAP], uint16_t (*s_dl)[kGridBlock],
+    uint16_t (*s_ul)[kGridBlock], int cap, int col0, int lane, bool* fits) {
+  const int nd = nf_wave_collect(D, c.x, c.y, wy, wz, s_dl, cap, col0, lane);
+  const int nu = nd ? nf_wave_collect(U, c.x, c.y, wy, wz, s_ul, cap, col0, lane) : 0;
+  *fits = nd <= cap && nu <= cap;
+  unsigned long long best = ~0ull;
+  if (!*fits || nu == 0) return best;
+  wave_lds_sync();
+  const int np = nd * nu, dp = 64 / nu, dq = 64 - dp * nu;
+  int p = lane / nu, q = lane - (lane / nu) * nu;
+  for (int k = lane; k < np; k += 64) {
+    const int jd = s_dl[p >> 6][col0 + (p & 63)], ju = s_ul[q >> 6][col0 + (q & 63)];
+    const float2 pd = D.yz[jd], pu = U.yz[ju];
+    const float dyd = pd.x - c.x, dzd = pd.y - c.y;
+    const float ry = dyd + t * ((pu.x - c.x) - dyd);
+    const float rz = dzd + t * ((pu.y - c.y) - dzd);
+    const float chi2 = (ry * ry * isy2 + rz * rz * isz2) * inorm;
+    const unsigned long long hi = (unsigned long long)__float_as_uint(chi2) << 32;
+    if (hi <= best)
+      best = min(best, hi | ((unsigned long long)(s_id[0][jd] - bd_) << 16) |
+                           (unsigned)(s_id[1][ju] - bu_));
+    q += dq;
+    p += dp;
+    if (q >= nu) {
+      q -= nu;
+      ++p;
+    }
+  }
+  for (int d = 32; d >= 1; d >>= 1) best = min(best, __shfl_xor(best, d, 64));
+  return best;
+}
+
+// The staged neighbour search of a row's clusters (section 1), one cluster
+// per lane.  Each lane lists its window candidates in both neighbour rows;
+// then the pairs of the wave's 64 clusters are dealt out evenly (each lane
+// walks a contiguous run of them), so that a dense cluster does not hold up
+// its wave.  The best pair of a cluster is the smallest (chi^2, d, u), with
+// d and u the clusters' positions in their rows (16 bits each; the cluster
+// indices of a row are contiguous, so this is the order of the indices),
+// whichever lane evaluated it: one 64-bit minimum per cluster in LDS.  A
+// cluster with more than LIST candidates in a row is searched by the whole
+// wave afterwards (nf_wave_pairs).
+template <int CAP, int LIST>
+__device__ __forceinline__ void nf_pairs_staged(
+    const DevEvent& ev, const KParams& kp, const Scratch& sc, int b, int e, int bd_, int bu_,
+    const RowGrid& gd, const RowGrid& gu, const GridRec& me_first, float t, float inorm,
+    float isy2, float isz2, float wy, float wz, float2 (*s_yz)[CAP], int32_t (*s_id)[CAP],
+    int32_t (*s_bins)[CAP + 1], uint16_t (*s_dl)[kGridBlock], uint16_t (*s_ul)[kGridBlock],
+    NfPairs* s_pw) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, col0 = tid - lane;
+  NfPairs& P = s_pw[w];
+  const RowView D{s_yz[0], s_id[0], s_bins[0], gd}, U{s_yz[1], s_id[1], s_bins[1], gu};
+  const bool both = gd.n > 0 && gu.n > 0;
+  for (int base = col0; base < e - b; base += kGridBlock) {  // uniform over the wave
+    const int ii = base + lane;
+    const bool have = ii < e - b;
+    GridRec me = {};
+    if (have) me = ii == tid ? me_first : sc.g_rec[b + ii];
+    const float yc = me.y, zc = me.z;
+    int nd = 0, nu = 0;
+    if (have && both) {
+      nd = nf_collect<LIST>(D, yc, zc, wy, wz, s_dl, tid);
+      nu = nd ? nf_collect<LIST>(U, yc, zc, wy, wz, s_ul, tid) : 0;
+    }
+    const bool listed = nd <= LIST && nu <= LIST;
+    const int np = listed ? nd * nu : 0;
+    int incl = np;  // inclusive scan over the wave
+    for (int d = 1; d < 64; d <<= 1) {
+      const int v = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += v;
+    }
+    const int total = __shfl(incl, 63, 64);
+    P.off[lane] = incl - np;
+    P.nu[lane] = nu;
+    P.c[lane] = make_float2(yc, zc);
+    P.key[lane] = ~0ull;
+    wave_lds_sync();
+    // this lane's run [k, kend) of the wave's pairs
+    const int per = (total + 63) >> 6;
+    int k = min(lane * per, total);
+    const int kend = min(k + per, total);
+    if (k < kend) {
+      int o = 0;  // owner: the last cluster whose first pair is <= k
+      for (int step = 32; step >= 1; step >>= 1)
+        if (o + step < 64 && P.off[o + step] <= k) o += step;
+      int nu_o = P.nu[o];
+      int next = o < 63 ? P.off[o + 1] : total;
+      float2 c = P.c[o];
+      int rel = k - P.off[o];
+      int p = rel / nu_o, q = rel - p * nu_o;
+      int jd = s_dl[p][col0 + o];
+      float2 pd = s_yz[0][jd];
+      float dyd = pd.x - c.x, dzd = pd.y - c.y;
+      unsigned long long kd = (unsigned long long)(s_id[0][jd] - bd_) << 16;
+      unsigned long long best = ~0ull;
+      auto pair = [&](int ku, float2 pu) {
+        const float ry = dyd + t * ((pu.x - c.x) - dyd);
+        const float rz = dzd + t * ((pu.y - c.y) - dzd);
+        const float chi2 = (ry * ry * isy2 + rz * rz * isz2) * inorm;
+        const unsigned long long hi = (unsigned long long)__float_as_uint(chi2) << 32;
+        // the candidate's index only when it can win: most pairs do not
+        if (hi <= best) best = min(best, hi | kd | (unsigned)(s_id[1][ku] - bu_));
+      };
+      while (true) {
+        // up to four pairs of the same (cluster, d) at once: their LDS reads
+        // overlap
+        const int m = min(4, min(nu_o - q, kend - k));
+        const int col = col0 + o;
+        const int ku0 = s_ul[q][col], ku1 = s_ul[q + (m > 1)][col];
+        const int ku2 = s_ul[q + (m > 2 ? 2 : 0)][col], ku3 = s_ul[q + (m > 3 ? 3 : 0)][col];
+        const float2 pu0 = s_yz[1][ku0], pu1 = s_yz[1][ku1], pu2 = s_yz[1][ku2], pu3 = s_yz[1][ku3];
+        pair(ku0, pu0);
+        if (m > 1) pair(ku1, pu1);
+        if (m > 2) pair(ku2, pu2);
+        if (m > 3) pair(ku3, pu3);
+        k += m;
+        q += m - 1;
+        if (k == kend) break;
+        if (k == next) {  // the next cluster with pairs
+          atomicMin(&P.key[o], best);
+          best = ~0ull;
+          do {
+            ++o;
+          } while (o < 63 && P.off[o + 1] <= k);
+          nu_o = P.nu[o];
+          next = o < 63 ? P.off[o + 1] : total;
+          c = P.c[o];
+          p = q = 0;
+        } else if (++q == nu_o) {
+          q = 0;
+          ++p;
+        } else {
+          continue;
+        }
+        jd = s_dl[p][col0 + o];
+        pd = s_yz[0][jd];
+        dyd = pd.x - c.x;
+        dzd = pd.y - c.y;
+        kd = (unsigned long long)(s_id[0][jd] - bd_) << 16;
+      }
+      atomicMin(&P.key[o], best);
+    }
+    wave_lds_sync();
+    unsigned long long key = P.key[lane];
+    bool alone = false;
+    // a cluster with more than LIST candidates in a row: the wave takes each
+    // in turn, listing its candidates in the wave's columns of the lists
+    // (free now) and sharing its pairs
+    for (unsigned long long ov = __ballot(!listed); ov; ov &= ov - 1ull) {
+      const int o = __ffsll((unsigned long long)ov) - 1;
+      bool fits;
+      const unsigned long long ko = nf_wave_pairs<CAP>(D, U, P.c[o], t, inorm, isy2, isz2, wy, wz,
+                                                       bd_, bu_, s_id, s_dl, s_ul, LIST * 64,
+                                                       col0, lane, &fits);
+      if (lane == o) {
+        key = ko;
+        alone = !fits;
+      }
+      wave_lds_sync();  // the lists are rewritten for the next one
+    }
+    float best = INFINITY;
+    int bd = -1, bu = -1;
+    if (alone) {  // even the wave's lists overflow: nested bin scans
+      nf_search(D, U, yc, zc, t, wy, wz, isy2, isz2, inorm, best, bd, bu);
+    } else if (key != ~0ull) {
+      best = __uint_as_float((unsigned)(key >> 32));
+      bd = bd_ + (int)((key >> 16) & 0xffffu);
+      bu = bu_ + (int)(key & 0xffffu);
+    }
+    if (have) {
+      const bool ok = bd >= 0 && best <= kp.nf_chi2_max;
+      sc.up[me.id] = ok ? bu : -1;
+      sc.dn[me.id] = ok ? bd : -1;
+    }
+    wave_lds_sync();  // P is rewritten by the next round
+  }
 }
 
 template <int CAP, int LIST>
@@ -332,6 +576,7 @@ __global__ __launch_bounds__(kGridBlock) void k_nf(DevEvent ev, KParams kp, Scra
   __shared__ int32_t s_bins[2][CAP + 1];
   __shared__ uint16_t s_dl[LIST][kGridBlock];
   __shared__ uint16_t s_ul[LIST][kGridBlock];
+  __shared__ NfPairs s_pw[kGridBlock / 64];
   if (event_bad(sc.counters)) return;
   const int rs = blockIdx.x;
   const int r = rs % kp.n_rows;
@@ -351,7 +596,8 @@ __global__ __launch_bounds__(kGridBlock) void k_nf(DevEvent ev, KParams kp, Scra
   if (tid < e - b) me_first = sc.g_rec[b + tid];
   const RowGrid gd = sc.grid[rs - 1], gu = sc.grid[rs + 1];
   const int bd_ = ev.ro[rs - 1], bu_ = ev.ro[rs + 1];
-  const bool stage = gd.n <= CAP && gu.n <= CAP;
+  // staged: both rows fit the LDS stage, and positions in them fit 16 bits
+  const bool stage = gd.n <= CAP && gu.n <= CAP && b - bd_ <= 65536 && ev.ro[rs + 2] - bu_ <= 65536;
   const float xd = kp.row_x[r - 1], xc = kp.row_x[r], xu = kp.row_x[r + 1];
   const float t = (xc - xd) / (xu - xd);
   const float inorm = 1.f / (1.f + t * t + (1.f - t) * (1.f - t));
@@ -377,52 +623,20 @@ __global__ __launch_bounds__(kGridBlock) void k_nf(DevEvent ev, KParams kp, Scra
   }
   // lanes take the row's clusters in grid order: neighbouring lanes sit at
   // nearby positions and visit similar bins, so a wave diverges less
+  if (stage) {
+    nf_pairs_staged<CAP, LIST>(ev, kp, sc, b, e, bd_, bu_, gd, gu, me_first, t, inorm, isy2, isz2,
+                               wy, wz, s_yz, s_id, s_bins, s_dl, s_ul, s_pw);
+    return;
+  }
   for (int ii = tid; ii < e - b; ii += kGridBlock) {
     const GridRec me = ii == tid ? me_first : sc.g_rec[b + ii];
     const int i = me.id;
-    const float yc = me.y, zc = me.z;
     float best = INFINITY;
     int bd = -1, bu = -1;
     if (gd.n > 0 && gu.n > 0) {
-      if (stage) {
-        const RowView D{s_yz[0], s_id[0], s_bins[0], gd}, U{s_yz[1], s_id[1], s_bins[1], gu};
-        // candidates of each neighbour row once, then the pairs: no nested
-        // bin scans, so lanes of a wave stay in step
-        const int nd = nf_collect<LIST>(D, yc, zc, wy, wz, s_dl, tid);
-        const int nu = nd ? nf_collect<LIST>(U, yc, zc, wy, wz, s_ul, tid) : 0;
-        if (nd <= LIST && nu <= LIST) {
-          for (int p = 0; p < nd; ++p) {
-            const int j = s_dl[p][tid];
-            const float2 pd = s_yz[0][j];
-            const int idd = s_id[0][j];
-            const float dyd = pd.x - yc, dzd = pd.y - zc;
-            // two pairs per iteration: their LDS loads overlap
-#pragma unroll 2
-            for (int q = 0; q < nu; ++q) {
-              const int k = s_ul[q][tid];
-              const float2 pu = s_yz[1][k];
-              const float ry = dyd + t * ((pu.x - yc) - dyd);
-              const float rz = dzd + t * ((pu.y - zc) - dzd);
-              const float chi2 = (ry * ry * isy2 + rz * rz * isz2) * inorm;
-              // the candidate's id only when it can win: most pairs do not
-              if (bd < 0 || chi2 <= best) {
-                const int idu = s_id[1][k];
-                if (bd < 0 || chi2 < best || idd < bd || (idd == bd && idu < bu)) {
-                  best = chi2;
-                  bd = idd;
-                  bu = idu;
-                }
-              }
-            }
-          }
-        } else {
-          nf_search(D, U, yc, zc, t, wy, wz, isy2, isz2, inorm, best, bd, bu);
-        }
-      } else {
-        const RowViewG D{sc.g_rec + bd_, sc.bins + gd.bin_base, gd};
-        const RowViewG U{sc.g_rec + bu_, sc.bins + gu.bin_base, gu};
-        nf_search(D, U, yc, zc, t, wy, wz, isy2, isz2, inorm, best, bd, bu);
-      }
+      const RowViewG D{sc.g_rec + bd_, sc.bins + gd.bin_base, gd};
+      const RowViewG U{sc.g_rec + bu_, sc.bins + gu.bin_base, gu};
+      nf_search(D, U, me.y, me.z, t, wy, wz, isy2, isz2, inorm, best, bd, bu);
     }
     const bool ok = bd >= 0 && best <= kp.nf_chi2_max;
     sc.up[i] = ok ? bu : -1;
