@@ -11,7 +11,7 @@ import os
 import time
 
 CANDIDATES = ([dict(construct_schedule=0, construct_blocks=0, construct_lanes=a, bin_occupancy=o)
-               for a in (0, 16, 64) for o in (1.0, 2.0)] +
+               for a in (0, 16, 32, 64) for o in (1.0, 2.0)] +
               [dict(construct_schedule=1, construct_blocks=0, bin_occupancy=1.0)])
 
 
