@@ -901,7 +901,7 @@ struct Work {
 };
 
 struct AcceptAll {
-  __device__ bool operator()(int) const { return true; }
+  __device__ bool operator()(const GridRec&) const { return true; }
 };
 
 // Best cluster of a row inside the chi^2 gate (smallest (chi2, index)) among
@@ -926,7 +926,7 @@ __device__ __forceinline__ int search_row(const Scratch& sc, const RowGrid& g, i
   auto consider = [&](const GridRec& v) {
     const float ry = v.y - s.y, rz = v.z - s.z;
     const float chi2 = (ry * ry * S11 - 2.f * ry * rz * S01 + rz * rz * S00) * idet;
-    if (chi2 <= kp.chi2_gate && (chi2 < best || (chi2 == best && v.id < bid)) && accept(v.id)) {
+    if (chi2 <= kp.chi2_gate && (chi2 < best || (chi2 == best && v.id < bid)) && accept(v)) {
       best = chi2;
       bid = v.id;
       by = v.y;
@@ -1847,13 +1847,29 @@ __global__ __launch_bounds__(kGridBlock) void k_output(DevEvent ev, KParams kp, 
 // numbers the slots that own at least one, and k_pro_output writes them in
 // (track, end) order.
 
-__global__ __launch_bounds__(kGridBlock) void k_pro_init(DevEvent ev, Scratch sc,
-                                                         GlobalScratch gs) {
+__global__ __launch_bounds__(kGridBlock) void k_pro_init(DevEvent ev, KParams kp, Scratch sc,
+                                                         GlobalScratch gs,
+                                                         const int32_t* cluster_track) {
   __shared__ int s_p2s[kLayoutSectors];
   const int n_cl = ev.n_dev ? *ev.n_dev : ev.n_clusters;
   const int stride = gridDim.x * kGridBlock;
   for (int i = blockIdx.x * kGridBlock + threadIdx.x; i < n_cl; i += stride)
     gs.claim[i] = 0x7fffffff;
+  // the sector tracker's ownership into the grid records' spare word (for
+  // the prolongations' free-cluster test), row slot by row slot: a row's
+  // first bins[ny * nz] records are its clusters.  Nothing to do after an
+  // error of the tracker (no prolongation then) or without prolongations.
+  if (cluster_track && sc.counters[C_ERR] == 0) {
+    const int R = ev.n_sectors * kp.n_rows;
+    for (int rs = blockIdx.x; rs < R; rs += gridDim.x) {
+      const RowGrid g = sc.grid[rs];
+      if (g.n == 0) continue;
+      const int cnt = sc.bins[g.bin_base + g.ny * g.nz];
+      GridRec* rec = sc.g_rec + ev.ro[rs];
+      for (int j = threadIdx.x; j < cnt; j += kGridBlock)
+        rec[j].pad = cluster_track[rec[j].id] >= 0 ? 1 : 0;
+    }
+  }
   if (blockIdx.x != 0) return;
   if (threadIdx.x < kLayoutSectors) s_p2s[threadIdx.x] = 0x7fffffff;
   __syncthreads();
@@ -1967,15 +1983,16 @@ __device__ __forceinline__ bool step_par(HelixPar& h, float x2, const KParams& k
   return true;
 }
 
+// A cluster no sector track owns: k_pro_init copies the sector tracker's
+// cluster_track into the grid records' spare word (1 = owned), so the test
+// reads the record the search already holds.
 struct FreeCluster {
-  const int32_t* cluster_track;
-  __device__ bool operator()(int c) const { return cluster_track[c] < 0; }
+  __device__ bool operator()(const GridRec& v) const { return v.pad == 0; }
 };
 
 // Prolongation of slot q; returns the number of clusters collected.
 __device__ int prolong_slot(int q, const DevEvent& ev, const KParams& kp, const Scratch& sc,
-                            const GlobalScratch& gs, const int32_t* cluster_track,
-                            const float* s_x) {
+                            const GlobalScratch& gs, const float* s_x) {
   const int t = q >> 1, e = q & 1, dir = e ? 1 : -1, nr = kp.n_rows;
   const int row = e ? sc.row_hi[t] : sc.row_lo[t];
   const float* E = sc.ends + (size_t)q * kEndStride;
@@ -2016,7 +2033,7 @@ __device__ int prolong_slot(int q, const DevEvent& ev, const KParams& kp, const 
     while (r < nr && s_x[r] <= s.x) ++r;
   int32_t* H = gs.hit + (size_t)q * kHitStride;
   float* P = gs.par + (size_t)q * 8;
-  const FreeCluster free_only{cluster_track};
+  const FreeCluster free_only{};
   Work wk;
   int misses = 0, n = 0;
   float chi2 = 0.f;
@@ -2050,8 +2067,7 @@ __device__ int prolong_slot(int q, const DevEvent& ev, const KParams& kp, const 
 }
 
 __global__ __launch_bounds__(kGridBlock) void k_prolong(DevEvent ev, KParams kp, Scratch sc,
-                                                        GlobalScratch gs,
-                                                        const int32_t* cluster_track) {
+                                                        GlobalScratch gs) {
   __shared__ float s_x[TPC_MAX_ROWS];
   for (int i = threadIdx.x; i < kp.n_rows; i += kGridBlock) s_x[i] = kp.row_x[i];
   __syncthreads();
@@ -2060,7 +2076,7 @@ __global__ __launch_bounds__(kGridBlock) void k_prolong(DevEvent ev, KParams kp,
   const int n_act = 2 * sc.counters[C_TRACKS];
   for (int i = blockIdx.x * kGridBlock + threadIdx.x; i < n_act; i += gridDim.x * kGridBlock) {
     const int q = gs.act[i];
-    gs.n[q] = prolong_slot(q, ev, kp, sc, gs, cluster_track, s_x);
+    gs.n[q] = prolong_slot(q, ev, kp, sc, gs, s_x);
   }
 }
 
@@ -2901,7 +2917,8 @@ hipError_t enqueue_global(const DevEvent& ev, const KParams& kp, const Scratch& 
                                         65535);
   if (part != 1) {
     pre(K_PRO_INIT);
-    hipLaunchKernelGGL(k_pro_init, dim3(cb), dim3(kGridBlock), 0, st, ev, sc, gs);
+    hipLaunchKernelGGL(k_pro_init, dim3(cb), dim3(kGridBlock), 0, st, ev, kp, sc, gs,
+                       po ? (const int32_t*)out.cluster_track : nullptr);
     post(K_PRO_INIT);
     pre(K_ENDS);
     hipLaunchKernelGGL(k_ends, dim3(qb), dim3(kGridBlock), 0, st, kp, sc, gs);
@@ -2909,8 +2926,7 @@ hipError_t enqueue_global(const DevEvent& ev, const KParams& kp, const Scratch& 
   }
   if (!po || part == 0) return hipGetLastError();
   pre(K_PROLONG);
-  hipLaunchKernelGGL(k_prolong, dim3(qb), dim3(kGridBlock), 0, st, ev, kp, sc, gs,
-                     (const int32_t*)out.cluster_track);
+  hipLaunchKernelGGL(k_prolong, dim3(qb), dim3(kGridBlock), 0, st, ev, kp, sc, gs);
   post(K_PROLONG);
   pre(K_PRO_OWN);
   hipLaunchKernelGGL(k_pro_own, dim3(qb), dim3(kGridBlock), 0, st, sc, gs);
