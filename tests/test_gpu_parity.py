@@ -9,6 +9,8 @@ matched tracks' parameters within 1e-3 relative.
 """
 import os
 
+import types
+
 import numpy as np
 import pytest
 
@@ -274,6 +276,43 @@ def test_dense_rows_use_the_global_memory_path(orc, tracker, geo):
     res = tpc.to_numpy(tracker.track_event(dev_event(e), geo, e.bz, pg))
     ref = orc.track_event(event_dict(e), GEO_T, e.bz, po)
     assert concordance.compare(ref, res, e.n_clusters)["cluster_concordance"] >= 0.999
+
+
+def crowded_event(seed, noise_frac, n_hot):
+    """One sector with a hot spot of n_hot clusters in a 6 x 6 cm box on every
+    row: each of them sees about n_hot window candidates in both neighbour
+    rows, more than a lane's candidate list holds."""
+    cfg = synth.EventConfig(n_tracks=100, sectors=(0,), phi_range_deg=(0, 20),
+                            ignore_membrane=True, noise_frac=noise_frac)
+    e = synth.make_event(cfg, seed)
+    rng = np.random.default_rng(seed)
+    ys, zs, ro = [], [], [0]
+    for r in range(e.row_offsets.shape[0] - 1):
+        a, b = e.row_offsets[r], e.row_offsets[r + 1]
+        ys += [e.y[a:b], rng.uniform(-3.0, 3.0, n_hot).astype(np.float32)]
+        zs += [e.z[a:b], rng.uniform(97.0, 103.0, n_hot).astype(np.float32)]
+        ro.append(ro[-1] + (b - a) + n_hot)
+    return types.SimpleNamespace(y=np.concatenate(ys), z=np.concatenate(zs),
+                                 row_offsets=np.array(ro, np.int32), sector_id=e.sector_id,
+                                 bz=e.bz, n_clusters=int(ro[-1]))
+
+
+@pytest.mark.parametrize("noise_frac,n_hot", [(0.0, 30), (3.0, 140)])
+def test_crowded_windows_match_the_oracle(orc, tracker, geo, noise_frac, n_hot):
+    """Clusters with more window candidates than a lane's list (16 on sparse
+    rows, 32 on dense ones, about 300 clusters per row and more) are searched
+    by the whole wave: the links are the oracle's (up to near-ties)."""
+    e = crowded_event(41, noise_frac, n_hot)
+    say("crowded", noise_frac, n_hot, e.n_clusters)
+    dense = e.n_clusters > 320 * (e.row_offsets.shape[0] - 1)
+    assert dense == (n_hot > 32)
+    pg, po = params_pair(orc)
+    up, dn, _, _ = (x.cpu().numpy() for x in tracker.links(dev_event(e), geo, pg))
+    uo, do_ = orc.neighbours(event_dict(e), GEO_T, po)
+    assert check_links(orc, e, po, up, dn, uo, do_) <= max(2, 1e-5 * e.n_clusters)
+    hot = np.concatenate([np.arange(e.row_offsets[r + 1] - n_hot, e.row_offsets[r + 1])
+                          for r in range(1, e.row_offsets.shape[0] - 2)])
+    assert (up[hot] >= 0).mean() > 0.9                    # the hot spot links up
 
 
 def test_invalid_offsets_and_nonfinite(tracker, geo):
