@@ -2428,24 +2428,25 @@ __global__ __launch_bounds__(kGridBlock) void k_rowmap(DevEvent ev, KParams kp, 
   for (int c = a + threadIdx.x; c < b; c += kGridBlock) ms.rowslot[c] = rs;
 }
 
-// A list entry as the refit reads it: coordinates and row slot of the
-// cluster (row slot -1: not a cluster of the event).
-__device__ __forceinline__ float4 list_rec(const DevEvent& ev, const MergeScratch& ms, int c) {
+// A list entry as the refit reads it: coordinates, row slot and sector slot
+// of the cluster (both -1: not a cluster of the event).
+__device__ __forceinline__ float4 list_rec(const DevEvent& ev, const MergeScratch& ms, int nr,
+                                           int c) {
   const int rs = (c >= 0 && c < ev.n_clusters) ? ms.rowslot[c] : -1;
-  return rs >= 0 ? make_float4(ev.y[c], ev.z[c], __int_as_float(rs), 0.f)
-                 : make_float4(0.f, 0.f, __int_as_float(-1), 0.f);
+  return rs >= 0 ? make_float4(ev.y[c], ev.z[c], __int_as_float(rs), __int_as_float(rs / nr))
+                 : make_float4(0.f, 0.f, __int_as_float(-1), __int_as_float(-1));
 }
 
 // The entries of the lists, gathered once (all entries in parallel), so that
 // the refit walks a contiguous 16-byte record per cluster.
-__global__ __launch_bounds__(kGridBlock) void k_refit_gather(DevEvent ev, Scratch sc,
+__global__ __launch_bounds__(kGridBlock) void k_refit_gather(DevEvent ev, int nr, Scratch sc,
                                                              MergeScratch ms, const int32_t* n_dev,
                                                              int n_host, const int32_t* clusters) {
   if (event_bad(sc.counters)) return;
   if (n_dev && __builtin_nontemporal_load(&ms.counters[C_ERR]) != 0) return;
   const int n = min(n_dev ? *n_dev : n_host, ms.cap_rec);
   for (int e = blockIdx.x * kGridBlock + threadIdx.x; e < n; e += gridDim.x * kGridBlock)
-    ms.rec[e] = list_rec(ev, ms, clusters[e]);
+    ms.rec[e] = list_rec(ev, ms, nr, clusters[e]);
 }
 
 // The refit of one list (path order, records R[0 .. n)): the seed circle of
@@ -2459,36 +2460,43 @@ __global__ __launch_bounds__(kGridBlock) void k_refit_gather(DevEvent ev, Scratc
 // go (together they see every entry).  P = x, state at the innermost fitted
 // cluster, chi^2, ndf (all 0 and frame -1 if the refit fails).  The next
 // record is loaded a step ahead.
+constexpr int kRefitSlots = 1024;  // sector ids staged in LDS by k_refit
+
+// sid: the sector id of each slot (slot < n_sid; others are read from the
+// event).
 __device__ void refit_list(const float4* R, int n, const DevEvent& ev, const KParams& kp,
-                           const float* s_x, float* P, int32_t* frame) {
+                           const float* s_x, const int32_t* sid, int n_sid, float* P,
+                           int32_t* frame) {
   const int nr = kp.n_rows;
   for (int i = 0; i < 8; ++i) P[i] = 0.f;
   *frame = -1;
   if (n < 3) return;
+  auto sector_id = [&](int sl) { return sl < n_sid ? sid[sl] : ev.sector_id[sl]; };
+  auto slot = [](const float4& r) { return __float_as_int(r.w); };
   bool bad = false, multi = false, bad_id = false;
   int s_first = -1;
-  auto note = [&](int rs) {  // validity and the sectors seen
-    if (rs < 0) {
+  auto note = [&](const float4& r) {  // validity and the sectors seen
+    const int sl = slot(r);
+    if (sl < 0) {
       bad = true;
       return;
     }
-    const int sl = rs / nr;
     if (s_first < 0) s_first = sl;
     multi |= sl != s_first;
-    const int ph = ev.sector_id[sl];
+    const int ph = sector_id(sl);
     bad_id |= ph < 0 || ph >= kLayoutSectors;
   };
   // the seed run: sliding window of three records
   int i0 = -1;
   float4 ra = R[0], rb = R[1];
-  note(__float_as_int(ra.z));
-  note(__float_as_int(rb.z));
+  note(ra);
+  note(rb);
   for (int i = 0; i + 2 < n; ++i) {
     const float4 rc = R[i + 2];
-    note(__float_as_int(rc.z));
+    note(rc);
     const int xa = __float_as_int(ra.z), xb = __float_as_int(rb.z), xc = __float_as_int(rc.z);
-    if (xa >= 0 && xb >= 0 && xc >= 0 && xb / nr == xa / nr && xc / nr == xa / nr && xa < xb &&
-        xb < xc) {
+    if (xa >= 0 && xb >= 0 && xc >= 0 && slot(rb) == slot(ra) && slot(rc) == slot(ra) &&
+        xa < xb && xb < xc) {
       i0 = i;
       break;
     }
@@ -2496,11 +2504,12 @@ __device__ void refit_list(const float4* R, int n, const DevEvent& ev, const KPa
     rb = rc;
   }
   if (i0 < 0 || bad) return;
-  const int rs0 = __float_as_int(R[i0].z), sl0 = rs0 / nr;
+  const int rs0 = __float_as_int(R[i0].z), sl0 = slot(R[i0]);
   int m = 1, prs = rs0;
   while (i0 + m < n && m < kp.seed_window) {
-    const int rs = __float_as_int(R[i0 + m].z);
-    if (rs < 0 || rs / nr != sl0 || !(rs > prs)) break;
+    const float4 rm = R[i0 + m];
+    const int rs = __float_as_int(rm.z);
+    if (rs < 0 || slot(rm) != sl0 || !(rs > prs)) break;
     prs = rs;
     ++m;
   }
@@ -2517,11 +2526,11 @@ __device__ void refit_list(const float4* R, int n, const DevEvent& ev, const KPa
     const float4 cur = nx;
     if (j + 1 < n) nx = R[j + 1];
     const int rs = __float_as_int(cur.z);
-    note(rs);
+    note(cur);
     if (rs < 0 || (multi && bad_id)) continue;
-    const int sl = rs / nr;
+    const int sl = slot(cur);
     KState t = s;
-    if (sl != fr && !rotate_steps(t, frame_steps(ev.sector_id[fr], ev.sector_id[sl]), kp)) continue;
+    if (sl != fr && !rotate_steps(t, frame_steps(sector_id(fr), sector_id(sl)), kp)) continue;
     if (!propagate(t, s_x[rs - sl * nr], kp)) continue;
     kf_update(t, cur.x, cur.y, kp);
     s = t;
@@ -2533,7 +2542,7 @@ __device__ void refit_list(const float4* R, int n, const DevEvent& ev, const KPa
   const float4 L = R[last];
   const int rsl = __float_as_int(L.z);
   KState w;
-  w.x = s_x[rsl - (rsl / nr) * nr];
+  w.x = s_x[rsl - slot(L) * nr];
   w.y = L.x;
   w.z = L.y;
   w.sp = s.sp;
@@ -2541,16 +2550,16 @@ __device__ void refit_list(const float4* R, int n, const DevEvent& ev, const KPa
   w.qpt = s.qpt;
   reset_cov(w.C, kp);
   float chi2 = 0.f;
-  int nn = 1, ifr = rsl / nr;
+  int nn = 1, ifr = slot(L);
   float o[6] = {w.x, w.y, w.z, w.sp, w.tl, w.qpt};
   nx = last > 0 ? R[last - 1] : make_float4(0.f, 0.f, 0.f, 0.f);
   for (int j = last - 1; j >= 0; --j) {
     const float4 cur = nx;
     if (j > 0) nx = R[j - 1];
     const int rs = __float_as_int(cur.z);
-    const int sl = rs / nr;
+    const int sl = slot(cur);
     KState t = w;
-    if (sl != fr && !rotate_steps(t, frame_steps(ev.sector_id[fr], ev.sector_id[sl]), kp)) continue;
+    if (sl != fr && !rotate_steps(t, frame_steps(sector_id(fr), sector_id(sl)), kp)) continue;
     if (!propagate(t, s_x[rs - sl * nr], kp)) continue;
     chi2 += kf_update(t, cur.x, cur.y, kp);
     w = t;
@@ -2563,7 +2572,7 @@ __device__ void refit_list(const float4* R, int n, const DevEvent& ev, const KPa
   for (int i = 0; i < 6; ++i) P[i] = o[i];
   P[6] = chi2;
   P[7] = (float)(2 * nn - 5);
-  *frame = ev.sector_id[ifr];
+  *frame = sector_id(ifr);
 }
 
 // One lane per list over the gathered records.  n_lists is read from n_dev
@@ -2575,7 +2584,10 @@ __global__ __launch_bounds__(kGridBlock) void k_refit(DevEvent ev, KParams kp, S
                                                       const int32_t* offsets, float* par,
                                                       int32_t* frame, int32_t* meta_frame) {
   __shared__ float s_x[TPC_MAX_ROWS];
+  __shared__ int32_t s_sid[kRefitSlots];  // sector ids of the first slots
   for (int i = threadIdx.x; i < kp.n_rows; i += kGridBlock) s_x[i] = kp.row_x[i];
+  const int n_sid = min(ev.n_sectors, kRefitSlots);
+  for (int i = threadIdx.x; i < n_sid; i += kGridBlock) s_sid[i] = ev.sector_id[i];
   __syncthreads();
   if (event_bad(sc.counters)) return;
   if (n_dev && __builtin_nontemporal_load(&ms.counters[C_ERR]) != 0) return;
@@ -2587,7 +2599,7 @@ __global__ __launch_bounds__(kGridBlock) void k_refit(DevEvent ev, KParams kp, S
     b = clampi(b, a, lim);
     float P[8];
     int32_t f;
-    refit_list(ms.rec + a, b - a, ev, kp, s_x, P, &f);
+    refit_list(ms.rec + a, b - a, ev, kp, s_x, s_sid, n_sid, P, &f);
     for (int i = 0; i < 8; ++i) par[(size_t)k * 8 + i] = P[i];
     if (frame) frame[k] = f;
     if (meta_frame && f >= 0) meta_frame[(size_t)k * 5] = f;
@@ -3056,7 +3068,7 @@ hipError_t enqueue_merge(const DevEvent& ev, const KParams& kp, const Scratch& s
   pre(K_REFIT_GATHER);
   const int gb = (int)std::min<int64_t>(std::max<int64_t>((ms.cap_rec + kGridBlock - 1) /
                                                               kGridBlock, 1), 4096);
-  hipLaunchKernelGGL(k_refit_gather, dim3(gb), dim3(kGridBlock), 0, st, ev, sc, ms,
+  hipLaunchKernelGGL(k_refit_gather, dim3(gb), dim3(kGridBlock), 0, st, ev, kp.n_rows, sc, ms,
                      (const int32_t*)&ms.counters[C_TRACK_CLUSTERS], 0,
                      (const int32_t*)mo.cluster);
   post(K_REFIT_GATHER);
@@ -3086,8 +3098,8 @@ hipError_t enqueue_refit(const DevEvent& ev, const KParams& kp, const Scratch& s
     if (n_entries > 0) {
       const int gb = std::min((n_entries + kGridBlock - 1) / kGridBlock, 4096);
       pre(K_REFIT_GATHER);
-      hipLaunchKernelGGL(k_refit_gather, dim3(gb), dim3(kGridBlock), 0, st, ev, sc, ms,
-                         (const int32_t*)nullptr, n_entries, clusters);
+      hipLaunchKernelGGL(k_refit_gather, dim3(gb), dim3(kGridBlock), 0, st, ev, kp.n_rows, sc,
+                         ms, (const int32_t*)nullptr, n_entries, clusters);
       post(K_REFIT_GATHER);
     }
     const int lb = std::min((n_lists + kGridBlock - 1) / kGridBlock, 65535);
