@@ -207,6 +207,36 @@ def test_refit_edge_cases(tracker, geo):
         tracker.refit(bad, geo, e.bz, torch.from_numpy(off).cuda(), torch.from_numpy(cl).cuda())
 
 
+def test_refit_beyond_the_staged_sector_ids(tracker, geo):
+    """The refit stages the sector ids of the first 1024 slots; an event with
+    more slots reads the others from the event: the single-sector event in
+    slot 1050 of 1100 refits bitwise as in slot 0, in slot 1050's frame."""
+    e = synth.make_preset("c1_sector", 1)
+    nr = synth.N_ROWS
+    S, at = 1100, 1050
+    ro = np.zeros(S * nr + 1, np.int32)
+    ro[at * nr:(at + 1) * nr + 1] = e.row_offsets
+    ro[(at + 1) * nr + 1:] = e.n_clusters
+    sid = (np.arange(S) % 18).astype(np.int32)
+    big = tpc.DeviceEvent.from_host(e.y, e.z, ro, sid)
+    row = e.row_of()
+    lists = []
+    for p in np.unique(e.mc_track[e.mc_track >= 0]):
+        cl = np.nonzero(e.mc_track == p)[0]
+        if cl.shape[0] >= 10:
+            lists.append(cl[np.argsort(row[cl], kind="stable")].astype(np.int32))
+    off = np.zeros(len(lists) + 1, np.int32)
+    np.cumsum([len(l) for l in lists], out=off[1:])
+    cl = torch.from_numpy(np.concatenate(lists)).cuda()
+    off = torch.from_numpy(off).cuda()
+    par0, fr0 = (x.cpu().numpy() for x in tracker.refit(dev_event(e), geo, e.bz, off, cl))
+    par1, fr1 = (x.cpu().numpy() for x in tracker.refit(big, geo, e.bz, off, cl))
+    ok = fr0 >= 0
+    assert ok.sum() > 0.8 * len(lists)
+    assert np.array_equal(par0.view(np.uint32), par1.view(np.uint32))
+    assert np.all(fr0[ok] == e.sector_id[0]) and np.all(fr1[ok] == sid[at]) and np.all(fr1[~ok] == -1)
+
+
 def test_merger_capacity_and_empty_event(tracker, geo):
     e = synth.make_event(synth.EventConfig(n_tracks=1500), 8)
     dev = dev_event(e)
