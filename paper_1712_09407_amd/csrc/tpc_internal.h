@@ -30,6 +30,7 @@ struct KParams {
   int32_t construct_schedule;  // 0 = one lane per tracklet, 1 = row-synchronous
   int32_t nf_dense;            // neighbours finder for dense rows (larger LDS stage)
   int32_t construct_lanes;     // lane schedule: lanes of a wave that take tracklets
+  int32_t own_chunk;           // selection: clusters per LDS chunk of a sector (speed only)
   float rot_c, rot_s;          // cos, sin of one sector width (global tracking)
   float rot_tab[18][2];        // cos, sin of k sector widths, k = -9 .. 8 at [k + 9]
   float merge_chi2;            // track merger: chi^2(5) cut of a join

@@ -1566,9 +1566,9 @@ __device__ __forceinline__ unsigned int order_bits(float w) {
 }
 
 constexpr int kOwnBlock = 512;
-constexpr int kOwnChunk = 4096;   // clusters per chunk (about 18 rows of a central sector)
+constexpr int kOwnChunk = 4096;   // clusters per chunk at most (KParams::own_chunk)
 constexpr int kOwnTable = 1024;   // tracklets per pass over the hit table
-constexpr int kOwnSplit = 16;     // workgroups per sector; chunks are dealt out
+constexpr int kOwnSplit = 32;     // workgroups per sector; chunks are dealt out
 
 // Owner key of tracklet t, 0 if it does not compete: the weight
 // w = n (alpha - (chi^2/ndf)/beta) in order-preserving bits above the
@@ -1598,9 +1598,10 @@ __global__ __launch_bounds__(kOwnBlock) void k_own(DevEvent ev, KParams kp, Scra
   const int n_tl = min(sc.counters[C_SEEDS], sc.cap_tl);
   const int t0 = min(sc.row_cnt[s * nr], n_tl), t1 = min(sc.row_cnt[(s + 1) * nr], n_tl);
   const int c0 = ev.ro[s * nr], c1 = ev.ro[(s + 1) * nr];
-  const int nch = (c1 - c0 + kOwnChunk - 1) / kOwnChunk;
+  const int chunk = min(max(kp.own_chunk, 256), kOwnChunk);
+  const int nch = (c1 - c0 + chunk - 1) / chunk;
   for (int ch = blockIdx.y; ch < nch; ch += gridDim.y) {
-    const int cb = c0 + ch * kOwnChunk, ce = min(cb + kOwnChunk, c1);
+    const int cb = c0 + ch * chunk, ce = min(cb + chunk, c1);
     // rows of the sector with clusters in [cb, ce)
     if (tid == 0) {
       s_rows[0] = nr;
