@@ -1788,22 +1788,34 @@ __global__ __launch_bounds__(kGridBlock) void k_output(DevEvent ev, KParams kp, 
   const int lane = threadIdx.x & 63;
   const int wpb = kGridBlock / 64;
   const unsigned long long lt = (1ull << lane) - 1ull;
+  constexpr int kChunks = (kHitStride + 63) / 64;  // 64-row pieces of a hit row list
   for (int t = blockIdx.x * wpb + (threadIdx.x >> 6); t < n_tl; t += gridDim.x * wpb) {
-    if (!sc.kept[t]) continue;  // wave-uniform
+    // the tracklet's fields are loaded with its flag (they exist for every
+    // tracklet), then every piece's hits at once and their owner keys at
+    // once: three waits per kept tracklet instead of two per piece
+    const bool kept = sc.kept[t] != 0;
     const int i = sc.trk_idx[t];
     int off = sc.trk_off[t];
     const unsigned long long key = sc.key[t];
-    const int32_t* H = sc.hits + (size_t)t * kHitStride;
     const int lo = max(sc.row_lo[t], 0), hi = min(sc.row_hi[t], kHitStride - 1);
-    for (int r0 = lo; r0 <= hi; r0 += 64) {  // wave-uniform trip count
-      const int r = r0 + lane;
-      const int c = r <= hi ? H[r] : -1;
-      const bool mine = c >= 0 && c < n_cl && sc.own[c] == key;
-      const unsigned long long m = __ballot(mine);
-      if (mine) {
+    if (!kept) continue;  // wave-uniform
+    const int32_t* H = sc.hits + (size_t)t * kHitStride;
+    int c[kChunks];
+#pragma unroll
+    for (int u = 0; u < kChunks; ++u) {
+      const int r = lo + u * 64 + lane;
+      c[u] = r <= hi ? H[r] : -1;
+    }
+    bool mine[kChunks];
+#pragma unroll
+    for (int u = 0; u < kChunks; ++u) mine[u] = c[u] >= 0 && c[u] < n_cl && sc.own[c[u]] == key;
+#pragma unroll
+    for (int u = 0; u < kChunks; ++u) {
+      const unsigned long long m = __ballot(mine[u]);
+      if (mine[u]) {
         const int k = __popcll(m & lt);
-        out.track_cluster[off + k] = c;
-        out.cluster_track[c] = i;
+        out.track_cluster[off + k] = c[u];
+        out.cluster_track[c[u]] = i;
       }
       off += __popcll(m);
     }
