@@ -433,7 +433,7 @@ __device__ __forceinline__ unsigned long long nf_wave_pairs(
 // whichever lane evaluated it: one 64-bit minimum per cluster in LDS.  A
 // cluster with more than LIST candidates in a row is searched by the whole
 // wave afterwards (nf_wave_pairs).
-template <int CAP, int LIST, bool BOX>
+template <int CAP, int LIST>
 __device__ __forceinline__ void nf_pairs_staged(
     const DevEvent& ev, const KParams& kp, const Scratch& sc, int b, int e, int bd_, int bu_,
     const RowGrid& gd, const RowGrid& gu, const GridRec& me_first, float t, float inorm,
@@ -442,11 +442,6 @@ __device__ __forceinline__ void nf_pairs_staged(
     NfPairs* s_pw) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, col0 = tid - lane;
   NfPairs& P = s_pw[w];
-  // BOX: |ry| bound of a pair inside the cut (chi^2 >= ry^2 isy2 inorm),
-  // widened by 1% and 1e-3 cm; NaN (no cut) leaves the whole window
-  const float it = 1.f / t;
-  const float box_y = sqrtf(kp.nf_chi2_max / (isy2 * inorm)) * 1.01f + 1e-3f;
-  const float box_z = sqrtf(kp.nf_chi2_max / (isz2 * inorm)) * 1.01f + 1e-3f;
   const RowView D{s_yz[0], s_id[0], s_bins[0], gd}, U{s_yz[1], s_id[1], s_bins[1], gu};
   const bool both = gd.n > 0 && gu.n > 0;
   for (int base = col0; base < e - b; base += kGridBlock) {  // uniform over the wave
@@ -458,11 +453,10 @@ __device__ __forceinline__ void nf_pairs_staged(
     int nd = 0, nu = 0;
     if (have && both) {
       nd = nf_collect<LIST>(D, yc, zc, wy, wz, s_dl, tid);
-      if constexpr (!BOX) nu = nd ? nf_collect<LIST>(U, yc, zc, wy, wz, s_ul, tid) : 0;
+      nu = nd ? nf_collect<LIST>(U, yc, zc, wy, wz, s_ul, tid) : 0;
     }
-    // BOX: one task per lower candidate, which searches the upper row itself
     const bool listed = nd <= LIST && nu <= LIST;
-    const int np = listed ? (BOX ? nd : nd * nu) : 0;
+    const int np = listed ? nd * nu : 0;
     int incl = np;  // inclusive scan over the wave
     for (int d = 1; d < 64; d <<= 1) {
       const int v = __shfl_up(incl, d, 64);
@@ -474,64 +468,11 @@ __device__ __forceinline__ void nf_pairs_staged(
     P.c[lane] = make_float2(yc, zc);
     P.key[lane] = ~0ull;
     wave_lds_sync();
-    // this lane's run [k, kend) of the wave's pairs (BOX: lower candidates)
+    // this lane's run [k, kend) of the wave's pairs
     const int per = (total + 63) >> 6;
     int k = min(lane * per, total);
     const int kend = min(k + per, total);
-    if (BOX && k < kend) {
-      int o = 0;  // owner: the last cluster whose first task is <= k
-      for (int step = 32; step >= 1; step >>= 1)
-        if (o + step < 64 && P.off[o + step] <= k) o += step;
-      int next = o < 63 ? P.off[o + 1] : total;
-      float2 c = P.c[o];
-      int p = k - P.off[o];
-      unsigned long long best = ~0ull;
-      while (true) {
-        const int jd = s_dl[p][col0 + o];
-        const float2 pd = s_yz[0][jd];
-        const float dyd = pd.x - c.x, dzd = pd.y - c.y;
-        const unsigned long long kd = (unsigned long long)(s_id[0][jd] - bd_) << 16;
-        // an upper candidate whose pair can pass the cut has |ry| <= box_y
-        // and |rz| <= box_z: it lies in a box around the straight line
-        // through d and the cluster (ry = dyd + t (dyu - dyd)), taken with
-        // a wide margin and within the window
-        const float ylo = fmaxf(c.x + dyd + (-box_y - dyd) * it, c.x - wy) - 1e-3f;
-        const float yhi = fminf(c.x + dyd + (box_y - dyd) * it, c.x + wy) + 1e-3f;
-        const float zlo = fmaxf(c.y + dzd + (-box_z - dzd) * it, c.y - wz) - 1e-3f;
-        const float zhi = fminf(c.y + dzd + (box_z - dzd) * it, c.y + wz) + 1e-3f;
-        if (ylo <= yhi && zlo <= zhi) {
-          const int y0 = bin_y(U.g, ylo), y1 = bin_y(U.g, yhi);
-          const int z0 = bin_z(U.g, zlo), z1 = bin_z(U.g, zhi);
-          for (int iz = z0; iz <= z1; ++iz) {
-            const int j0 = U.bins[iz * U.g.ny + y0], j1 = U.bins[iz * U.g.ny + y1 + 1];
-            for (int j = j0; j < j1; ++j) {
-              const float2 pu = U.yz[j];
-              if (!in_window(pu, c.x, c.y, wy, wz)) continue;
-              const float ry = dyd + t * ((pu.x - c.x) - dyd);
-              const float rz = dzd + t * ((pu.y - c.y) - dzd);
-              const float chi2 = (ry * ry * isy2 + rz * rz * isz2) * inorm;
-              const unsigned long long hi = (unsigned long long)__float_as_uint(chi2) << 32;
-              if (hi <= best) best = min(best, hi | kd | (unsigned)(s_id[1][j] - bu_));
-            }
-          }
-        }
-        if (++k == kend) break;
-        if (k == next) {  // the next cluster with tasks
-          atomicMin(&P.key[o], best);
-          best = ~0ull;
-          do {
-            ++o;
-          } while (o < 63 && P.off[o + 1] <= k);
-          next = o < 63 ? P.off[o + 1] : total;
-          c = P.c[o];
-          p = 0;
-        } else {
-          ++p;
-        }
-      }
-      atomicMin(&P.key[o], best);
-    }
-    if (!BOX && k < kend) {
+    if (k < kend) {
       int o = 0;  // owner: the last cluster whose first pair is <= k
       for (int step = 32; step >= 1; step >>= 1)
         if (o + step < 64 && P.off[o + step] <= k) o += step;
@@ -628,7 +569,7 @@ __device__ __forceinline__ void nf_pairs_staged(
   }
 }
 
-template <int CAP, int LIST, bool BOX>
+template <int CAP, int LIST>
 __global__ __launch_bounds__(kGridBlock) void k_nf(DevEvent ev, KParams kp, Scratch sc) {
   __shared__ float2 s_yz[2][CAP];
   __shared__ int32_t s_id[2][CAP];
@@ -683,8 +624,8 @@ __global__ __launch_bounds__(kGridBlock) void k_nf(DevEvent ev, KParams kp, Scra
   // lanes take the row's clusters in grid order: neighbouring lanes sit at
   // nearby positions and visit similar bins, so a wave diverges less
   if (stage) {
-    nf_pairs_staged<CAP, LIST, BOX>(ev, kp, sc, b, e, bd_, bu_, gd, gu, me_first, t, inorm, isy2,
-                                    isz2, wy, wz, s_yz, s_id, s_bins, s_dl, s_ul, s_pw);
+    nf_pairs_staged<CAP, LIST>(ev, kp, sc, b, e, bd_, bu_, gd, gu, me_first, t, inorm, isy2, isz2,
+                               wy, wz, s_yz, s_id, s_bins, s_dl, s_ul, s_pw);
     return;
   }
   for (int ii = tid; ii < e - b; ii += kGridBlock) {
@@ -2933,11 +2874,9 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
   if (upto <= STAGE_GRID) return hipGetLastError();
   pre(K_NF);
   if (kp.nf_dense)
-    hipLaunchKernelGGL((k_nf<kNfCapLarge, kNfListLarge, true>), dim3(R), dim3(kGridBlock), 0, st, ev,
-                       kp, sc);
+    hipLaunchKernelGGL((k_nf<kNfCapLarge, kNfListLarge>), dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc);
   else
-    hipLaunchKernelGGL((k_nf<kNfCapSmall, kNfListSmall, false>), dim3(R), dim3(kGridBlock), 0, st, ev,
-                       kp, sc);
+    hipLaunchKernelGGL((k_nf<kNfCapSmall, kNfListSmall>), dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc);
   post(K_NF);
   pre(K_EVO);
   hipLaunchKernelGGL(k_evo, dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc);
