@@ -25,6 +25,17 @@ import numpy as np
 PAR_FLOORS = np.array([1.0, 1.0, 0.1, 0.1, 0.1])   # y, z cm; sinphi; tanl; q/pT 1/GeV
 
 
+def rel_dev(ref, got, with_x=False):
+    """Largest relative deviation of each row of parameters from the
+    reference: |got - ref| / max(|ref|, floor), floors 1 cm for x, y, z,
+    0.1 for sin phi and tan lambda, 0.1 GeV^-1 for q/pT (relative above
+    the floor, absolute below it)."""
+    fl = np.concatenate([[1.0], PAR_FLOORS]) if with_x else PAR_FLOORS
+    ref = np.asarray(ref, np.float64)
+    got = np.asarray(got, np.float64)
+    return (np.abs(got - ref) / np.maximum(np.abs(ref), fl)).max(axis=-1)
+
+
 def _track_of_clusters(res):
     meta = np.asarray(res["track_meta"]).reshape(-1, 4)
     n = meta[:, 1].astype(np.int64)
@@ -101,21 +112,31 @@ def compare(res_a, res_b, n_clusters: int, rel_tol: float = 1e-3) -> dict:
         cluster_concordance_ba=float(agree_sum / max(1, tot_ba)),
         clusters_a=int(n_a.sum()), clusters_b=int(n_b.sum()),
     )
-    # parameters of matched pairs with identical cluster sets and the same reference x
+    # parameters of matched pairs with identical cluster sets, the same
+    # reference x and the same seed: the same fit, so rounding alone may
+    # separate them.  A pair grown from different seeds (two chains of the
+    # same clusters, e.g. after a link near-tie) ran another outward filter,
+    # whose end state is the inward fit's linearisation point: such pairs
+    # are listed in other_seed_pairs, not compared here.
     same = mutual & (agree == n_a) & (n_a == n_b[np.maximum(match_a, 0)] if n_b.size else False)
     pa = np.asarray(res_a["track_par"]).reshape(-1, 8)
     pb = np.asarray(res_b["track_par"]).reshape(-1, 8)
+    ma = np.asarray(res_a["track_meta"]).reshape(-1, 4)
+    mb = np.asarray(res_b["track_meta"]).reshape(-1, 4)
     ia_s = ia[same]
     ib_s = match_a[same]
     if ia_s.size:
         samex = pa[ia_s, 0] == pb[ib_s, 0]
         ia_s, ib_s = ia_s[samex], ib_s[samex]
+    other = np.zeros(0, np.int64)
     if ia_s.size:
-        A = pa[ia_s, 1:6]
-        B = pb[ib_s, 1:6].astype(np.float64)
-        scale = np.maximum(np.abs(A), PAR_FLOORS)
-        rel = np.abs(B - A) / scale
-        worst = rel.max(axis=1)
+        same_seed = ma[ia_s, 3] == mb[ib_s, 3]
+        other = np.stack([ia_s[~same_seed], ib_s[~same_seed]], axis=1)
+        ia_s, ib_s = ia_s[same_seed], ib_s[same_seed]
+    out["other_seed_pairs"] = other.reshape(-1, 2)
+    out["par_other_seed"] = int(other.shape[0])
+    if ia_s.size:
+        worst = rel_dev(pa[ia_s, 1:6], pb[ib_s, 1:6])
         out.update(par_compared=int(ia_s.size), par_max_rel=float(worst.max()),
                    par_fail=int((worst > rel_tol).sum()),
                    par_fail_frac=float((worst > rel_tol).mean()))
@@ -152,7 +173,7 @@ def compare_prolongations(tracks_a, pro_a, tracks_b, pro_b, n_clusters: int,
     B's prolongation of the same (track, end) also holds; _ba the other way.
     For pairs with identical clusters whose tracks grew from the same seed in
     both runs, the parameters x..q/pT must agree within rel_tol relative
-    (absolute below 1), ndf exactly and chi2 within chi2_tol relative
+    (rel_dev's floors), ndf exactly and chi2 within chi2_tol relative
     (absolute below 1).  The chi2 of an update is r^2/S with a residual r of
     about sigma: an FP32 rounding of 1e-5 in sin(phi) of the filtered state,
     over the 10-20 cm lever arm to the next cluster, moves r by ~2e-4 cm, i.e.
@@ -178,7 +199,7 @@ def compare_prolongations(tracks_a, pro_a, tracks_b, pro_b, n_clusters: int,
             continue
         compared += 1
         pa, pb = v[2], b[k][2]
-        ok = np.all(np.abs(pb[:6] - pa[:6]) <= rel_tol * np.maximum(1.0, np.abs(pa[:6])))
+        ok = rel_dev(pa[:6], pb[:6], with_x=True) <= rel_tol
         ok = ok and pb[7] == pa[7] and abs(pb[6] - pa[6]) <= chi2_tol * max(1.0, abs(pa[6]))
         fail += 0 if ok else 1
     return dict(n_a=len(a), n_b=len(b), clusters_a=tot_a, clusters_b=tot_b,
@@ -197,7 +218,7 @@ def compare_merged(tracks_a, merged_a, tracks_b, merged_b, n_clusters: int,
     joined track of B; cluster_concordance_ab / _ba: the fraction of A's (B's)
     list clusters that the corresponding list of the other run holds; for
     identical lists, the refit parameters must agree within rel_tol relative
-    (absolute below 1), ndf exactly and chi2 within chi2_tol (the refit is a
+    (rel_dev's floors), ndf exactly and chi2 within chi2_tol (the refit is a
     function of the list alone, so only FP32/FP64 rounding separates them),
     for refits that fitted at least min_fit clusters on both sides (ndf >=
     2 min_fit - 5).  Shorter fits are counted, not compared: they are lists
@@ -240,9 +261,9 @@ def compare_merged(tracks_a, merged_a, tracks_b, merged_b, n_clusters: int,
             short += 1
             continue
         compared += 1
-        rel = np.abs(pb[:6] - pa[:6]) / np.maximum(1.0, np.abs(pa[:6]))
-        max_rel = max(max_rel, float(rel.max()))
-        ok = np.all(rel <= rel_tol)
+        rel = rel_dev(pa[:6], pb[:6], with_x=True)
+        max_rel = max(max_rel, float(rel))
+        ok = rel <= rel_tol
         ok = ok and pb[7] == pa[7] and abs(pb[6] - pa[6]) <= chi2_tol * max(1.0, abs(pa[6]))
         fail += 0 if ok else 1
     return dict(n_a=len(la), n_b=len(lb), joins_same=same_join,

@@ -73,7 +73,7 @@ enum Counter {
 enum ErrBits { E_OFFSETS = 1, E_NONFINITE = 2, E_TL_OVERFLOW = 4, E_CAPACITY = 8 };
 
 constexpr int kHitStride = 160;  // per-tracklet row slots (>= n_rows, padded)
-constexpr int kEndStride = 24;   // floats per tracklet end state (x, 5 state, 15 cov, pad)
+constexpr int kEndStride = 40;   // floats per tracklet end state (x, 5 state, flag, pad, 15 FP64 cov, pad)
 constexpr int kLayoutSectors = 36;  // 2 x 18 sectors: ids 0-17 and 18-35
 
 // Device scratch of one event.

@@ -38,6 +38,7 @@
 #include <algorithm>
 
 #include "tpc_internal.h"
+#include "tpc_model.h"
 
 namespace tpc {
 
@@ -723,177 +724,8 @@ __global__ __launch_bounds__(kGridBlock) void k_seed_write(DevEvent ev, Scratch 
 }
 
 // ------------------------------------------------------------------ track model
-
-// Hardware reciprocal / square root (about 1 ulp): the FP32 path is compared
-// with the FP64 oracle at 1e-3, far above these rounding differences.
-__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
-
-// Lower-triangular packed symmetric 5x5 covariance.
-struct Cov {
-  float c00, c10, c11, c20, c21, c22, c30, c31, c32, c33, c40, c41, c42, c43, c44;
-};
-
-struct KState {
-  float x, y, z, sp, tl, qpt;
-  Cov C;
-};
-
-__device__ __forceinline__ void reset_cov(Cov& C, const KParams& kp) {
-  C.c00 = kp.sy2;
-  C.c11 = kp.sz2;
-  C.c22 = kp.prior_sinphi;
-  C.c33 = kp.prior_tanl;
-  C.c44 = kp.prior_qpt;
-  C.c10 = C.c20 = C.c21 = C.c30 = C.c31 = C.c32 = C.c40 = C.c41 = C.c42 = C.c43 = 0.f;
-}
-
-// asin(u)/u and its derivative; series below |u| = 0.1 (next term < 1e-9).
-__device__ __forceinline__ float asinc(float u) {
-  const float u2 = u * u;
-  if (u2 < 0.01f) return 1.f + u2 * (1.f / 6.f + u2 * (3.f / 40.f + u2 * (5.f / 112.f)));
-  return asinf(u) * frcp(u);
-}
-__device__ __forceinline__ float asinc_d(float u, float isq) {
-  const float u2 = u * u;
-  if (u2 < 0.01f) return u * (1.f / 3.f + u2 * (3.f / 10.f + u2 * (15.f / 56.f)));
-  return (u * isq - asinf(u)) * frcp(u2);
-}
-
-// Exact helix step to x2 with the analytic Jacobian (section 1's Kalman fit
-// needs the extrapolation to adjacent rows).  Returns false, leaving the
-// state unchanged, if |sin phi| would pass max_sinphi.
-__device__ __forceinline__ bool propagate(KState& s, float x2, const KParams& kp) {
-  const float k = kp.k_curv;
-  const float dx = x2 - s.x;
-  const float kap = k * s.qpt;
-  const float s1 = s.sp, s2 = s1 - kap * dx;
-  if (fabsf(s1) > kp.max_sinphi || fabsf(s2) > kp.max_sinphi) return false;
-  const float ic1 = frsq((1.f - s1) * (1.f + s1)), ic2 = frsq((1.f - s2) * (1.f + s2));
-  const float c1 = (1.f - s1) * (1.f + s1) * ic1, c2 = (1.f - s2) * (1.f + s2) * ic2;
-  const float T = (s1 + s2) * frcp(c1 + c2);
-  const float Q2 = 1.f + T * T;
-  const float iQ = frsq(Q2);
-  const float Q = Q2 * iQ;
-  const float u = 0.5f * kap * dx * Q;
-  const float isq = frsq(1.f - u * u);
-  const float h = asinc(u);
-  const float ds = dx * Q * h;
-  const float dT_ds1 = 0.5f * Q2 * (ic1 + ic2);
-  const float dT_dk = -0.5f * Q2 * dx * ic2;
-  const float TQ = T * iQ;
-  const float dds_ds1 = dx * TQ * dT_ds1 * isq;
-  const float dds_dk = dx * (TQ * dT_dk * isq + 0.5f * Q2 * dx * asinc_d(u, isq));
-  const float a = dx * dT_ds1;        // dy/dsinphi
-  const float bq = dx * dT_dk * k;    // dy/dqpt
-  const float c = s.tl * dds_ds1;     // dz/dsinphi
-  const float d = ds;                 // dz/dtanl
-  const float ee = s.tl * dds_dk * k; // dz/dqpt
-  const float f = -dx * k;            // dsinphi/dqpt
-  Cov& C = s.C;
-  // T = J C (rows 0..2 differ from C)
-  const float t00 = C.c00 + a * C.c20 + bq * C.c40;
-  const float t02 = C.c20 + a * C.c22 + bq * C.c42;
-  const float t04 = C.c40 + a * C.c42 + bq * C.c44;
-  const float t10 = C.c10 + c * C.c20 + d * C.c30 + ee * C.c40;
-  const float t11 = C.c11 + c * C.c21 + d * C.c31 + ee * C.c41;
-  const float t12 = C.c21 + c * C.c22 + d * C.c32 + ee * C.c42;
-  const float t13 = C.c31 + c * C.c32 + d * C.c33 + ee * C.c43;
-  const float t14 = C.c41 + c * C.c42 + d * C.c43 + ee * C.c44;
-  const float t20 = C.c20 + f * C.c40;
-  const float t21 = C.c21 + f * C.c41;
-  const float t22 = C.c22 + f * C.c42;
-  const float t23 = C.c32 + f * C.c43;
-  const float t24 = C.c42 + f * C.c44;
-  Cov N;
-  N.c00 = t00 + a * t02 + bq * t04;
-  N.c10 = t10 + a * t12 + bq * t14;
-  N.c11 = t11 + c * t12 + d * t13 + ee * t14;
-  N.c20 = t20 + a * t22 + bq * t24;
-  N.c21 = t21 + c * t22 + d * t23 + ee * t24;
-  N.c22 = t22 + f * t24;
-  N.c30 = C.c30 + a * C.c32 + bq * C.c43;
-  N.c31 = C.c31 + c * C.c32 + d * C.c33 + ee * C.c43;
-  N.c32 = C.c32 + f * C.c43;
-  N.c33 = C.c33;
-  N.c40 = C.c40 + a * C.c42 + bq * C.c44;
-  N.c41 = C.c41 + c * C.c42 + d * C.c43 + ee * C.c44;
-  N.c42 = C.c42 + f * C.c44;
-  N.c43 = C.c43;
-  N.c44 = C.c44;
-  C = N;
-  s.y += dx * T;
-  s.z += s.tl * ds;
-  s.sp = s2;
-  s.x = x2;
-  return true;
-}
-
-// Kalman update with the measurement (my, mz); returns its chi^2.
-__device__ __forceinline__ float kf_update(KState& s, float my, float mz, const KParams& kp) {
-  Cov& C = s.C;
-  const float S00 = C.c00 + kp.sy2, S01 = C.c10, S11 = C.c11 + kp.sz2;
-  const float idet = frcp(S00 * S11 - S01 * S01);
-  const float i00 = S11 * idet, i01 = -S01 * idet, i11 = S00 * idet;
-  const float ry = my - s.y, rz = mz - s.z;
-  const float chi2 = ry * ry * i00 + 2.f * ry * rz * i01 + rz * rz * i11;
-  // K = C H^T S^-1 (columns 0 and 1 of C)
-  const float k00 = C.c00 * i00 + C.c10 * i01, k01 = C.c00 * i01 + C.c10 * i11;
-  const float k10 = C.c10 * i00 + C.c11 * i01, k11 = C.c10 * i01 + C.c11 * i11;
-  const float k20 = C.c20 * i00 + C.c21 * i01, k21 = C.c20 * i01 + C.c21 * i11;
-  const float k30 = C.c30 * i00 + C.c31 * i01, k31 = C.c30 * i01 + C.c31 * i11;
-  const float k40 = C.c40 * i00 + C.c41 * i01, k41 = C.c40 * i01 + C.c41 * i11;
-  s.y += k00 * ry + k01 * rz;
-  s.z += k10 * ry + k11 * rz;
-  s.sp += k20 * ry + k21 * rz;
-  s.tl += k30 * ry + k31 * rz;
-  s.qpt += k40 * ry + k41 * rz;
-  // C -= K (H C): rows 0 and 1 of the old C
-  const float h00 = C.c00, h01 = C.c10, h02 = C.c20, h03 = C.c30, h04 = C.c40;
-  const float h10 = C.c10, h11 = C.c11, h12 = C.c21, h13 = C.c31, h14 = C.c41;
-  C.c00 -= k00 * h00 + k01 * h10;
-  C.c10 -= k10 * h00 + k11 * h10;
-  C.c11 -= k10 * h01 + k11 * h11;
-  C.c20 -= k20 * h00 + k21 * h10;
-  C.c21 -= k20 * h01 + k21 * h11;
-  C.c22 -= k20 * h02 + k21 * h12;
-  C.c30 -= k30 * h00 + k31 * h10;
-  C.c31 -= k30 * h01 + k31 * h11;
-  C.c32 -= k30 * h02 + k31 * h12;
-  C.c33 -= k30 * h03 + k31 * h13;
-  C.c40 -= k40 * h00 + k41 * h10;
-  C.c41 -= k40 * h01 + k41 * h11;
-  C.c42 -= k40 * h02 + k41 * h12;
-  C.c43 -= k40 * h03 + k41 * h13;
-  C.c44 -= k40 * h04 + k41 * h14;
-  return chi2;
-}
-
-// Seed from chain clusters a (first), b (middle) and e (last of the seed
-// window): the circle through them in (x, y) gives curvature and direction at
-// a; tan lambda is the z rise over the arc a -> e.
-__device__ __forceinline__ void seed3(KState& s, float xa, float ya, float za, float xb, float yb,
-                                      float xe, float ye, float ze, const KParams& kp) {
-  const float d1x = xb - xa, d1y = yb - ya, d2x = xe - xa, d2y = ye - ya;
-  float kappa = 0.f;
-  if (kp.bz != 0.f) {
-    const float cross = d1x * d2y - d1y * d2x;
-    const float den = sqrtf(d1x * d1x + d1y * d1y) * sqrtf(d2x * d2x + d2y * d2y) *
-                      sqrtf((d2x - d1x) * (d2x - d1x) + (d2y - d1y) * (d2y - d1y));
-    kappa = den > 0.f ? -2.f * cross / den : 0.f;
-  }
-  const float L = sqrtf(d2x * d2x + d2y * d2y);
-  float u = 0.5f * kappa * L;
-  u = fminf(fmaxf(u, -1.f), 1.f);
-  s.x = xa;
-  s.y = ya;
-  s.z = za;
-  s.sp = (d2y / L) * sqrtf(1.f - u * u) + (d2x / L) * u;
-  s.tl = (ze - za) / (L * asinc(u));
-  s.qpt = kp.bz != 0.f ? kappa / kp.k_curv : 0.f;
-  reset_cov(s.C, kp);
-}
+//
+// propagate, kf_update, seed3, rotate and step_par are in tpc_model.h.
 
 // Work done by one lane of the constructor (for the algorithmic FLOP count).
 struct Work {
@@ -912,7 +744,8 @@ __device__ __forceinline__ int search_row(const Scratch& sc, const RowGrid& g, i
                                           const KState& s, const KParams& kp, float& by,
                                           float& bz_, Work& wk, Accept accept = Accept()) {
   if (g.n == 0) return -1;
-  const float S00 = s.C.c00 + kp.sy2, S01 = s.C.c10, S11 = s.C.c11 + kp.sz2;
+  const float S00 = (float)(s.C.c00 + kp.sy2), S01 = (float)s.C.c10,
+              S11 = (float)(s.C.c11 + kp.sz2);
   const float idet = frcp(S00 * S11 - S01 * S01);
   const float wy = fsqrt(kp.chi2_gate * S00) * 1.001f + 1e-4f;
   const float wz = fsqrt(kp.chi2_gate * S11) * 1.001f + 1e-4f;
@@ -970,31 +803,42 @@ __device__ __forceinline__ int search_row(const Scratch& sc, const RowGrid& g, i
 
 enum Phase { P_CHAIN = 0, P_UP = 1, P_REFIT = 2, P_DOWN = 3, P_DONE = 4 };
 
-// End state of a tracklet (global tracking): x, state, packed covariance,
-// kEndStride floats, six 16-byte stores.
+// End state of a tracklet (global tracking), kEndStride floats: x and the
+// state (floats 0-5), the validity flag (float 6), then the packed FP64
+// covariance from float 8 on; ten 16-byte stores.
+constexpr int kEndValid = 6;
+constexpr int kEndCov = 8;
+__device__ __forceinline__ const double* end_cov(const float* E) {
+  return reinterpret_cast<const double*>(E + kEndCov);
+}
 __device__ __forceinline__ void store_end(float* E, const KState& s) {
   float4* q = reinterpret_cast<float4*>(E);
+  double2* w = reinterpret_cast<double2*>(E + kEndCov);
   const Cov& C = s.C;
   q[0] = make_float4(s.x, s.y, s.z, s.sp);
-  q[1] = make_float4(s.tl, s.qpt, C.c00, C.c10);
-  q[2] = make_float4(C.c11, C.c20, C.c21, C.c22);
-  q[3] = make_float4(C.c30, C.c31, C.c32, C.c33);
-  q[4] = make_float4(C.c40, C.c41, C.c42, C.c43);
-  q[5] = make_float4(C.c44, 0.f, 0.f, 0.f);
+  q[1] = make_float4(s.tl, s.qpt, 0.f, 0.f);
+  w[0] = make_double2(C.c00, C.c10);
+  w[1] = make_double2(C.c11, C.c20);
+  w[2] = make_double2(C.c21, C.c22);
+  w[3] = make_double2(C.c30, C.c31);
+  w[4] = make_double2(C.c32, C.c33);
+  w[5] = make_double2(C.c40, C.c41);
+  w[6] = make_double2(C.c42, C.c43);
+  w[7] = make_double2(C.c44, 0.0);
 }
-// k_ends marks an end state valid (element 21) once it sits at its cluster's row.
-constexpr int kEndValid = 21;
 __device__ __forceinline__ void load_end(const float* E, KState& s) {
   const float4* q = reinterpret_cast<const float4*>(E);
-  const float4 a = q[0], b = q[1], c = q[2], d = q[3], e = q[4], f = q[5];
+  const double2* w = reinterpret_cast<const double2*>(E + kEndCov);
+  const float4 a = q[0], b = q[1];
+  const double2 w0 = w[0], w1 = w[1], w2 = w[2], w3 = w[3], w4 = w[4], w5 = w[5], w6 = w[6],
+                w7 = w[7];
   s.x = a.x; s.y = a.y; s.z = a.z; s.sp = a.w;
   s.tl = b.x; s.qpt = b.y;
   Cov& C = s.C;
-  C.c00 = b.z; C.c10 = b.w;
-  C.c11 = c.x; C.c20 = c.y; C.c21 = c.z; C.c22 = c.w;
-  C.c30 = d.x; C.c31 = d.y; C.c32 = d.z; C.c33 = d.w;
-  C.c40 = e.x; C.c41 = e.y; C.c42 = e.z; C.c43 = e.w;
-  C.c44 = f.x;
+  C.c00 = w0.x; C.c10 = w0.y; C.c11 = w1.x; C.c20 = w1.y; C.c21 = w2.x; C.c22 = w2.y;
+  C.c30 = w3.x; C.c31 = w3.y; C.c32 = w4.x; C.c33 = w4.y;
+  C.c40 = w5.x; C.c41 = w5.y; C.c42 = w6.x; C.c43 = w6.y;
+  C.c44 = w7.x;
 }
 
 // ENDS: also record what global tracking starts from: the outward filter at
@@ -1329,7 +1173,8 @@ __device__ __forceinline__ void stage_store(const RowGrid& g, const StageRegs& R
 __device__ __forceinline__ int search_row_lds(const RowStage& L, const RowGrid& g, const KState& s,
                                               const KParams& kp, float& by, float& bz_, Work& wk) {
   if (g.n == 0) return -1;
-  const float S00 = s.C.c00 + kp.sy2, S01 = s.C.c10, S11 = s.C.c11 + kp.sz2;
+  const float S00 = (float)(s.C.c00 + kp.sy2), S01 = (float)s.C.c10,
+              S11 = (float)(s.C.c11 + kp.sz2);
   const float idet = frcp(S00 * S11 - S01 * S01);
   const float wy = fsqrt(kp.chi2_gate * S00) * 1.001f + 1e-4f;
   const float wz = fsqrt(kp.chi2_gate * S11) * 1.001f + 1e-4f;
@@ -1929,73 +1774,6 @@ __global__ __launch_bounds__(kGridBlock) void k_ends(KParams kp, Scratch sc, Glo
   }
 }
 
-// Rotation of the local frame by the angle whose cosine and sine are (ca, sa):
-// the point and the direction stay, x becomes the rotated x.  A change of y
-// at fixed x is carried along the track onto the new reference plane:
-// dy'/dy = cos(phi)/cos(phi'), dz'/dy = -sin(d) tan(lambda)/cos(phi'),
-// dsin(phi')/dy = kappa sin(d), dsin(phi')/dsin(phi) = cos(phi')/cos(phi).
-// False (state unchanged) if the direction would not point along +x'.
-__device__ __forceinline__ bool rotate(KState& s, float ca, float sa, const KParams& kp) {
-  const float sp = s.sp, cp = fsqrt((1.f - sp) * (1.f + sp));
-  const float sp2 = sp * ca - cp * sa, cp2 = cp * ca + sp * sa;
-  if (!(cp2 > 0.f)) return false;
-  const float j00 = cp / cp2, j10 = -sa * s.tl / cp2, j20 = kp.k_curv * s.qpt * sa;
-  const float j22 = cp2 / cp;
-  Cov& C = s.C;
-  // rows of J C: row 1 = j10 (C row 0) + (C row 1), row 2 = j20 (C row 0) + j22 (C row 2)
-  const float b0 = j10 * C.c00 + C.c10, b1 = j10 * C.c10 + C.c11;
-  const float b3 = j10 * C.c30 + C.c31, b4 = j10 * C.c40 + C.c41;
-  const float a0 = j20 * C.c00 + j22 * C.c20, a1 = j20 * C.c10 + j22 * C.c21;
-  const float a2 = j20 * C.c20 + j22 * C.c22, a3 = j20 * C.c30 + j22 * C.c32;
-  const float a4 = j20 * C.c40 + j22 * C.c42;
-  Cov N;
-  N.c00 = j00 * j00 * C.c00;
-  N.c10 = j00 * b0;
-  N.c11 = b0 * j10 + b1;
-  N.c20 = j00 * a0;
-  N.c21 = a0 * j10 + a1;
-  N.c22 = a0 * j20 + a2 * j22;
-  N.c30 = j00 * C.c30;
-  N.c31 = b3;
-  N.c32 = a3;
-  N.c33 = C.c33;
-  N.c40 = j00 * C.c40;
-  N.c41 = b4;
-  N.c42 = a4;
-  N.c43 = C.c43;
-  N.c44 = C.c44;
-  C = N;
-  const float x2 = s.x * ca + s.y * sa, y2 = -s.x * sa + s.y * ca;
-  s.x = x2;
-  s.y = y2;
-  s.sp = sp2;
-  return true;
-}
-
-// The helix parameters alone, stepped to x2 with the same formulas as
-// propagate (no Jacobian): for checks along a path whose covariance is
-// needed only at its end.
-struct HelixPar {
-  float x, y, z, sp, tl, qpt;
-};
-__device__ __forceinline__ bool step_par(HelixPar& h, float x2, const KParams& kp) {
-  const float dx = x2 - h.x;
-  const float kap = kp.k_curv * h.qpt;
-  const float s1 = h.sp, s2 = s1 - kap * dx;
-  if (fabsf(s1) > kp.max_sinphi || fabsf(s2) > kp.max_sinphi) return false;
-  const float c1 = (1.f - s1) * (1.f + s1) * frsq((1.f - s1) * (1.f + s1));
-  const float c2 = (1.f - s2) * (1.f + s2) * frsq((1.f - s2) * (1.f + s2));
-  const float T = (s1 + s2) * frcp(c1 + c2);
-  const float Q2 = 1.f + T * T;
-  const float Q = Q2 * frsq(Q2);
-  const float u = 0.5f * kap * dx * Q;
-  h.y += dx * T;
-  h.z += h.tl * dx * Q * asinc(u);
-  h.sp = s2;
-  h.x = x2;
-  return true;
-}
-
 // A cluster no sector track owns: k_pro_init copies the sector tracker's
 // cluster_track into the grid records' spare word (1 = owned), so the test
 // reads the record the search already holds.
@@ -2204,8 +1982,10 @@ __global__ __launch_bounds__(kGridBlock) void k_mrg_init(DevEvent ev, KParams kp
     const float4 a = reinterpret_cast<const float4*>(E)[0];
     const float4 b = reinterpret_cast<const float4*>(E)[1];
     ms.sum[2 * i] = make_float4(a.x, a.y, b.x, b.y);
-    // var tan(lambda) = C33 (element 15), var q/pT = C44 (element 20)
-    ms.sum[2 * i + 1] = make_float4(E[15], E[20], sqrtf(a.x * a.x + a.y * a.y), E[kEndValid]);
+    // var tan(lambda) = C33, var q/pT = C44 (packed elements 9 and 14)
+    const double* EC = end_cov(E);
+    ms.sum[2 * i + 1] = make_float4((float)EC[9], (float)EC[14], sqrtf(a.x * a.x + a.y * a.y),
+                                    E[kEndValid]);
     ms.prev_key[i] = ~0ull;
     ms.prev[i] = -1;
   }
@@ -2241,6 +2021,7 @@ __device__ __forceinline__ float chi2_5(const float d[5], float S[5][5]) {
 }
 
 __device__ __forceinline__ void cov_full(const Cov& C, float M[5][5]) {
+  // the join test is a decision: FP32 is enough
   M[0][0] = C.c00; M[1][0] = C.c10; M[1][1] = C.c11; M[2][0] = C.c20; M[2][1] = C.c21;
   M[2][2] = C.c22; M[3][0] = C.c30; M[3][1] = C.c31; M[3][2] = C.c32; M[3][3] = C.c33;
   M[4][0] = C.c40; M[4][1] = C.c41; M[4][2] = C.c42; M[4][3] = C.c43; M[4][4] = C.c44;
@@ -2283,7 +2064,8 @@ __global__ __launch_bounds__(kGridBlock) void k_mrg_match(DevEvent ev, KParams k
           // tan(lambda), q/pT and their variances do not change under rotation
           // and propagation, and d_i^2 / S_ii <= chi^2: exact rejections
           const float dt = u.z - A.tl, dq = u.w - A.qpt;
-          if (dt * dt > cut * (A.C.c33 + v.x) || dq * dq > cut * (A.C.c44 + v.y)) continue;
+          if (dt * dt > cut * ((float)A.C.c33 + v.x) || dq * dq > cut * ((float)A.C.c44 + v.y))
+            continue;
           if (!(v.z > ra) || v.w == 0.f) continue;  // outward only; valid end
           KState B;
           load_end(sc.ends + (size_t)(2 * tl_of_track(gs, b)) * kEndStride, B);

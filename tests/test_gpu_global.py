@@ -4,11 +4,11 @@ The sector tracks of tpc_track_event_global are bitwise those of
 tpc_track_event.  Prolongations are compared per (seed id of the track, end):
 on noiseless tracks that cross a sector edge the two sides must give the
 same prolongations with the same clusters; on central events the clusters of
-the prolongations must agree to >= 99.9% both ways (a decision on an FP32
+the prolongations must agree to >= 99.95% both ways (a decision on an FP32
 chi^2 near the gate, or a near-tie of two candidates, may differ from the
 FP64 oracle, and a changed pick changes the rest of that prolongation), and
-the parameters of prolongations with identical clusters within 1e-3
-relative (absolute for |value| < 1), chi2 within 1e-2, when both sides built
+the parameters of every prolongation with identical clusters within 1e-3
+relative (floors 1 cm for x, y, z, 0.1 for the rest), chi2 within 1e-2, when both sides built
 the track from the same seed (FP32 and FP64 may keep different seeds among tracklets with the
 same clusters; the outer end state then comes from another outward filter).
 """
@@ -72,10 +72,6 @@ def run_both(orc, tracker, geo, e, sector_id=None):
     return (tr, pr), (tro, pro)
 
 
-def par_close(a, b, tol=1e-3):
-    return np.all(np.abs(a - b) <= tol * np.maximum(1.0, np.abs(b)))
-
-
 def crossing_event(seed, phi_range):
     cfg = synth.EventConfig(n_tracks=8, sectors=tuple(range(18)), phi_range_deg=phi_range,
                             sigma=0.0, noise_frac=0.0, pt_min=1.9, pt_mean=1e-9, eta_max=0.5)
@@ -106,9 +102,9 @@ def test_central_event_prolongations(orc, tracker, geo, seed):
     rep = concordance.compare_prolongations(*ref, *gpu, e.n_clusters)
     say(rep)
     assert rep["n_a"] > 100
-    assert rep["cluster_concordance_ab"] >= 0.999 and rep["cluster_concordance_ba"] >= 0.999
+    assert rep["cluster_concordance_ab"] >= 0.9995 and rep["cluster_concordance_ba"] >= 0.9995
     assert rep["par_compared"] >= 0.7 * rep["n_a"]
-    assert rep["par_fail"] <= max(2, 2e-3 * rep["par_compared"])
+    assert rep["par_fail"] == 0
     # output invariants of the GPU side
     tr, pr = gpu
     cl = pr["cluster"]

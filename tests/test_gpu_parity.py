@@ -100,7 +100,7 @@ def test_links_match_oracle(orc, tracker, geo, name, seed):
 
 
 # ------------------------------------------------------------- tracklets
-@pytest.mark.parametrize("name,seed", [("c1_sector", 1), ("c2_central", 2)])
+@pytest.mark.parametrize("name,seed", [("c1_sector", 1), ("c2_central", 2), ("c5_stress", 5000)])
 def test_seeds_and_tracklets_match_oracle(orc, tracker, geo, name, seed):
     e = get_event(name, seed)
     say("tracklets", name, seed)
@@ -125,8 +125,8 @@ def test_seeds_and_tracklets_match_oracle(orc, tracker, geo, name, seed):
         same[t] = (lo == ref["row_lo"][t] and hi == ref["row_hi"][t] and
                    np.array_equal(tl["hits"][t, lo:hi + 1], ref["hits"][t, lo:hi + 1]))
     frac = same.mean()
-    say("identical tracklets", frac, n_tl)
-    assert frac >= 0.999
+    say("identical tracklets", frac, n_tl, "differing", int((~same).sum()))
+    assert frac >= 0.9999
     ok = same & (ref["n"] > 0)
     assert np.array_equal(tl["par"][ok, 0].astype(np.float64), ref["par"][ok, 0])
     # parameters: the 1e-3 relative tolerance is for tracklets long enough to
@@ -139,9 +139,11 @@ def test_seeds_and_tracklets_match_oracle(orc, tracker, geo, name, seed):
     worst = int(np.argmax(rel.max(axis=1)))
     say("worst parameter difference", rel.max(axis=1)[worst], "n", ref["n"][ok][worst],
         "gpu", P[worst], "oracle", R[worst])
-    assert np.mean(rel.max(axis=1) > 1e-3) <= 1e-3, rel.max(axis=0)
+    assert rel.max() <= 1e-3, rel.max(axis=0)
     c = tl["chi2"][ok].astype(np.float64)
-    assert np.mean(np.abs(c - ref["chi2"][ok]) > 1e-3 * np.maximum(ref["chi2"][ok], 1.0)) <= 1e-3
+    cdev = np.abs(c - ref["chi2"][ok]) / np.maximum(ref["chi2"][ok], 1.0)
+    say("chi2 deviation: max", cdev.max(), "above 1e-3", np.mean(cdev > 1e-3))
+    assert np.mean(cdev > 1e-3) <= 1e-3
     assert np.array_equal(tl["ndf"][ok], ref["ndf"][ok])
 
 
@@ -178,6 +180,30 @@ def test_selection_matches_oracle_on_gpu_tracklets(orc, tracker, geo):
 
 
 # ------------------------------------------------------------- end to end
+def check_other_seed_fits(orc, tracker, e, pg, po, res, pairs):
+    """Matched tracks with identical clusters whose seeds differ (the chains
+    of the two runs start at different clusters, e.g. after a neighbour-pair
+    near-tie) are not the same fit: each ran its own outward filter, and the
+    inward fit starts from that filter's state.  The oracle's construction
+    from the GPU's seed, along the GPU's links, must reproduce the GPU's
+    parameters: then the difference is the seed, not the arithmetic."""
+    say("identical clusters from another seed", len(pairs))
+    if not len(pairs):
+        return
+    _, _, up2, _ = (x.cpu().numpy() for x in tracker.links(dev_event(e), geo_of(), pg))
+    ib = pairs[:, 1]
+    seeds = res["track_meta"][ib, 3].astype(np.int32)
+    tlo = orc.construct(event_dict(e), GEO_T, e.bz, up2, seeds, po)
+    assert np.array_equal(tlo["ndf"], res["track_par"][ib, 7].astype(np.int32))
+    dev = concordance.rel_dev(tlo["par"][:, 1:6], res["track_par"][ib, 1:6])
+    say("  oracle from the GPU's seeds: max deviation", dev.max())
+    assert dev.max() <= 1e-3
+
+
+def geo_of():
+    return tpc.make_geometry(*GEO_T)
+
+
 @pytest.mark.parametrize("name,seed", [("c1_sector", 1), ("c2_central", 2), ("c2_central", 3),
                                        ("c5_stress", 5000)])
 def test_end_to_end_concordance(orc, tracker, geo, name, seed):
@@ -192,18 +218,36 @@ def test_end_to_end_concordance(orc, tracker, geo, name, seed):
                                          "par_fail")})
     assert rep["cluster_concordance"] >= 0.9999
     assert rep["track_concordance"] >= 0.9999
-    if name == "c5_stress":
-        # low-pT loopers on short arcs are ill-conditioned fits: FP32 rounding
-        # moves their q/pT by ~1e-3 relative (1-2% of its statistical error);
-        # the stress case reports the parameter error rather than meeting 1e-3
-        assert rep["par_fail_frac"] <= 5e-3 and rep["par_max_rel"] <= 2e-2
-    else:
-        assert rep["par_fail_frac"] <= 1e-3
+    # identical clusters grown from the same seed: the same fit (section 3.3)
+    assert rep["par_fail"] == 0, rep["par_max_rel"]
+    check_other_seed_fits(orc, tracker, e, pg, po, res, rep["other_seed_pairs"])
     # output invariants
     m = res["track_meta"]
     assert np.all(m[:, 1] >= 30)
     assert np.all(np.diff(m[:, 3]) > 0)                           # sorted by seed id
     assert np.sum(res["cluster_track"] >= 0) == res["n_track_clusters"]
+
+
+@pytest.mark.parametrize("alpha_gpu,alpha_orc", [(1.0, 1.0), (1e9, 1e30)])
+def test_other_alphas_match_the_oracle(orc, tracker, geo, alpha_gpu, alpha_orc):
+    """Section 3.1's weight w = n (alpha - chi^2/beta) at a small alpha and at
+    alpha = infinity, the longest-track rule: on the GPU alpha = 1e9, where
+    FP32 rounds alpha - chi^2/ndf to alpha, so w orders by length alone, as
+    the oracle's 1e30 does in FP64.  The same concordance bar as at alpha = 6."""
+    e = get_event("c2_central", 2)
+    say("alpha", alpha_gpu, alpha_orc)
+    pg, po = params_pair(orc, e.config.sigma, alpha=alpha_gpu)
+    po.alpha = alpha_orc
+    res = tpc.to_numpy(tracker.track_event(dev_event(e), geo, e.bz, pg))
+    ref = orc.track_event(event_dict(e), GEO_T, e.bz, po, n_threads=THREADS)
+    rep = concordance.compare(ref, res, e.n_clusters)
+    say({k: rep[k] for k in ("n_tracks_a", "n_tracks_b", "cluster_concordance_ab",
+                             "cluster_concordance_ba", "track_concordance", "par_compared",
+                             "par_max_rel", "par_fail")})
+    assert rep["cluster_concordance"] >= 0.9999
+    assert rep["track_concordance"] >= 0.9999
+    assert rep["par_fail"] == 0, rep["par_max_rel"]
+    check_other_seed_fits(orc, tracker, e, pg, po, res, rep["other_seed_pairs"])
 
 
 def test_deterministic(orc, tracker, geo):
@@ -275,7 +319,10 @@ def test_dense_rows_use_the_global_memory_path(orc, tracker, geo):
     assert check_links(orc, e, po, up, dn, uo, do_) <= max(2, 1e-5 * e.n_clusters)
     res = tpc.to_numpy(tracker.track_event(dev_event(e), geo, e.bz, pg))
     ref = orc.track_event(event_dict(e), GEO_T, e.bz, po)
-    assert concordance.compare(ref, res, e.n_clusters)["cluster_concordance"] >= 0.999
+    rep = concordance.compare(ref, res, e.n_clusters)
+    say("noise flood", {k: rep[k] for k in ("cluster_concordance", "track_concordance",
+                                            "par_fail")})
+    assert rep["cluster_concordance"] >= 0.9999 and rep["track_concordance"] >= 0.9999
 
 
 def crowded_event(seed, noise_frac, n_hot):
