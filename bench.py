@@ -57,6 +57,61 @@ def path_bytes(N, tracklets, steps, cands, n_tracks, n_track_clusters):
     return b
 
 
+# The method's algorithmic HBM bytes per cluster, staged (every stage reads
+# its inputs and writes its outputs once): grid build 28, neighbours finder
+# with evolution 16, seeds 8, tracklet construction 50-60, weights and
+# assignment 16-32, selection and output 24.
+STAGED_BYTES_PER_CLUSTER = (160, 190)
+
+
+def staged_hbm(clusters_per_s):
+    """The whole path against HBM under the staged algorithmic model."""
+    lo, hi = STAGED_BYTES_PER_CLUSTER
+    return dict(model="staged algorithmic bytes, 160-190 B per cluster (grid 28, links 16, "
+                      "seeds 8, construction 50-60, assignment 16-32, selection and output 24)",
+                bytes_per_cluster=[lo, hi], unit="GB/s", peak=PEAK_HBM_GBS,
+                achieved=round(lo * clusters_per_s / 1e9, 2),
+                achieved_high=round(hi * clusters_per_s / 1e9, 2),
+                frac=round(lo * clusters_per_s / 1e9 / PEAK_HBM_GBS, 6),
+                frac_high=round(hi * clusters_per_s / 1e9 / PEAK_HBM_GBS, 6))
+
+
+def roofline_of(st, n_clusters_per_launch):
+    """Roofline of the dominant kernel of a timed probe (stats with every
+    kernel timed): the constructor against the FP32 vector peak (algorithmic
+    FLOP from the device's work counters), a streaming kernel against HBM."""
+    per = {k: st["kernel_ms"][k] / st["kernel_launches"][k] for k in st["kernel_ms"]
+           if st["kernel_launches"][k] > 0}
+    dominant = max(per, key=per.get)
+    dom_ms = per[dominant]
+    launches = max(1, st["kernel_launches"][dominant])
+    if dominant == "k_construct":
+        flops = (st["steps"] * FLOP_STEP + st["updates"] * FLOP_UPDATE +
+                 st["candidates"] * FLOP_CAND) / launches
+        achieved = flops / (dom_ms * 1e-3) / 1e12
+        return dict(bound="alu", achieved=round(achieved, 4), peak=PEAK_FP32_TFLOPS,
+                    unit="TFLOP/s", frac=round(achieved / PEAK_FP32_TFLOPS, 6),
+                    kernel=dominant, kernel_ms=round(dom_ms, 5),
+                    algorithmic_per_launch=f"{flops:.4g} FLOP"), per
+    nbytes = BYTES_PER_CLUSTER.get(dominant, 16) * n_clusters_per_launch
+    achieved = nbytes / (dom_ms * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(achieved, 2), peak=PEAK_HBM_GBS, unit="GB/s",
+                frac=round(achieved / PEAK_HBM_GBS, 6), kernel=dominant,
+                kernel_ms=round(dom_ms, 5), algorithmic_per_launch=f"{nbytes} B"), per
+
+
+def timed_probe(tr, fn, reps=3):
+    """Every kernel timed with HIP events over `reps` eager calls."""
+    tr.set_timing(None)
+    tr.reset_stats()
+    for _ in range(reps):
+        fn()
+    st = tr.stats()
+    tr.set_timing([])
+    tr.reset_stats()
+    return st
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -66,14 +121,23 @@ def kernel_src_sha():
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def cpu_model():
+def cpu_info():
+    """The host CPU as /proc/cpuinfo describes it (first processor), with the
+    logical CPU count and this process's affinity."""
+    info = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            if not line.strip():
+                break
+            k, _, v = line.partition(":")
+            info[k.strip()] = v.strip()
     except OSError:
         pass
-    return "unknown"
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
+    return dict(cpu_model=info.get("model name", "unknown"),
+                cpu_family=info.get("cpu family"), cpu_model_number=info.get("model"),
+                stepping=info.get("stepping"), cpu_mhz=info.get("cpu MHz"),
+                cache=info.get("cache size"), nproc=os.cpu_count(), affinity=aff)
 
 
 def cpu_baseline(ev_host, geo_t, bz, gpu_res, n_clusters, seconds, params=None):
@@ -81,10 +145,10 @@ def cpu_baseline(ev_host, geo_t, bz, gpu_res, n_clusters, seconds, params=None):
     import oracle
     from oracle import concordance
     try:
-        cores = len(os.sched_getaffinity(0))
+        cores = len(os.sched_getaffinity(0))      # every core this process may run on
     except AttributeError:
         cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
+    cores = max(1, cores)
     runs, t0 = 0, time.perf_counter()
     ref = None
     while True:
@@ -100,25 +164,66 @@ def cpu_baseline(ev_host, geo_t, bz, gpu_res, n_clusters, seconds, params=None):
     single = 1.0 / (time.perf_counter() - t1)
     base = dict(value=runs / el, unit="events/s", cores=cores, kind="oracle",
                 sample=f"{runs} run(s) of the benchmark event ({n_clusters} clusters), "
-                       f"{el:.1f} s wall, {cores} threads over sectors",
-                single_thread_value=round(single, 4), cpu_model=cpu_model())
+                       f"{el:.1f} s wall, {cores} threads over sectors (every core of the "
+                       f"process's affinity)",
+                single_thread_value=round(single, 4), **cpu_info())
     conc = {k: rep[k] for k in ("cluster_concordance", "track_concordance", "cluster_concordance_ab",
                                 "cluster_concordance_ba", "n_tracks_a", "n_tracks_b",
-                                "par_compared", "par_fail", "par_max_rel")}
+                                "par_compared", "par_fail", "par_max_rel", "par_other_seed")}
     conc["reference"] = "FP64 oracle"
     return base, conc
 
 
-def _gen_preset(args):
+def _gen_event(args):
     from paper_1712_09407_amd import synth
     name, seed = args
-    e = synth.make_preset(name, seed)
+    return synth.make_preset(name, seed)
+
+
+def _gen_arrays(args):
+    from paper_1712_09407_amd import synth
+    name, seed = args
+    e = synth.make_preset(name, seed) if name != "batch" else synth.batch_event(seed)
     return e.y, e.z, e.row_offsets, e.sector_id
 
 
 def _pool_workers():
     n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     return max(1, min(16, n))
+
+
+CENTRAL_SEEDS = list(range(2, 12))   # concordance over ten central events
+ALPHA_SEEDS = [2, 3, 4]              # the alpha scan's central events
+STRESS_SEEDS = [5000 + i for i in range(16)]
+
+
+def pregenerate(args):
+    """Every host event the benchmark needs, generated in worker processes
+    before this process touches the GPU: a process that holds a GPU context
+    must not fork.  Returns a dict of event lists."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    jobs = {"main": [("event", (args.event, args.seed))]}
+    if args.extra:
+        jobs["central"] = [("event", ("c2_central", s)) for s in CENTRAL_SEEDS]
+        jobs["stress"] = [("arrays", ("c5_stress", s)) for s in STRESS_SEEDS]
+    if args.batch_events > 0:
+        jobs["batch"] = [("arrays", ("batch", 3000 + i)) for i in range(args.batch_events)]
+    flat = [(k, i, kind, a) for k, v in jobs.items() for i, (kind, a) in enumerate(v)]
+    # the main event is one of the central ones when it is a central seed
+    reuse = args.extra and args.event == "c2_central" and args.seed in CENTRAL_SEEDS
+    flat = [f for f in flat if not (reuse and f[0] == "main")]
+    log(f"generating {len(flat)} host events with {_pool_workers()} processes")
+    out = {k: [None] * len(v) for k, v in jobs.items()}
+    with cf.ProcessPoolExecutor(_pool_workers(), mp_context=mp.get_context("fork")) as ex:
+        futs = {ex.submit(_gen_event if kind == "event" else _gen_arrays, a): (k, i)
+                for k, i, kind, a in flat}
+        for f in cf.as_completed(futs):
+            k, i = futs[f]
+            out[k][i] = f.result()
+    if reuse:
+        out["main"] = [out["central"][CENTRAL_SEEDS.index(args.seed)]]
+    return out
 
 
 def oracle_params(tpc, gpu_params):
@@ -160,37 +265,36 @@ def single_sector_section(tr, tpc, synth, geo, prm, steps, log_):
                 ms_per_event=round(el / steps * 1e3, 4), n_tracks=int(res["n_tracks"]))
 
 
-def central_concordance_section(tr, tpc, synth, geo, prm, seeds, log_):
+def central_concordance_section(tr, tpc, synth, geo, prm, events, log_):
     """The GPU's tracks of several central events (so that concordance with
     the oracle, computed by the cpu_baseline leg, resolves 99.99% on ~100k
     tracks)."""
-    import concurrent.futures as cf
-    with cf.ProcessPoolExecutor(_pool_workers()) as ex:
-        host = list(ex.map(_gen_preset, [("c2_central", s) for s in seeds]))
     runs = []
-    for (y, z, ro, si) in host:
-        dev = tpc.DeviceEvent.from_host(y, z, ro, si)
-        runs.append((dict(y=y, z=z, row_offsets=ro, sector_id=si),
-                     tpc.to_numpy(tr.track_event(dev, geo, 0.5, prm))))
+    for e in events:
+        dev = tpc.DeviceEvent.from_host(e.y, e.z, e.row_offsets, e.sector_id)
+        runs.append((dict(y=e.y, z=e.z, row_offsets=e.row_offsets, sector_id=e.sector_id),
+                     tpc.to_numpy(tr.track_event(dev, geo, e.bz, prm))))
     ORACLE_CHECKS["central_concordance"] = dict(runs=runs)
-    return dict(workload=f"{len(seeds)} central events (seeds {seeds[0]}-{seeds[-1]})",
+    return dict(workload=f"{len(events)} central events (seeds {CENTRAL_SEEDS[0]}-"
+                         f"{CENTRAL_SEEDS[len(events) - 1]})",
                 tracks=int(sum(r["n_tracks"] for _, r in runs)),
                 clusters=int(sum(len(h["y"]) for h, _ in runs)))
 
 
-def stress_section(tr, tpc, synth, geo, n_events, steps, log_):
+def stress_section(tr, tpc, synth, geo, host, steps, log_):
     """Stress events (20000 primaries + 6000 loopers, 10% noise, sigma 0.15)
-    in batches of n_events: throughput; concordance and parameter error
-    against the oracle on the first event come from the cpu_baseline leg."""
-    import concurrent.futures as cf
+    in batches of len(host): throughput, the dominant kernel's roofline and
+    the path against HBM; concordance and parameter error against the oracle
+    on the first event come from the cpu_baseline leg."""
     import torch
-    seeds = [5000 + i for i in range(n_events)]
-    log_(f"generating {n_events} stress events")
-    with cf.ProcessPoolExecutor(_pool_workers()) as ex:
-        host = list(ex.map(_gen_preset, [("c5_stress", s) for s in seeds]))
+    n_events = len(host)
     prm = tpc.default_params(sigma_y=0.15, sigma_z=0.15)
     devs = [tpc.DeviceEvent.from_host(*h) for h in host]
     n_cl = sum(d.n_clusters for d in devs)
+    tr.set_tuning(use_graph=0)
+    st = timed_probe(tr, lambda: tr.track_batch(devs, geo, 0.5, prm), reps=2)
+    roof, per = roofline_of(st, n_cl)
+    tr.set_tuning()
     res = tr.track_batch(devs, geo, 0.5, prm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -201,11 +305,14 @@ def stress_section(tr, tpc, synth, geo, n_events, steps, log_):
     y, z, ro, si = host[0]
     ORACLE_CHECKS["stress"] = dict(ev=dict(y=y, z=z, row_offsets=ro, sector_id=si), bz=0.5,
                                    res=tpc.to_numpy(res[0]), n=len(y), prm=prm)
+    cps = n_cl * steps / el
     return dict(workload=f"{n_events} stress events per batch (20000 primaries + 6000 loopers, "
-                         f"10% noise, sigma 0.15 cm; seeds {seeds[0]}+), {n_cl} clusters",
+                         f"10% noise, sigma 0.15 cm; seeds {STRESS_SEEDS[0]}+), {n_cl} clusters",
                 events_per_s=round(n_events * steps / el, 2),
-                clusters_per_s=round(n_cl * steps / el, 1),
-                ms_per_batch=round(el / steps * 1e3, 3))
+                clusters_per_s=round(cps, 1),
+                ms_per_batch=round(el / steps * 1e3, 3),
+                roofline=roof, path_hbm=staged_hbm(cps),
+                kernels_ms_per_batch={k: round(v, 4) for k, v in per.items()})
 
 
 def global_section(tr, tpc, synth, geo, prm, e, dev_ev, steps, log_):
@@ -337,7 +444,8 @@ def cpu_baseline_leg(tpc, prm, main_args, log_):
     geo_t = (synth.ROW_X, synth.TAN_HALF, synth.Z_MAX)
     op = oracle_params(tpc, prm)
     base, conc = cpu_baseline(*main_args, op)
-    cores = _pool_workers()
+    cores = max(1, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                else (os.cpu_count() or 1))
     extra = {}
     for name, chk in ORACLE_CHECKS.items():
         log_(f"oracle check: {name}")
@@ -376,7 +484,8 @@ def cpu_baseline_leg(tpc, prm, main_args, log_):
                                    cluster_concordance=rep["cluster_concordance"],
                                    track_concordance=rep["track_concordance"],
                                    par_compared=rep["par_compared"], par_fail=rep["par_fail"],
-                                   par_max_rel=rep["par_max_rel"])
+                                   par_max_rel=rep["par_max_rel"],
+                                   par_other_seed=rep["par_other_seed"])
             elif name == "merger":
                 t1 = time.perf_counter()
                 rtr, _, rmg = oracle.track_event_merged(chk["ev"], geo_t, chk["bz"], op,
@@ -403,20 +512,11 @@ def cpu_baseline_leg(tpc, prm, main_args, log_):
     return base, conc, extra
 
 
-def _gen_event(args):
-    from paper_1712_09407_amd import synth
-    name, seed = args
-    return synth.make_preset(name, seed)
-
-
-def alpha_scan_section(tr, tpc, synth, geo, seeds, log_):
+def alpha_scan_section(tr, tpc, synth, geo, evs, log_):
     """Track-finding quality against MC truth as a function of the weight's
     alpha (section 3.1; alpha = infinity is the longest-track rule), on
     central events."""
-    import concurrent.futures as cf
     from paper_1712_09407_amd import quality
-    with cf.ProcessPoolExecutor(_pool_workers()) as ex:
-        evs = list(ex.map(_gen_event, [("c2_central", s) for s in seeds]))
     devs = [tpc.DeviceEvent.from_host(e.y, e.z, e.row_offsets, e.sector_id) for e in evs]
     rows = {}
     for a in quality.ALPHAS:
@@ -429,29 +529,18 @@ def alpha_scan_section(tr, tpc, synth, geo, seeds, log_):
             fake_rate=round(m["fake_rate"], 5), tracks=m["tracks"],
             **{f"res_{k}": round(v, 6) for k, v in m["resolution"].items() if k != "tracks"})
         log_(f"alpha {a}: {rows['inf' if a == float('inf') else f'{a:g}']}")
-    return dict(workload=f"{len(seeds)} central events (seeds {seeds[0]}-{seeds[-1]}), "
+    return dict(workload=f"{len(evs)} central events (seeds {ALPHA_SEEDS[0]}-{ALPHA_SEEDS[-1]}), "
                          "quality against MC truth per alpha", alphas=rows)
 
 
-def _gen_batch_event(seed):
-    from paper_1712_09407_amd import synth
-    e = synth.batch_event(seed)
-    return e.y, e.z, e.row_offsets, e.sector_id
-
-
-def batched_section(tr, tpc, synth, geo, prm, n_events, steps, log_):
+def batched_section(tr, tpc, synth, geo, prm, host, steps, log_):
     """Many events of very different multiplicity in one launch sequence
     (graph replay, autotuned), against the plain per-event loop on the same
-    events."""
-    import concurrent.futures as cf
+    events; the dominant kernel's roofline (eager probe, every kernel timed)
+    and the path against HBM."""
     import torch
     from paper_1712_09407_amd import tune
-    seeds = [3000 + i for i in range(n_events)]
-    workers = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
-                         else (os.cpu_count() or 1)))
-    log_(f"generating {n_events} batch events with {workers} processes")
-    with cf.ProcessPoolExecutor(workers) as ex:
-        host = list(ex.map(_gen_batch_event, seeds))
+    n_events = len(host)
     devs = [tpc.DeviceEvent.from_host(*h) for h in host]
     n_cl = sum(d.n_clusters for d in devs)
     # plain per-event loop over the same events
@@ -468,28 +557,30 @@ def batched_section(tr, tpc, synth, geo, prm, n_events, steps, log_):
     name = torch.cuda.get_device_name(0)
     rec = tune.autotune(tr, devs, geo, 0.5, prm, reps=1, device_name=name, use_cache=False,
                         log=log_)
-    outs = None
+    tuned = tr.set_tuning(use_graph=0, **rec["best"])
+    st = timed_probe(tr, lambda: tr.track_batch(devs, geo, 0.5, prm), reps=2)
+    roof, per = roofline_of(st, n_cl)
+    tr.set_tuning(use_graph=1, **rec["best"])
     res = tr.track_batch(devs, geo, 0.5, prm)
     torch.cuda.synchronize()
-    lat = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        ts = time.perf_counter()
         tr.track_batch(devs, geo, 0.5, prm)
-        lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     tr.set_tuning()
-    batched_section.host_events = host
+    cps = n_cl * steps / el
     return dict(workload=f"{n_events} events, multiplicity log-uniform 100-8000 tracks "
                          f"(seeds 3000+), {n_cl} clusters", events=n_events, clusters=n_cl,
                 events_per_s=round(n_events * steps / el, 2),
-                clusters_per_s=round(n_cl * steps / el, 1),
+                clusters_per_s=round(cps, 1),
                 ms_per_batch=round(el / steps * 1e3, 3),
                 plain_loop_events_per_s=round(n_events / plain_s, 2),
                 speedup_vs_plain=round((n_events * steps / el) / (n_events / plain_s), 3),
                 tuned=rec["best"], graph=True,
-                tracks=int(sum(r["n_tracks"] for r in res)))
+                tracks=int(sum(r["n_tracks"] for r in res)),
+                roofline=roof, path_hbm=staged_hbm(cps),
+                kernels_ms_per_batch={k: round(v, 4) for k, v in per.items()})
 
 
 def serving_section(tpc, synth, geo, prm, host, rates, n_events, log_):
@@ -568,14 +659,16 @@ def main():
               "(the path shards by event across GPUs, see the design notes)", file=sys.stderr)
         sys.exit(2)
 
+    # every host event first: nothing may fork once the GPU is initialised
+    host = pregenerate(args)
     import torch
     from paper_1712_09407_amd import synth, tpc
     import ctypes as C
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    log("generating the event", args.event, "seed", args.seed)
-    e = synth.make_preset(args.event, args.seed)
+    e = host["main"][0]
+    log("benchmark event", args.event, "seed", args.seed, e.n_clusters, "clusters")
     N = e.n_clusters
     geo = tpc.make_geometry(synth.ROW_X, synth.TAN_HALF, synth.Z_MAX)
     dev_ev = tpc.DeviceEvent.from_host(e.y, e.z, e.row_offsets, e.sector_id, device=dev)
@@ -683,13 +776,17 @@ def main():
             traffic = tj.get("bytes_per_launch")
     roof["traffic"] = traffic
 
-    # the whole path against HBM: staged algorithmic bytes, and the counters
+    # the whole path against HBM: the staged algorithmic model, the
+    # implementation's own traffic model, and the counters
+    eps = args.steps / el
+    path_hbm = staged_hbm(N * eps)
     pb = path_bytes(N, st["tracklets"] / ev_n, st["steps"] / ev_n, st["candidates"] / ev_n,
                     nt.value, nc.value)
-    eps = args.steps / el
-    path_hbm = dict(algorithmic_bytes_per_event=int(pb),
-                    achieved=round(pb * eps / 1e9, 2), unit="GB/s", peak=PEAK_HBM_GBS,
-                    frac=round(pb * eps / 1e9 / PEAK_HBM_GBS, 6), measured_bytes_per_event=None)
+    path_hbm["implementation_model"] = dict(
+        note="this implementation's traffic model: 16 B per candidate record, per-row hits "
+             "written and read back, owner keys",
+        bytes_per_event=int(pb), frac=round(pb * eps / 1e9 / PEAK_HBM_GBS, 6))
+    path_hbm["measured_bytes_per_event"] = None
     if os.path.exists(args.traffic_json):
         tj = json.load(open(args.traffic_json))
         if tj.get("kernel_src_sha") == kernel_src_sha() and tj.get("path_bytes_per_event"):
@@ -728,23 +825,24 @@ def main():
                 roofline=roof, path_hbm=path_hbm)
     if args.batch_events > 0:
         log("batched path ...")
-        line["batched"] = batched_section(tr, tpc, synth, geo, prm, args.batch_events,
+        line["batched"] = batched_section(tr, tpc, synth, geo, prm, host["batch"],
                                           args.batch_steps, log)
         log("batched:", line["batched"])
     if args.serve_events > 0 and args.batch_events > 0:
         log("serving ...")
-        line["serving"] = serving_section(tpc, synth, geo, prm, batched_section.host_events,
+        line["serving"] = serving_section(tpc, synth, geo, prm, host["batch"],
                                           (200.0, 500.0, 1000.0), args.serve_events, log)
     if args.extra:
+        alpha_evs = [host["central"][CENTRAL_SEEDS.index(s_)] for s_ in ALPHA_SEEDS]
         sections = (("single_sector", lambda: single_sector_section(tr, tpc, synth, geo, prm, 500, log)),
                     ("central_concordance", lambda: central_concordance_section(
-                        tr, tpc, synth, geo, prm, list(range(2, 12)), log)),
-                    ("stress", lambda: stress_section(tr, tpc, synth, geo, 16, 3, log)),
+                        tr, tpc, synth, geo, prm, host["central"], log)),
+                    ("stress", lambda: stress_section(tr, tpc, synth, geo, host["stress"], 3, log)),
                     ("global_tracking", lambda: global_section(tr, tpc, synth, geo, prm, e,
                                                                dev_ev, 20, log)),
                     ("merger", lambda: merge_section(tr, tpc, synth, geo, prm, e, dev_ev, 20,
                                                      log)),
-                    ("alpha_scan", lambda: alpha_scan_section(tr, tpc, synth, geo, [2, 3, 4], log)))
+                    ("alpha_scan", lambda: alpha_scan_section(tr, tpc, synth, geo, alpha_evs, log)))
         for name, fn in sections:
             log(f"{name} ...")
             try:

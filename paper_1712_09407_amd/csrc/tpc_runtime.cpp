@@ -388,6 +388,7 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
           ctx->kernel_launches[k] += 1;
         }
       }
+      (void)hipGetLastError();  // a kernel this call skipped has no recorded events
     }
     ctx->work[0] += 1;
     ctx->work[1] += c[C_SEEDS];
@@ -639,7 +640,9 @@ int run_batch(tpc_ctx* ctx, const tpc_event* evs, int E, const tpc_geometry* geo
     }
     if (c[C_ERR] & E_CAPACITY) return fail(TPC_ERR_DEVICE, "internal batch output overflow");
     if (timed) {
-      for (int k = 0; k < K_NUM; ++k) {
+      // only the kernels a batch launches: an elapsed-time query on an event
+      // that was never recorded fails and would leave HIP's last error set
+      for (int k = 0; k <= K_OUTPUT; ++k) {
         if (!(ctx->timer.mask >> k & 1u)) continue;
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, ctx->timer.ev[k][0], ctx->timer.ev[k][1]) == hipSuccess) {
@@ -647,6 +650,7 @@ int run_batch(tpc_ctx* ctx, const tpc_event* evs, int E, const tpc_geometry* geo
           ctx->kernel_launches[k] += 1;
         }
       }
+      (void)hipGetLastError();  // a kernel this call skipped has no recorded events
     }
     ctx->work[0] += E;
     ctx->work[1] += c[C_SEEDS];
