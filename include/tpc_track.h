@@ -135,6 +135,23 @@ void tpc_ctx_destroy(tpc_ctx* ctx);
 int tpc_track_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float bz_tesla,
                     const tpc_params* params, tpc_tracks* out, void* hip_stream);
 
+/* ---- allocation-free variant ----------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * tpc_track_event with the same arguments, outputs and results, except that
+ * its scratch is a static array of TPC_NOALLOC_SCRATCH_BYTES per GPU (held
+ * by the library until the process ends, its address resolved by
+ * tpc_ctx_create) instead of the context's arena: the call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine).  The scratch of an
+ * event is about 130 B per cluster (a central event of 1.33 M clusters:
+ * about 175 MB); an event whose scratch does not fit returns TPC_ERR_OOM.
+ * Every call on a GPU shares that GPU's array, so calls that overlap on one
+ * GPU (from different contexts or streams) race: serialise them. */
+#define TPC_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int tpc_track_event_noalloc(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo,
+                            float bz_tesla, const tpc_params* params, tpc_tracks* out,
+                            void* hip_stream);
+
 /* Track n_events events in one launch sequence (sections 1, 3.1, 3.2): the
  * events' sectors are tracked side by side and each event's tracks, cluster
  * lists and cluster->track map are written to its own outputs[i], exactly as

@@ -198,6 +198,15 @@ hipError_t enqueue_batch_gather(const BatchBuffers& bb, const Scratch& sc, int n
 hipError_t enqueue_batch_scatter(const BatchBuffers& bb, const Scratch& sc, int n_events,
                                  hipStream_t st);
 
+// Static scratch of the allocation-free entry point (one array per device).
+constexpr size_t kStaticScratchBytes = TPC_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+// Resolves the array's address on `device`, which must be current; once per
+// device, later calls return at once.
+hipError_t static_scratch_init(int device);
+// The device address of the array on `device`, or null before static_scratch_init.
+void* static_scratch(int device);
+
 size_t scratch_bytes(int64_t n_clusters, int64_t n_rowslots, int64_t cap_tl);
 // Global tracking: the end states (Scratch::ends) and GlobalScratch.
 size_t global_bytes(int64_t n_clusters, int64_t cap_tl);

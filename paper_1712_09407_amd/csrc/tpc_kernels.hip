@@ -36,6 +36,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "tpc_internal.h"
 #include "tpc_model.h"
@@ -2499,6 +2500,38 @@ hipError_t enqueue_batch_scatter(const BatchBuffers& bb, const Scratch& sc, int 
 // ------------------------------------------------------------------ host side
 
 static inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// ------------------------------------------------------------------ static scratch
+//
+// The scratch of tpc_track_event_noalloc, for callers that cannot allocate:
+// one array per GPU, held until the process ends.  In host code the name
+// `scratch` is a host-side stand-in, not a device address: the address on
+// each device comes from hipGetSymbolAddress, resolved once per device (with
+// that device current) by static_scratch_init, and only that pointer is
+// handed to the kernels.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = p;
+  return hipSuccess;
+}
+
+void* static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 size_t scratch_bytes(int64_t N, int64_t R, int64_t T) {
   size_t b = 0;

@@ -274,10 +274,16 @@ int ensure_glob(tpc_ctx* ctx, int64_t N, int64_t S, int64_t T, bool with_merge, 
 // bits to return codes.  With `po`, global tracking follows the whole path
 // and its counters land in h_counters[C_COUNT ..].  On a tracklet overflow the reservation is raised and
 // the event is run once more (results do not depend on the reservation).
+//
+// no_alloc: the scratch is the static per-device array (static_scratch), never
+// the context's arena: nothing is allocated, and an event whose scratch does
+// not fit the array fails with TPC_ERR_OOM.  The tracklet reservation is
+// capped to what fits; an overflow is retried once with a larger one if it
+// fits.
 int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float bz,
               const tpc_params* p, const Outputs& out, int upto, hipStream_t st,
               Scratch* sc_out, const ProOutputs* po = nullptr, const MergeOutputs* mo = nullptr,
-              float merge_chi2 = 0.f) {
+              float merge_chi2 = 0.f, bool no_alloc = false) {
   int rc = validate(ev, geo, p);
   if (rc) return rc;
   if (!std::isfinite(bz)) return fail(TPC_ERR_INVALID_ARG, "bz must be finite");
@@ -303,11 +309,27 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
   kp.merge_chi2 = merge_chi2;
   const DevEvent dev = make_devevent(ev);
   int64_t T = default_tracklets(ctx, N, p);
+  void* fixed = nullptr;
+  if (no_alloc) {
+    fixed = static_scratch(ctx->device);
+    if (!fixed) return fail(TPC_ERR_DEVICE, "static scratch of device %d not resolved", ctx->device);
+    if (scratch_bytes(N, R, 256) > kStaticScratchBytes)
+      return fail(TPC_ERR_OOM, "an event of %lld clusters needs more scratch than the static "
+                               "%zu bytes", (long long)N, kStaticScratchBytes);
+  }
+  // the largest reservation up to T whose scratch fits the static array
+  auto fit = [&](int64_t t) {
+    while (t > 256 && scratch_bytes(N, R, t) > kStaticScratchBytes) t -= t / 16 + 1;
+    return t < 256 ? 256 : t;
+  };
+  if (no_alloc) T = fit(T);
   for (int attempt = 0; attempt < 2; ++attempt) {
-    rc = ensure_arena(ctx, N, R, T, st);
-    if (rc) return rc;
+    if (!no_alloc) {
+      rc = ensure_arena(ctx, N, R, T, st);
+      if (rc) return rc;
+    }
     Scratch sc;
-    scratch_carve(ctx->arena, N, R, T, &sc);
+    scratch_carve(no_alloc ? fixed : ctx->arena, N, R, T, &sc);
     GlobalScratch gs{};
     MergeScratch ms{};
     if (po || mo) {
@@ -372,6 +394,9 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
         return fail(TPC_ERR_OVERFLOW, "%lld tracklets exceed the reservation of %lld",
                     (long long)need, (long long)T);
       T = grow_tracklets(ctx, need, N);
+      if (no_alloc && scratch_bytes(N, R, T) > kStaticScratchBytes)
+        return fail(TPC_ERR_OOM, "%lld tracklets need more scratch than the static %zu bytes",
+                    (long long)need, kStaticScratchBytes);
       continue;
     }
     if (timed) {
@@ -723,6 +748,13 @@ int tpc_ctx_create(int device, size_t hbm_budget_bytes, tpc_ctx** out) {
     delete c;
     return hip_fail(e, "hipHostMalloc");
   }
+  // the allocation-free entry point's array on this device (once per device)
+  e = static_scratch_init(device);
+  if (e != hipSuccess) {
+    (void)hipHostFree(c->h_counters);
+    delete c;
+    return hip_fail(e, "hipGetSymbolAddress(static scratch)");
+  }
   *out = c;
   return TPC_OK;
 }
@@ -828,6 +860,27 @@ int tpc_track_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, 
             out->track_cluster, out->cluster_track};
   hipStream_t st = (hipStream_t)hip_stream;
   int rc = run_event(ctx, ev, geo, bz_tesla, params, o, STAGE_ALL, st, nullptr);
+  if (rc) return rc;
+  const int32_t* c = ctx->h_counters;
+  *out->n_tracks = c[C_TRACKS];
+  *out->n_track_clusters = c[C_TRACK_CLUSTERS];
+  if (c[C_ERR] & E_CAPACITY)
+    return fail(TPC_ERR_CAPACITY, "need %d tracks / %d track clusters, have %d / %d",
+                c[C_TRACKS], c[C_TRACK_CLUSTERS], out->cap_tracks, out->cap_track_clusters);
+  return TPC_OK;
+}
+
+int tpc_track_event_noalloc(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo,
+                            float bz_tesla, const tpc_params* params, tpc_tracks* out,
+                            void* hip_stream) {
+  if (!ctx) return fail(TPC_ERR_INVALID_ARG, "ctx is null");
+  int rc0 = check_outputs(ev, out);
+  if (rc0) return rc0;
+  Outputs o{out->cap_tracks, out->cap_track_clusters, out->track_par, out->track_meta,
+            out->track_cluster, out->cluster_track};
+  hipStream_t st = (hipStream_t)hip_stream;
+  int rc = run_event(ctx, ev, geo, bz_tesla, params, o, STAGE_ALL, st, nullptr, nullptr, nullptr,
+                     0.f, true);
   if (rc) return rc;
   const int32_t* c = ctx->h_counters;
   *out->n_tracks = c[C_TRACKS];

@@ -85,9 +85,11 @@ class Merged(C.Structure):
 MERGE_CHI2 = 25.0   # joins: chi^2(5) <= 25, a 1e-4 tail for the same particle
 
 EXPORTS = ["tpc_params_default", "tpc_validate", "tpc_ctx_create", "tpc_ctx_destroy",
-           "tpc_track_event", "tpc_track_event_global", "tpc_track_event_merged", "tpc_refit", "tpc_track_batch", "tpc_debug_links", "tpc_debug_tracklets", "tpc_last_error",
+           "tpc_track_event", "tpc_track_event_global", "tpc_track_event_merged", "tpc_refit",
+           "tpc_track_batch", "tpc_debug_links", "tpc_debug_tracklets", "tpc_last_error",
            "tpc_kernel_count", "tpc_kernel_name", "tpc_ctx_set_timing", "tpc_ctx_get_stats",
-           "tpc_ctx_reset_stats", "tpc_tuning_default", "tpc_ctx_set_tuning",
+           "tpc_ctx_reset_stats", "tpc_track_event_noalloc", "tpc_tuning_default",
+           "tpc_ctx_set_tuning",
            "tpc_ctx_graph_launches", "tpc_server_config_default", "tpc_server_create",
            "tpc_server_submit", "tpc_server_poll", "tpc_server_fetch", "tpc_server_stats",
            "tpc_server_now", "tpc_server_last_error", "tpc_server_destroy"]
@@ -106,6 +108,8 @@ def _load():
     L.tpc_ctx_destroy.restype = None
     L.tpc_track_event.argtypes = [C.c_void_p, P(Event), P(Geometry), C.c_float, P(Params),
                                   P(Tracks), C.c_void_p]
+    L.tpc_track_event_noalloc.argtypes = [C.c_void_p, P(Event), P(Geometry), C.c_float,
+                                          P(Params), P(Tracks), C.c_void_p]
     L.tpc_track_event_global.argtypes = [C.c_void_p, P(Event), P(Geometry), C.c_float,
                                          P(Params), P(Tracks), P(Prolongations), C.c_void_p]
     L.tpc_track_event_merged.argtypes = [C.c_void_p, P(Event), P(Geometry), C.c_float,
@@ -478,6 +482,13 @@ class Tracker:
         """Direct call on prebuilt structs (no allocation), for timing loops."""
         return lib.tpc_track_event(self._h, C.byref(e), C.byref(geo), float(bz),
                                    C.byref(params), C.byref(tr), stream_handle)
+
+    def track_event_noalloc_raw(self, e: Event, geo: Geometry, bz: float, params: Params,
+                                tr: Tracks, stream_handle) -> int:
+        """tpc_track_event_noalloc on prebuilt structs: the caller's outputs,
+        the library's static scratch; nothing is allocated."""
+        return lib.tpc_track_event_noalloc(self._h, C.byref(e), C.byref(geo), float(bz),
+                                           C.byref(params), C.byref(tr), stream_handle)
 
     def track_event_global_raw(self, e: Event, geo: Geometry, bz: float, params: Params,
                                tr: Tracks, pro: Prolongations, stream_handle) -> int:
