@@ -428,8 +428,9 @@ static void kseed(kstate* s, double xa, double ya, double za, double xb, double 
  * rows, collect clusters that meet a chi^2 condition, refit, until no more
  * clusters are found.  Reading used:
  *   1. seed from the chain (kseed: first, middle and last of the first
- *      seed_window chain clusters), then filter outward through all chain
- *      clusters unconditionally;
+ *      seed_window chain clusters; the seed only starts the outward filter,
+ *      and a window of 16 and the whole chain give the same tracks), then
+ *      filter outward through all chain clusters unconditionally;
  *   2. keep going outward row by row: propagate, search the row, take the
  *      cluster with the smallest (chi2, index) if chi2 <= chi2_gate, else
  *      count a miss;
