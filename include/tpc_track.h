@@ -340,7 +340,8 @@ int tpc_ctx_reset_stats(tpc_ctx* ctx);
  * admitted when its device footprint (about 160 B per cluster) fits the
  * budget still free, is staged and uploaded at once, and is tracked by the
  * next free worker together with every other uploaded event (at most
- * max_batch).  n_workers workers, each with its own context and stream, keep
+ * max_batch; an event that finds a worker idle is tracked alone by the
+ * per-event path of tpc_track_event, without the batch's gather and scatter).  n_workers workers, each with its own context and stream, keep
  * that many batches in flight, so uploads, tracking and downloads of
  * different events overlap.  Each event's tracks are exactly those
  * tpc_track_event gives it alone.  One worker with max_batch = 1 is the

@@ -1,6 +1,8 @@
 // Serving loop of the tracker: events arrive one by one in host memory, are
 // admitted while their device footprint fits a budget, are uploaded at once,
-// and are tracked in batches by worker threads as the GPU frees up.  Several
+// and are tracked by worker threads as the GPU frees up: an event that finds
+// a worker idle is tracked alone by the per-event path, events that queued
+// behind busy workers are tracked together as one batch.  Several
 // workers keep several batches in flight, so uploads, tracking and result
 // downloads of different events overlap on the device.
 //
@@ -181,7 +183,11 @@ void worker_main(tpc_server* s, int wi) {
       o.track_cluster = (int32_t*)(out + al(32 * (size_t)j->cap_tracks) + al(16 * (size_t)j->cap_tracks));
       o.cluster_track = (int32_t*)((char*)o.track_cluster + al(4 * n));
     }
-    const int rc = tpc_track_batch(ctx, evs.data(), E, &s->geo, s->bz, &s->prm, outs.data(), st);
+    // a lone event (it arrived at an idle worker) takes the plain per-event
+    // path at once; events that queued behind busy workers go as one batch
+    const int rc = E == 1 ? tpc_track_event(ctx, &evs[0], &s->geo, s->bz, &s->prm, &outs[0], st)
+                          : tpc_track_batch(ctx, evs.data(), E, &s->geo, s->bz, &s->prm,
+                                            outs.data(), st);
     // results back to pinned host memory
     for (int i = 0; i < E && rc == TPC_OK; ++i) {
       Job* j = jobs[i];
