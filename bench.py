@@ -117,8 +117,12 @@ def log(*a):
 
 
 def kernel_src_sha():
-    p = os.path.join(ROOT, "paper_1712_09407_amd", "csrc", "tpc_kernels.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    """Hash of the device sources (kernels and track model): counter figures
+    taken from other sources are not reported."""
+    h = hashlib.sha256()
+    for f in ("tpc_kernels.hip", "tpc_model.h"):
+        h.update(open(os.path.join(ROOT, "paper_1712_09407_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def cpu_info():
