@@ -10,8 +10,9 @@
 //   k_grid        per row slot: validate offsets, counting-sort the row into a
 //                 y/z bin grid (the "initialization" of section 2, done on the
 //                 device), clear the cluster->track output
-//   k_nf          per row slot: stage rows k-1 and k+1 in LDS, best straight
-//                 neighbour pair of every cluster of row k
+//   k_nf          per row slot (rows of all sectors in row order, the dense
+//                 inner rows first): stage rows k-1 and k+1 in LDS, best
+//                 straight neighbour pair of every cluster of row k
 //   k_evo         per row slot: keep reciprocal links, flag chain starts of
 //                 at least min_seed_len clusters, count them per row
 //   k_scan_rows   one block: exclusive scan of the per-row seed counts
@@ -46,11 +47,12 @@ namespace tpc {
 constexpr int kGridBlock = 256;
 constexpr int kMaxBins = 4096;   // bins per row (LDS counting sort)
 // k_nf stages neighbour rows of up to CAP clusters in LDS and keeps up to
-// LIST window candidates per row and lane: (512, 16) for rows of central
-// density (smaller LDS footprint, more workgroups per CU), (1024, 32) for
-// dense events.  Larger rows or lists use the exact global-memory search;
-// every configuration gives the same links.
-constexpr int kNfCapSmall = 512, kNfListSmall = 16;
+// LIST window candidates per row and lane: (512, 12) with 16-bit entries for
+// rows of central density (31 KB of LDS, five workgroups per CU), (1024, 32)
+// with 8-bit entries for dense events (49 KB, three workgroups per CU).  A
+// lane's longer list is searched by its whole wave, a longer row by the
+// global-memory search; every configuration gives the same links.
+constexpr int kNfCapSmall = 512, kNfListSmall = 12;
 constexpr int kNfCapLarge = 1024, kNfListLarge = 32;
 constexpr int kScanBlock = 1024;
 constexpr int kTlBlock = 64;     // one wave per block for per-tracklet kernels
@@ -242,15 +244,39 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(DevEvent ev, KParams kp, Sc
 
 // ------------------------------------------------------------------ k_nf
 
+// The straightness of a candidate pair (section 1): d on row k-1, u on row
+// k+1 and the cluster c of row k between them.  (ry, rz) = (1 - t)(d - c) +
+// t (u - c) is how far the straight line through d and u passes from c on
+// row k, with t = (x_k - x_{k-1}) / (x_{k+1} - x_{k-1}); chi^2 = (ry^2 /
+// sigma_y^2 + rz^2 / sigma_z^2) / (1 + t^2 + (1 - t)^2).  a = (1 - t)(d - c)
+// is taken once per d, and w = the inverse variances over the norm once per
+// row.  Every search below evaluates chi^2 with these two functions, so the
+// staged, the wave-wide and the global-memory searches give the same links.
+struct NfMetric {
+  float t, omt, wy, wz;
+};
+__device__ __forceinline__ float2 nf_a(const NfMetric& k, float2 d, float2 c) {
+  return make_float2(k.omt * (d.x - c.x), k.omt * (d.y - c.y));
+}
+__device__ __forceinline__ float nf_chi2(const NfMetric& k, float2 a, float2 u, float2 c) {
+  const float ry = fmaf(k.t, u.x - c.x, a.x), rz = fmaf(k.t, u.y - c.y, a.y);
+  return fmaf(ry, ry * k.wy, rz * (rz * k.wz));
+}
+
 // Neighbour-row view staged in LDS.
 struct RowView {
   const float2* yz;
-  const int32_t* id;
-  const int32_t* bins;  // bins of the row, index 0 = first bin
+  const uint16_t* id;    // cluster index - base
+  const uint16_t* bins;  // bins of the row, index 0 = first bin
   RowGrid g;
+  int base;
   __device__ float2 yz_at(int j) const { return yz[j]; }
-  __device__ int id_at(int j) const { return id[j]; }
+  __device__ int id_at(int j) const { return base + id[j]; }
 };
+
+__device__ __forceinline__ float2 yz_off(const float2* yz, int off) {
+  return *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(yz) + off);
+}
 
 // Neighbour-row view in global memory (rows too large for the LDS stage).
 struct RowViewG {
@@ -265,33 +291,30 @@ struct RowViewG {
 };
 
 
-// Best (chi2, d, u) pair for a cluster at (yc, zc) of row k (section 1):
-// every pair of window candidates, no lists (used for dense rows).
+// Best (chi2, d, u) pair for a cluster at c of row k (section 1): every pair
+// of window candidates, no lists (used for rows beyond the LDS stage).
 template <class V>
-__device__ __forceinline__ void nf_search(const V& D, const V& U, float yc, float zc,
-                                          float t, float wy, float wz, float isy2, float isz2,
-                                          float inorm, float& best, int& bd, int& bu) {
+__device__ __forceinline__ void nf_search(const V& D, const V& U, float2 c, const NfMetric& km,
+                                          float wy, float wz, float& best, int& bd, int& bu) {
   const float m = 1e-3f;  // bin ranges are only an accelerator: widen them
-  const int dy0 = bin_y(D.g, yc - wy - m), dy1 = bin_y(D.g, yc + wy + m);
-  const int dz0 = bin_z(D.g, zc - wz - m), dz1 = bin_z(D.g, zc + wz + m);
-  const int uy0 = bin_y(U.g, yc - wy - m), uy1 = bin_y(U.g, yc + wy + m);
-  const int uz0 = bin_z(U.g, zc - wz - m), uz1 = bin_z(U.g, zc + wz + m);
+  const int dy0 = bin_y(D.g, c.x - wy - m), dy1 = bin_y(D.g, c.x + wy + m);
+  const int dz0 = bin_z(D.g, c.y - wz - m), dz1 = bin_z(D.g, c.y + wz + m);
+  const int uy0 = bin_y(U.g, c.x - wy - m), uy1 = bin_y(U.g, c.x + wy + m);
+  const int uz0 = bin_z(U.g, c.y - wz - m), uz1 = bin_z(U.g, c.y + wz + m);
   for (int iz = dz0; iz <= dz1; ++iz) {
     const int j0 = D.bins[iz * D.g.ny + dy0], j1 = D.bins[iz * D.g.ny + dy1 + 1];
     for (int j = j0; j < j1; ++j) {
       const float2 pd = D.yz_at(j);
-      if (!in_window(pd, yc, zc, wy, wz)) continue;
+      if (!in_window(pd, c.x, c.y, wy, wz)) continue;
       const int idd = D.id_at(j);
-      const float dyd = pd.x - yc, dzd = pd.y - zc;
+      const float2 a = nf_a(km, pd, c);
       for (int kz = uz0; kz <= uz1; ++kz) {
         const int k0 = U.bins[kz * U.g.ny + uy0], k1 = U.bins[kz * U.g.ny + uy1 + 1];
         for (int k = k0; k < k1; ++k) {
           const float2 pu = U.yz_at(k);
-          if (!in_window(pu, yc, zc, wy, wz)) continue;
+          if (!in_window(pu, c.x, c.y, wy, wz)) continue;
           const int idu = U.id_at(k);
-          const float ry = dyd + t * ((pu.x - yc) - dyd);
-          const float rz = dzd + t * ((pu.y - zc) - dzd);
-          const float chi2 = (ry * ry * isy2 + rz * rz * isz2) * inorm;
+          const float chi2 = nf_chi2(km, a, pu, c);
           if (bd < 0 || chi2 < best ||
               (chi2 == best && (idd < bd || (idd == bd && idu < bu)))) {
             best = chi2;
@@ -304,19 +327,42 @@ __device__ __forceinline__ void nf_search(const V& D, const V& U, float yc, floa
   }
 }
 
-// Window candidates of one neighbour row: row-local positions into list
-// (column `lane` of a [LIST][blockDim] LDS array).  Returns the count,
-// which may exceed LIST (then the list is incomplete).
-template <int LIST>
+// Entries of a lane's candidate list.  uint16_t: the byte offset of the
+// record in the LDS stage (8 x its position), used as it is.  uint8_t: the
+// position relative to the lane's first candidate, so that twice as many
+// entries fit the same LDS; a candidate more than 255 positions after the
+// first does not fit.
+template <class E>
+struct NfEntry;
+template <>
+struct NfEntry<uint16_t> {
+  __device__ static uint16_t enc(int j, int) { return (uint16_t)(j << 3); }
+  __device__ static int off(int v, int) { return v; }
+};
+template <>
+struct NfEntry<uint8_t> {
+  __device__ static uint8_t enc(int j, int first) { return (uint8_t)(j - first); }
+  __device__ static int off(int v, int first) { return (first + v) << 3; }
+};
+
+// Window candidates of one neighbour row, listed in column `lane` of a
+// [LIST][blockDim] LDS array (NfEntry; *first = the first candidate's
+// position).  Returns the count, or LIST + 1 if the list cannot hold them
+// all.
+template <int LIST, class E>
 __device__ __forceinline__ int nf_collect(const RowView& V, float yc, float zc, float wy, float wz,
-                                          uint16_t (*list)[kGridBlock], int lane) {
+                                          E (*list)[kGridBlock], int lane, int* first) {
   const float m = 1e-3f;
   const int y0 = bin_y(V.g, yc - wy - m), y1 = bin_y(V.g, yc + wy + m);
   const int z0 = bin_z(V.g, zc - wz - m), z1 = bin_z(V.g, zc + wz + m);
-  int cnt = 0;
+  int cnt = 0, j0 = 0;
+  bool far = false;
+  // candidates come in position order (bin rows, then bins, of the grid)
   auto take = [&](int j, float2 p) {
     if (in_window(p, yc, zc, wy, wz)) {
-      if (cnt < LIST) list[cnt][lane] = (uint16_t)j;
+      j0 = cnt ? j0 : j;
+      if constexpr (sizeof(E) == 1) far |= j - j0 >= 256;
+      if (cnt < LIST && !far) list[cnt][lane] = NfEntry<E>::enc(j, j0);
       ++cnt;
     }
   };
@@ -342,16 +388,20 @@ __device__ __forceinline__ int nf_collect(const RowView& V, float yc, float zc, 
         if (k + u < n) take(j[u], p[u]);
     }
   }
-  return cnt;
+  *first = j0;
+  return far ? LIST + 1 : cnt;
 }
 
 // Pair bookkeeping of one wave: its clusters' first pair, candidate counts
-// in the upper row, coordinates, and best pair keys.
+// in the upper row, coordinates, best pair keys and, for relative list
+// entries, the first candidates' positions in both rows.
+template <class E>
 struct NfPairs {
   int off[64];
-  int nu[64];
+  uint16_t nu[64];
   float2 c[64];
   unsigned long long key[64];
+  uint16_t first[2][sizeof(E) == 1 ? 64 : 1];
 };
 
 // LDS written by other lanes of the wave is visible after this.
@@ -361,12 +411,22 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Entry e of a wave's shared list: the 16-bit byte offset of a record in
+// the stage, in the wave's columns of a list, 32 sizeof(E) entries a row.
+template <class E>
+__device__ __forceinline__ uint16_t& wave_slot(E (*list)[kGridBlock], int col0, int e) {
+  constexpr int per = 32 * sizeof(E);
+  return *reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(&list[e / per][col0]) +
+                                      2 * (e % per));
+}
+
 // Window candidates of one neighbour row for ONE cluster (yc, zc the same in
-// every lane), listed by the whole wave into its columns of list: entry e
-// sits at list[e / 64][col0 + e % 64], in bin order.  Returns the count
-// (the list is incomplete beyond cap entries).
+// every lane), listed by the whole wave into its columns of list (wave_slot),
+// in bin order.  Returns the count (the list is incomplete beyond cap
+// entries).
+template <class E>
 __device__ __forceinline__ int nf_wave_collect(const RowView& V, float yc, float zc, float wy,
-                                               float wz, uint16_t (*list)[kGridBlock], int cap,
+                                               float wz, E (*list)[kGridBlock], int cap,
                                                int col0, int lane) {
   const float m = 1e-3f;
   const int y0 = bin_y(V.g, yc - wy - m), y1 = bin_y(V.g, yc + wy + m);
@@ -379,22 +439,21 @@ __device__ __forceinline__ int nf_wave_collect(const RowView& V, float yc, float
       const bool in = j < j1 && in_window(V.yz[min(j, j1 - 1)], yc, zc, wy, wz);
       const unsigned long long bal = __ballot(in);
       const int pos = cnt + __popcll(bal & ((1ull << lane) - 1ull));
-      if (in && pos < cap) list[pos >> 6][col0 + (pos & 63)] = (uint16_t)j;
+      if (in && pos < cap) wave_slot(list, col0, pos) = (uint16_t)(j << 3);
       cnt += __popcll(bal);
     }
   }
   return cnt;
 }
 
-// The best pair key (chi^2 bits, d, u positions; ~0 if none) of ONE cluster
-// at c, searched by the whole wave: both candidate lists, then the pairs
-// dealt out over the lanes and a 64-bit minimum.  *fits is false if a list
-// exceeded cap (the key is then not valid).
-template <int CAP>
+// The best pair key (chi^2 bits, d, u row-local indices; ~0 if none) of ONE
+// cluster at c, searched by the whole wave: both candidate lists, then the
+// pairs dealt out over the lanes and a 64-bit minimum.  *fits is false if a
+// list exceeded cap (the key is then not valid).
+template <class E>
 __device__ __forceinline__ unsigned long long nf_wave_pairs(
-    const RowView& D, const RowView& U, float2 c, float t, float inorm, float isy2, float isz2,
-    float wy, float wz, int bd_, int bu_, const int32_t (*s_id)[CAP], uint16_t (*s_dl)[kGridBlock],
-    uint16_t (*s_ul)[kGridBlock], int cap, int col0, int lane, bool* fits) {
+    const RowView& D, const RowView& U, float2 c, const NfMetric& km, float wy, float wz,
+    E (*s_dl)[kGridBlock], E (*s_ul)[kGridBlock], int cap, int col0, int lane, bool* fits) {
   const int nd = nf_wave_collect(D, c.x, c.y, wy, wz, s_dl, cap, col0, lane);
   const int nu = nd ? nf_wave_collect(U, c.x, c.y, wy, wz, s_ul, cap, col0, lane) : 0;
   *fits = nd <= cap && nu <= cap;
@@ -404,16 +463,11 @@ __device__ __forceinline__ unsigned long long nf_wave_pairs(
   const int np = nd * nu, dp = 64 / nu, dq = 64 - dp * nu;
   int p = lane / nu, q = lane - (lane / nu) * nu;
   for (int k = lane; k < np; k += 64) {
-    const int jd = s_dl[p >> 6][col0 + (p & 63)], ju = s_ul[q >> 6][col0 + (q & 63)];
-    const float2 pd = D.yz[jd], pu = U.yz[ju];
-    const float dyd = pd.x - c.x, dzd = pd.y - c.y;
-    const float ry = dyd + t * ((pu.x - c.x) - dyd);
-    const float rz = dzd + t * ((pu.y - c.y) - dzd);
-    const float chi2 = (ry * ry * isy2 + rz * rz * isz2) * inorm;
+    const int jd = wave_slot(s_dl, col0, p), ju = wave_slot(s_ul, col0, q);
+    const float chi2 = nf_chi2(km, nf_a(km, yz_off(D.yz, jd), c), yz_off(U.yz, ju), c);
     const unsigned long long hi = (unsigned long long)__float_as_uint(chi2) << 32;
     if (hi <= best)
-      best = min(best, hi | ((unsigned long long)(s_id[0][jd] - bd_) << 16) |
-                           (unsigned)(s_id[1][ju] - bu_));
+      best = min(best, hi | ((unsigned long long)D.id[jd >> 3] << 16) | (unsigned)U.id[ju >> 3]);
     q += dq;
     p += dp;
     if (q >= nu) {
@@ -428,23 +482,30 @@ __device__ __forceinline__ unsigned long long nf_wave_pairs(
 // The staged neighbour search of a row's clusters (section 1), one cluster
 // per lane.  Each lane lists its window candidates in both neighbour rows;
 // then the pairs of the wave's 64 clusters are dealt out evenly (each lane
-// walks a contiguous run of them), so that a dense cluster does not hold up
-// its wave.  The best pair of a cluster is the smallest (chi^2, d, u), with
-// d and u the clusters' positions in their rows (16 bits each; the cluster
-// indices of a row are contiguous, so this is the order of the indices),
-// whichever lane evaluated it: one 64-bit minimum per cluster in LDS.  A
-// cluster with more than LIST candidates in a row is searched by the whole
-// wave afterwards (nf_wave_pairs).
-template <int CAP, int LIST>
+// walks a contiguous run of them, up to four pairs of one (cluster, d) at a
+// time), so that a dense cluster does not hold up its wave.  The best pair of
+// a cluster is the smallest (chi^2, d, u), with d and u the clusters' indices
+// relative to their rows' first (16 bits each), whichever lane evaluated it:
+// one 64-bit minimum per cluster in LDS.  Within a run a lane keeps only the
+// smallest chi^2 and where it was found; an exact tie of chi^2 (rare) is
+// decided on the indices on a separate path.  A cluster with more than LIST
+// candidates in a row is searched by the whole wave afterwards
+// (nf_wave_pairs).  The four reads of a group may run past the end of a
+// u list, into rows cleared before the first round or left by an earlier
+// one: s_ul has three rows more than LIST, and with relative entries the
+// upper row's stage 256 records more than CAP, so that these reads stay in
+// place; their pairs are not counted.
+template <int CAP, int LIST, class E>
 __device__ __forceinline__ void nf_pairs_staged(
     const DevEvent& ev, const KParams& kp, const Scratch& sc, int b, int e, int bd_, int bu_,
-    const RowGrid& gd, const RowGrid& gu, const GridRec& me_first, float t, float inorm,
-    float isy2, float isz2, float wy, float wz, float2 (*s_yz)[CAP], int32_t (*s_id)[CAP],
-    int32_t (*s_bins)[CAP + 1], uint16_t (*s_dl)[kGridBlock], uint16_t (*s_ul)[kGridBlock],
-    NfPairs* s_pw) {
+    const RowGrid& gd, const RowGrid& gu, const GridRec& me_first, const NfMetric& km,
+    float wy, float wz, const float2* s_yzd, const float2* s_yzu, uint16_t (*s_id)[CAP],
+    uint16_t (*s_bins)[CAP + 2], E (*s_dl)[kGridBlock], E (*s_ul)[kGridBlock],
+    NfPairs<E>* s_pw) {
+  constexpr bool kRel = sizeof(E) == 1;  // relative (8-bit) list entries
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, col0 = tid - lane;
-  NfPairs& P = s_pw[w];
-  const RowView D{s_yz[0], s_id[0], s_bins[0], gd}, U{s_yz[1], s_id[1], s_bins[1], gu};
+  NfPairs<E>& P = s_pw[w];
+  const RowView D{s_yzd, s_id[0], s_bins[0], gd, bd_}, U{s_yzu, s_id[1], s_bins[1], gu, bu_};
   const bool both = gd.n > 0 && gu.n > 0;
   for (int base = col0; base < e - b; base += kGridBlock) {  // uniform over the wave
     const int ii = base + lane;
@@ -452,10 +513,10 @@ __device__ __forceinline__ void nf_pairs_staged(
     GridRec me = {};
     if (have) me = ii == tid ? me_first : sc.g_rec[b + ii];
     const float yc = me.y, zc = me.z;
-    int nd = 0, nu = 0;
+    int nd = 0, nu = 0, fd = 0, fu = 0;
     if (have && both) {
-      nd = nf_collect<LIST>(D, yc, zc, wy, wz, s_dl, tid);
-      nu = nd ? nf_collect<LIST>(U, yc, zc, wy, wz, s_ul, tid) : 0;
+      nd = nf_collect<LIST>(D, yc, zc, wy, wz, s_dl, tid, &fd);
+      nu = nd ? nf_collect<LIST>(U, yc, zc, wy, wz, s_ul, tid, &fu) : 0;
     }
     const bool listed = nd <= LIST && nu <= LIST;
     const int np = listed ? nd * nu : 0;
@@ -467,6 +528,10 @@ __device__ __forceinline__ void nf_pairs_staged(
     const int total = __shfl(incl, 63, 64);
     P.off[lane] = incl - np;
     P.nu[lane] = nu;
+    if constexpr (kRel) {
+      P.first[0][lane] = fd;
+      P.first[1][lane] = fu;
+    }
     P.c[lane] = make_float2(yc, zc);
     P.key[lane] = ~0ull;
     wave_lds_sync();
@@ -478,46 +543,80 @@ __device__ __forceinline__ void nf_pairs_staged(
       int o = 0;  // owner: the last cluster whose first pair is <= k
       for (int step = 32; step >= 1; step >>= 1)
         if (o + step < 64 && P.off[o + step] <= k) o += step;
-      int nu_o = P.nu[o];
+      int nu_o = P.nu[o], db = 0, ub = 0;
+      if constexpr (kRel) {
+        db = P.first[0][o];
+        ub = P.first[1][o];
+      }
       int next = o < 63 ? P.off[o + 1] : total;
       float2 c = P.c[o];
-      int rel = k - P.off[o];
+      const int rel = k - P.off[o];
       int p = rel / nu_o, q = rel - p * nu_o;
-      int jd = s_dl[p][col0 + o];
-      float2 pd = s_yz[0][jd];
-      float dyd = pd.x - c.x, dzd = pd.y - c.y;
-      unsigned long long kd = (unsigned long long)(s_id[0][jd] - bd_) << 16;
-      unsigned long long best = ~0ull;
-      auto pair = [&](int ku, float2 pu) {
-        const float ry = dyd + t * ((pu.x - c.x) - dyd);
-        const float rz = dzd + t * ((pu.y - c.y) - dzd);
-        const float chi2 = (ry * ry * isy2 + rz * rz * isz2) * inorm;
-        const unsigned long long hi = (unsigned long long)__float_as_uint(chi2) << 32;
-        // the candidate's index only when it can win: most pairs do not
-        if (hi <= best) best = min(best, hi | kd | (unsigned)(s_id[1][ku] - bu_));
+      int jd = NfEntry<E>::off(s_dl[p][col0 + o], db);  // byte offsets into the stage
+      float2 a = nf_a(km, yz_off(s_yzd, jd), c);
+      float bc = INFINITY;  // the run's best for cluster o: chi^2, d and u offsets
+      int bj = -1, bk = -1;
+      auto flush = [&]() {
+        if (bj >= 0)
+          atomicMin(&P.key[o], ((unsigned long long)__float_as_uint(bc) << 32) |
+                                   ((unsigned long long)s_id[0][bj >> 3] << 16) |
+                                   (unsigned)s_id[1][bk >> 3]);
       };
       while (true) {
         // up to four pairs of the same (cluster, d) at once: their LDS reads
         // overlap
         const int m = min(4, min(nu_o - q, kend - k));
-        const int col = col0 + o;
-        const int ku0 = s_ul[q][col], ku1 = s_ul[q + (m > 1)][col];
-        const int ku2 = s_ul[q + (m > 2 ? 2 : 0)][col], ku3 = s_ul[q + (m > 3 ? 3 : 0)][col];
-        const float2 pu0 = s_yz[1][ku0], pu1 = s_yz[1][ku1], pu2 = s_yz[1][ku2], pu3 = s_yz[1][ku3];
-        pair(ku0, pu0);
-        if (m > 1) pair(ku1, pu1);
-        if (m > 2) pair(ku2, pu2);
-        if (m > 3) pair(ku3, pu3);
+        const E* lu = &s_ul[q][col0 + o];
+        int ku[4];
+        float x[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ku[i] = NfEntry<E>::off(lu[i * kGridBlock], ub);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i] = nf_chi2(km, a, yz_off(s_yzu, ku[i]), c);
+        const float bc0 = bc;
+        const int bj0 = bj, bk0 = bk;
+        bool tie = false;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const bool v = i < m;
+          tie |= v && x[i] == bc;
+          const bool lt = v && x[i] < bc;
+          bc = lt ? x[i] : bc;
+          bj = lt ? jd : bj;
+          bk = lt ? ku[i] : bk;
+        }
+        if (tie) {  // an exact tie of chi^2: the group again, on the full keys
+          bc = bc0;
+          bj = bj0;
+          bk = bk0;
+          for (int i = 0; i < m; ++i) {
+            bool take = bj < 0 || x[i] < bc;
+            if (!take && x[i] == bc) {
+              const int d1 = s_id[0][jd >> 3], d0 = s_id[0][bj >> 3];
+              take = d1 < d0 || (d1 == d0 && s_id[1][ku[i] >> 3] < s_id[1][bk >> 3]);
+            }
+            if (take) {
+              bc = x[i];
+              bj = jd;
+              bk = ku[i];
+            }
+          }
+        }
         k += m;
         q += m - 1;
         if (k == kend) break;
         if (k == next) {  // the next cluster with pairs
-          atomicMin(&P.key[o], best);
-          best = ~0ull;
+          flush();
+          bc = INFINITY;
+          bj = bk = -1;
           do {
             ++o;
           } while (o < 63 && P.off[o + 1] <= k);
           nu_o = P.nu[o];
+          if constexpr (kRel) {
+            db = P.first[0][o];
+            ub = P.first[1][o];
+          }
           next = o < 63 ? P.off[o + 1] : total;
           c = P.c[o];
           p = q = 0;
@@ -527,13 +626,10 @@ __device__ __forceinline__ void nf_pairs_staged(
         } else {
           continue;
         }
-        jd = s_dl[p][col0 + o];
-        pd = s_yz[0][jd];
-        dyd = pd.x - c.x;
-        dzd = pd.y - c.y;
-        kd = (unsigned long long)(s_id[0][jd] - bd_) << 16;
+        jd = NfEntry<E>::off(s_dl[p][col0 + o], db);
+        a = nf_a(km, yz_off(s_yzd, jd), c);
       }
-      atomicMin(&P.key[o], best);
+      flush();
     }
     wave_lds_sync();
     unsigned long long key = P.key[lane];
@@ -544,9 +640,9 @@ __device__ __forceinline__ void nf_pairs_staged(
     for (unsigned long long ov = __ballot(!listed); ov; ov &= ov - 1ull) {
       const int o = __ffsll((unsigned long long)ov) - 1;
       bool fits;
-      const unsigned long long ko = nf_wave_pairs<CAP>(D, U, P.c[o], t, inorm, isy2, isz2, wy, wz,
-                                                       bd_, bu_, s_id, s_dl, s_ul, LIST * 64,
-                                                       col0, lane, &fits);
+      const unsigned long long ko =
+          nf_wave_pairs(D, U, P.c[o], km, wy, wz, s_dl, s_ul, LIST * 32 * (int)sizeof(E), col0,
+                        lane, &fits);
       if (lane == o) {
         key = ko;
         alone = !fits;
@@ -556,7 +652,7 @@ __device__ __forceinline__ void nf_pairs_staged(
     float best = INFINITY;
     int bd = -1, bu = -1;
     if (alone) {  // even the wave's lists overflow: nested bin scans
-      nf_search(D, U, yc, zc, t, wy, wz, isy2, isz2, inorm, best, bd, bu);
+      nf_search(D, U, make_float2(yc, zc), km, wy, wz, best, bd, bu);
     } else if (key != ~0ull) {
       best = __uint_as_float((unsigned)(key >> 32));
       bd = bd_ + (int)((key >> 16) & 0xffffu);
@@ -571,17 +667,21 @@ __device__ __forceinline__ void nf_pairs_staged(
   }
 }
 
-template <int CAP, int LIST>
+template <int CAP, int LIST, class E>
 __global__ __launch_bounds__(kGridBlock) void k_nf(DevEvent ev, KParams kp, Scratch sc) {
-  __shared__ float2 s_yz[2][CAP];
-  __shared__ int32_t s_id[2][CAP];
-  __shared__ int32_t s_bins[2][CAP + 1];
-  __shared__ uint16_t s_dl[LIST][kGridBlock];
-  __shared__ uint16_t s_ul[LIST][kGridBlock];
-  __shared__ NfPairs s_pw[kGridBlock / 64];
+  static_assert(CAP * 8 <= 65536, "stage offsets are 16-bit");
+  static_assert(LIST * 32 * (int)sizeof(E) >= CAP, "a wave's lists hold a whole staged row");
+  __shared__ float2 s_yzd[CAP], s_yzu[CAP + (sizeof(E) == 1 ? 256 : 0)];
+  __shared__ uint16_t s_id[2][CAP];
+  __shared__ uint16_t s_bins[2][CAP + 2];
+  __shared__ E s_dl[LIST][kGridBlock];
+  __shared__ E s_ul[LIST + 3][kGridBlock];
+  __shared__ NfPairs<E> s_pw[kGridBlock / 64];
   if (event_bad(sc.counters)) return;
-  const int rs = blockIdx.x;
-  const int r = rs % kp.n_rows;
+  // blocks in row-major order over the sectors: the dense inner rows of every
+  // sector start first, and the sparse outer rows fill in behind them
+  const int r = blockIdx.x / ev.n_sectors;
+  const int rs = (blockIdx.x - r * ev.n_sectors) * kp.n_rows + r;
   const int tid = threadIdx.x;
   const int b = ev.ro[rs], e = ev.ro[rs + 1];
   if (r == 0 || r == kp.n_rows - 1) {
@@ -598,36 +698,40 @@ __global__ __launch_bounds__(kGridBlock) void k_nf(DevEvent ev, KParams kp, Scra
   if (tid < e - b) me_first = sc.g_rec[b + tid];
   const RowGrid gd = sc.grid[rs - 1], gu = sc.grid[rs + 1];
   const int bd_ = ev.ro[rs - 1], bu_ = ev.ro[rs + 1];
-  // staged: both rows fit the LDS stage, and positions in them fit 16 bits
-  const bool stage = gd.n <= CAP && gu.n <= CAP && b - bd_ <= 65536 && ev.ro[rs + 2] - bu_ <= 65536;
+  // staged: both rows fit the LDS stage
+  const bool stage = gd.n <= CAP && gu.n <= CAP;
   const float xd = kp.row_x[r - 1], xc = kp.row_x[r], xu = kp.row_x[r + 1];
-  const float t = (xc - xd) / (xu - xd);
-  const float inorm = 1.f / (1.f + t * t + (1.f - t) * (1.f - t));
-  const float isy2 = 1.f / kp.sy2, isz2 = 1.f / kp.sz2;
+  NfMetric km;
+  km.t = (xc - xd) / (xu - xd);
+  km.omt = 1.f - km.t;
+  const float inorm = 1.f / (1.f + km.t * km.t + km.omt * km.omt);
+  km.wy = inorm / kp.sy2;
+  km.wz = inorm / kp.sz2;
   const float wy = kp.nf_win_y, wz = kp.nf_win_z;
   if (stage) {
     const int nbd = gd.ny * gd.nz, nbu = gu.ny * gu.nz;
     for (int i = tid; i < gd.n; i += kGridBlock) {
       const GridRec v = sc.g_rec[bd_ + i];
-      s_yz[0][i] = make_float2(v.y, v.z);
-      s_id[0][i] = v.id;
+      s_yzd[i] = make_float2(v.y, v.z);
+      s_id[0][i] = (uint16_t)(v.id - bd_);
     }
     for (int i = tid; i < gu.n; i += kGridBlock) {
       const GridRec v = sc.g_rec[bu_ + i];
-      s_yz[1][i] = make_float2(v.y, v.z);
-      s_id[1][i] = v.id;
+      s_yzu[i] = make_float2(v.y, v.z);
+      s_id[1][i] = (uint16_t)(v.id - bu_);
     }
     if (gd.n > 0)
-      for (int i = tid; i <= nbd; i += kGridBlock) s_bins[0][i] = sc.bins[gd.bin_base + i];
+      for (int i = tid; i <= nbd; i += kGridBlock) s_bins[0][i] = (uint16_t)sc.bins[gd.bin_base + i];
     if (gu.n > 0)
-      for (int i = tid; i <= nbu; i += kGridBlock) s_bins[1][i] = sc.bins[gu.bin_base + i];
+      for (int i = tid; i <= nbu; i += kGridBlock) s_bins[1][i] = (uint16_t)sc.bins[gu.bin_base + i];
+    for (int i = 0; i < LIST + 3; ++i) s_ul[i][tid] = 0;
     __syncthreads();
   }
   // lanes take the row's clusters in grid order: neighbouring lanes sit at
   // nearby positions and visit similar bins, so a wave diverges less
   if (stage) {
-    nf_pairs_staged<CAP, LIST>(ev, kp, sc, b, e, bd_, bu_, gd, gu, me_first, t, inorm, isy2, isz2,
-                               wy, wz, s_yz, s_id, s_bins, s_dl, s_ul, s_pw);
+    nf_pairs_staged<CAP, LIST, E>(ev, kp, sc, b, e, bd_, bu_, gd, gu, me_first, km, wy, wz, s_yzd,
+                               s_yzu, s_id, s_bins, s_dl, s_ul, s_pw);
     return;
   }
   for (int ii = tid; ii < e - b; ii += kGridBlock) {
@@ -638,7 +742,7 @@ __global__ __launch_bounds__(kGridBlock) void k_nf(DevEvent ev, KParams kp, Scra
     if (gd.n > 0 && gu.n > 0) {
       const RowViewG D{sc.g_rec + bd_, sc.bins + gd.bin_base, gd};
       const RowViewG U{sc.g_rec + bu_, sc.bins + gu.bin_base, gu};
-      nf_search(D, U, me.y, me.z, t, wy, wz, isy2, isz2, inorm, best, bd, bu);
+      nf_search(D, U, make_float2(me.y, me.z), km, wy, wz, best, bd, bu);
     }
     const bool ok = bd >= 0 && best <= kp.nf_chi2_max;
     sc.up[i] = ok ? bu : -1;
@@ -2689,9 +2793,11 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
   if (upto <= STAGE_GRID) return hipGetLastError();
   pre(K_NF);
   if (kp.nf_dense)
-    hipLaunchKernelGGL((k_nf<kNfCapLarge, kNfListLarge>), dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc);
+    hipLaunchKernelGGL((k_nf<kNfCapLarge, kNfListLarge, uint8_t>), dim3(R), dim3(kGridBlock), 0, st,
+                       ev, kp, sc);
   else
-    hipLaunchKernelGGL((k_nf<kNfCapSmall, kNfListSmall>), dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc);
+    hipLaunchKernelGGL((k_nf<kNfCapSmall, kNfListSmall, uint16_t>), dim3(R), dim3(kGridBlock), 0, st,
+                       ev, kp, sc);
   post(K_NF);
   pre(K_EVO);
   hipLaunchKernelGGL(k_evo, dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc);
