@@ -346,7 +346,7 @@ def crowded_event(seed, noise_frac, n_hot):
 
 @pytest.mark.parametrize("noise_frac,n_hot", [(0.0, 30), (3.0, 140)])
 def test_crowded_windows_match_the_oracle(orc, tracker, geo, noise_frac, n_hot):
-    """Clusters with more window candidates than a lane's list (16 on sparse
+    """Clusters with more window candidates than a lane's list (12 on sparse
     rows, 32 on dense ones, about 300 clusters per row and more) are searched
     by the whole wave: the links are the oracle's (up to near-ties)."""
     e = crowded_event(41, noise_frac, n_hot)
@@ -360,6 +360,35 @@ def test_crowded_windows_match_the_oracle(orc, tracker, geo, noise_frac, n_hot):
     hot = np.concatenate([np.arange(e.row_offsets[r + 1] - n_hot, e.row_offsets[r + 1])
                           for r in range(1, e.row_offsets.shape[0] - 2)])
     assert (up[hot] >= 0).mean() > 0.9                    # the hot spot links up
+
+
+def test_wide_thin_rows_match_the_oracle(orc, tracker, geo):
+    """Dense rows (one sector, 0.44 clusters per cm^2, z in a 20 cm slab) on
+    which a window's candidates lie in several bin rows of the row's grid,
+    each as wide as the sector: on the outer rows about one in ten clusters
+    has at most 32 candidates in a neighbour row that lie more than 255
+    positions apart in grid order, beyond what an 8-bit list entry holds,
+    and about as many have more than 32.  Both go to the wave-wide search:
+    the links are the oracle's (up to near-ties)."""
+    rng = np.random.default_rng(43)
+    xr = synth.ROW_X.astype(np.float64)
+    ys, zs, ro = [], [], [0]
+    for r in range(synth.N_ROWS):
+        hw = xr[r] * float(synth.TAN_HALF)
+        n = int(0.44 * 2.0 * hw * 20.0)
+        ys.append(rng.uniform(-hw, hw, n).astype(np.float32))
+        zs.append(rng.uniform(0.0, 20.0, n).astype(np.float32))
+        ro.append(ro[-1] + n)
+    e = types.SimpleNamespace(y=np.concatenate(ys), z=np.concatenate(zs),
+                              row_offsets=np.array(ro, np.int32),
+                              sector_id=np.array([0], np.int32), bz=0.5, n_clusters=int(ro[-1]))
+    say("wide thin rows", e.n_clusters)
+    assert e.n_clusters > 320 * synth.N_ROWS                  # the dense configuration
+    pg, po = params_pair(orc)
+    up, dn, _, _ = (x.cpu().numpy() for x in tracker.links(dev_event(e), geo, pg))
+    uo, do_ = orc.neighbours(event_dict(e), GEO_T, po)
+    assert check_links(orc, e, po, up, dn, uo, do_) <= max(2, 1e-5 * e.n_clusters)
+    assert (up >= 0).mean() > 0.9
 
 
 def test_invalid_offsets_and_nonfinite(tracker, geo):
