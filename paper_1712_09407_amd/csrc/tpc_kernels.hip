@@ -56,6 +56,7 @@ constexpr int kNfCapSmall = 512, kNfListSmall = 12;
 constexpr int kNfCapLarge = 1024, kNfListLarge = 32;
 constexpr int kScanBlock = 1024;
 constexpr int kTlBlock = 64;     // one wave per block for per-tracklet kernels
+constexpr int kLdsHitLanes = 24; // the lane constructor keeps hits in LDS up to this many lanes
 
 // ------------------------------------------------------------------ helpers
 
@@ -951,7 +952,14 @@ __device__ __forceinline__ void load_end(const float* E, KState& s) {
 // Rows without a cluster do not update the state, so each is stored once,
 // when its pass ends (the state then sits some miss rows beyond its cluster),
 // and k_prolong carries it back to that cluster's row with one helix step.
-template <bool ENDS>
+// LDSH: the cluster of every row the tracklet visits is kept in the lane's
+// row slots in LDS (H), and only the rows inner..outer go out to the hits
+// array, once, at emit; the inward refit reads a row's coordinates through
+// its cluster index.  Otherwise H is the tracklet's row of the hits array and
+// the collected clusters' coordinates are stored beside it (HY), so that
+// the refit reads them without a dependent load.  Both give the same
+// tracklets.
+template <bool ENDS, bool LDSH = false>
 struct Lane {
   KState s;
   int t = 0, phase = P_DONE, r = 0, k0 = 0, rsb = 0, last_row = 0, misses = 0, n = 0, inner = 0;
@@ -962,7 +970,7 @@ struct Lane {
   float chi2 = 0.f;
   float o0 = 0.f, o1 = 0.f, o2 = 0.f, o3 = 0.f, o4 = 0.f, o5 = 0.f;  // output state
   bool dropped = false;
-  int32_t* H = nullptr;
+  int32_t* H = nullptr;   // LDSH: this lane's kHitStride row slots in LDS
   float2* HY = nullptr;
   // the hit of the last step, stored at the start of the next one (or at the
   // end), so that no wait for loads of a step also waits for these stores
@@ -973,7 +981,9 @@ struct Lane {
   __device__ void flush() {
     if (pend_r >= 0) {
       H[pend_r] = pend_h;
-      if (pend_yz) HY[pend_r] = make_float2(pend_y, pend_z);
+      if constexpr (!LDSH) {
+        if (pend_yz) HY[pend_r] = make_float2(pend_y, pend_z);
+      }
       pend_r = -1;
     }
   }
@@ -991,8 +1001,10 @@ struct Lane {
     const int rs0 = sc.seed_rs[tt];
     k0 = rs0 % nr;
     rsb = rs0 - k0;
-    H = sc.hits + (size_t)tt * kHitStride;
-    HY = sc.hit_yz + (size_t)tt * kHitStride;
+    if constexpr (!LDSH) {
+      H = sc.hits + (size_t)tt * kHitStride;
+      HY = sc.hit_yz + (size_t)tt * kHitStride;
+    }
     int m = 0, c = start, last = start, c1 = -1, c2 = -1;
     while (c >= 0 && m < kp.seed_window && k0 + m < nr) {
       H[k0 + m] = c;
@@ -1009,7 +1021,7 @@ struct Lane {
     dropped = fabsf(s.sp) > kp.max_sinphi;
     last_row = k0;
     l_sp = s.sp; l_tl = s.tl; l_q = s.qpt; l_y = s.y; l_z = s.z;
-    HY[k0] = make_float2(s.y, s.z);
+    if constexpr (!LDSH) HY[k0] = make_float2(s.y, s.z);
     phase = P_CHAIN;
     r = k0 + 1;
     cn = c1;
@@ -1024,7 +1036,8 @@ struct Lane {
   }
 
   // Inward refit set-up from the outermost collected cluster.
-  __device__ void begin_refit(const KParams& kp, const Scratch& sc, const float* s_x) {
+  __device__ void begin_refit(const DevEvent& ev, const KParams& kp, const Scratch& sc,
+                              const float* s_x) {
     if constexpr (ENDS) store_end(sc.ends + ((size_t)t * 2 + 1) * kEndStride, s);
     s.x = s_x[last_row];
     s.y = l_y;
@@ -1039,17 +1052,22 @@ struct Lane {
     o0 = s.x; o1 = s.y; o2 = s.z; o3 = s.sp; o4 = s.tl; o5 = s.qpt;
     phase = P_REFIT;
     r = last_row - 1;
-    prefetch_refit();
+    prefetch_refit(ev);
   }
 
-  // Cluster of row r and its coordinates, both loads in flight at once (the
-  // coordinates are used only if the row has a cluster).
-  __device__ void prefetch_refit() {
+  // Cluster of row r and its coordinates (used only if the row has a
+  // cluster): without LDSH both loads are in flight at once.
+  __device__ void prefetch_refit(const DevEvent& ev) {
     if (r >= k0) {
       hc = H[r];
-      const float2 v = HY[r];
-      cy = v.x;
-      cz = v.y;
+      if constexpr (LDSH) {
+        cy = ev.y[max(hc, 0)];
+        cz = ev.z[max(hc, 0)];
+      } else {
+        const float2 v = HY[r];
+        cy = v.x;
+        cz = v.y;
+      }
     }
   }
 
@@ -1075,9 +1093,14 @@ struct Lane {
       nc = sc.up2[cnn];
     } else if (pf_refit) {
       nc = H[r - 1];
-      const float2 v = HY[r - 1];
-      ny = v.x;
-      nz = v.y;
+      if constexpr (LDSH) {
+        ny = ev.y[max(nc, 0)];
+        nz = ev.z[max(nc, 0)];
+      } else {
+        const float2 v = HY[r - 1];
+        ny = v.x;
+        nz = v.y;
+      }
     }
     // 1. one helix step for every lane, whatever its phase
     const bool ok = propagate(s, s_x[r], kp);
@@ -1132,12 +1155,12 @@ struct Lane {
         } else {
           phase = P_UP;
           misses = 0;
-          if (r >= nr) begin_refit(kp, sc, s_x);
+          if (r >= nr) begin_refit(ev, kp, sc, s_x);
         }
       } else {
         misses = st == 0 ? 0 : misses + 1;
         ++r;
-        if (st == 2 || misses > kp.max_miss || r >= nr) begin_refit(kp, sc, s_x);
+        if (st == 2 || misses > kp.max_miss || r >= nr) begin_refit(ev, kp, sc, s_x);
       }
     } else {  // P_REFIT or P_DOWN: collected clusters enter the final fit
       if (st == 0) {
@@ -1191,6 +1214,13 @@ struct Lane {
       sc.n[t] = n;
       sc.ndf[t] = 2 * n - 5;
       sc.chi2[t] = chi2;
+      if constexpr (LDSH) {
+        // rows inner..last_row out to the hits array, four at a time (the
+        // other rows of the first and last four are never read)
+        int4* G = reinterpret_cast<int4*>(sc.hits + (size_t)t * kHitStride);
+        const int4* S = reinterpret_cast<const int4*>(H);
+        for (int q = inner >> 2; q <= last_row >> 2; ++q) G[q] = S[q];
+      }
     }
     sc.owned[t] = 0;  // summed over the sector's chunks by k_own
     float* P = sc.par + (size_t)t * 6;
@@ -1439,8 +1469,9 @@ __global__ __launch_bounds__(64) void k_construct_rows(DevEvent ev, KParams kp, 
 
 // ---- lane schedule
 
-template <bool ENDS>
+template <bool ENDS, bool LDSH>
 __global__ __launch_bounds__(kTlBlock) void k_construct_lanes(DevEvent ev, KParams kp, Scratch sc) {
+  extern __shared__ __align__(16) int32_t s_hits[];  // LDSH: [A][kHitStride] row slots
   __shared__ float s_x[TPC_MAX_ROWS];
   if (event_bad(sc.counters)) return;
   for (int i = threadIdx.x; i < kp.n_rows; i += kTlBlock) s_x[i] = kp.row_x[i];
@@ -1475,7 +1506,8 @@ __global__ __launch_bounds__(kTlBlock) void k_construct_lanes(DevEvent ev, KPara
   };
   int kg = (int)threadIdx.x < A ? (int)(blockIdx.x / G) * A + (int)threadIdx.x : total_g;
   int t = kg < total_g ? group_tracklet(kg) : n_tl;
-  Lane<ENDS> ln;
+  Lane<ENDS, LDSH> ln;
+  if constexpr (LDSH) ln.H = s_hits + min((int)threadIdx.x, A - 1) * kHitStride;
   RowGrid gn;  // grid header of the next extension row, loaded one step early
   if (t < n_tl) ln.begin(t, ev, kp, sc, s_x);
   while (t < n_tl) {
@@ -2819,13 +2851,26 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
     else
       hipLaunchKernelGGL(k_construct_rows<false>, dim3(nb), dim3(64), 0, st, ev, kp, sc);
   } else {
-    const int nb = xcd_grid(kp.construct_blocks > 0
-                                ? kp.construct_blocks
-                                : tl_blocks(sc.cap_tl, min(max(kp.construct_lanes, 1), kTlBlock)));
-    if (sc.ends)
-      hipLaunchKernelGGL(k_construct_lanes<true>, dim3(nb), dim3(kTlBlock), 0, st, ev, kp, sc);
-    else
-      hipLaunchKernelGGL(k_construct_lanes<false>, dim3(nb), dim3(kTlBlock), 0, st, ev, kp, sc);
+    const int A = min(max(kp.construct_lanes, 1), kTlBlock);
+    const int nb = xcd_grid(kp.construct_blocks > 0 ? kp.construct_blocks : tl_blocks(sc.cap_tl, A));
+    // the lanes' row slots in LDS while their LDS still leaves about ten
+    // workgroups per CU; with more lanes per wave the hits array holds them
+    const size_t lds = sizeof(int32_t) * kHitStride * A;
+    if (A <= kLdsHitLanes) {
+      if (sc.ends)
+        hipLaunchKernelGGL((k_construct_lanes<true, true>), dim3(nb), dim3(kTlBlock), lds, st, ev,
+                           kp, sc);
+      else
+        hipLaunchKernelGGL((k_construct_lanes<false, true>), dim3(nb), dim3(kTlBlock), lds, st, ev,
+                           kp, sc);
+    } else {
+      if (sc.ends)
+        hipLaunchKernelGGL((k_construct_lanes<true, false>), dim3(nb), dim3(kTlBlock), 0, st, ev,
+                           kp, sc);
+      else
+        hipLaunchKernelGGL((k_construct_lanes<false, false>), dim3(nb), dim3(kTlBlock), 0, st, ev,
+                           kp, sc);
+    }
   }
   post(K_CONSTRUCT);
   if (upto <= STAGE_TRACKLETS) return hipGetLastError();

@@ -264,7 +264,10 @@ def test_deterministic(orc, tracker, geo):
 def test_constructor_schedules_agree_bitwise(tracker, geo, name, seed):
     """The row-synchronous and the lane-per-tracklet constructor run the same
     lane steps: every output bit must agree (dense rows exercise the
-    global-memory search of the row-synchronous schedule)."""
+    global-memory search of the row-synchronous schedule).  The lane
+    constructor runs twice: with its default lanes per wave (at most 24 on
+    these events), which keep their hit rows in LDS, and with 64, which keep
+    them in the hits array."""
     if name == "dense":
         e = synth.make_event(synth.EventConfig(n_tracks=150, sectors=(0,), phi_range_deg=(0, 20),
                                                ignore_membrane=True, noise_frac=20.0), seed)
@@ -276,21 +279,23 @@ def test_constructor_schedules_agree_bitwise(tracker, geo, name, seed):
     say("schedules", name, seed, e.n_clusters)
     dev = dev_event(e)
     out = []
-    for sched in (0, 1):
-        tracker.set_tuning(construct_schedule=sched)
+    for tuning in (dict(construct_schedule=0), dict(construct_schedule=1),
+                   dict(construct_schedule=0, construct_lanes=64)):
+        tracker.set_tuning(**tuning)
         tl = tracker.tracklets(dev, geo, e.bz)
         res = tpc.to_numpy(tracker.track_event(dev, geo, e.bz))
         out.append((tpc.to_numpy(tl), res))
     tracker.set_tuning()
-    (tla, ra), (tlb, rb) = out
-    for k in tla:
-        if k != "hits":
-            assert np.array_equal(tla[k].view(np.uint8), tlb[k].view(np.uint8)), k
-    for t in range(len(tla["seeds"])):  # hits are defined on [row_lo, row_hi]
-        lo, hi = tla["row_lo"][t], tla["row_hi"][t]
-        assert np.array_equal(tla["hits"][t, lo:hi + 1], tlb["hits"][t, lo:hi + 1]), t
-    for k in ("track_par", "track_meta", "track_cluster", "cluster_track"):
-        assert np.array_equal(ra[k].view(np.uint8), rb[k].view(np.uint8)), k
+    tla, ra = out[0]
+    for tlb, rb in out[1:]:
+        for k in tla:
+            if k != "hits":
+                assert np.array_equal(tla[k].view(np.uint8), tlb[k].view(np.uint8)), k
+        for t in range(len(tla["seeds"])):  # hits are defined on [row_lo, row_hi]
+            lo, hi = tla["row_lo"][t], tla["row_hi"][t]
+            assert np.array_equal(tla["hits"][t, lo:hi + 1], tlb["hits"][t, lo:hi + 1]), t
+        for k in ("track_par", "track_meta", "track_cluster", "cluster_track"):
+            assert np.array_equal(ra[k].view(np.uint8), rb[k].view(np.uint8)), k
 
 
 # ------------------------------------------------------------- edge cases
