@@ -315,6 +315,12 @@ typedef struct {
                                  tracklets (1 .. 64); fewer lanes per wave shorten
                                  each wave's steps at the cost of more waves;
                                  0 = automatic (about 2048 waves for the event) */
+  int32_t nf_stage;           /* neighbours finder's LDS stage: 1 = rows of up to 512
+                                 clusters, 12 window candidates per lane and row
+                                 (five workgroups per CU); 2 = rows of up to 1024
+                                 clusters, 32 candidates (three per CU); larger rows
+                                 take the global-memory search; 0 = automatic (2 when
+                                 the event averages more than 320 clusters per row) */
 } tpc_tuning;
 void tpc_tuning_default(tpc_tuning* t);
 int tpc_ctx_set_tuning(tpc_ctx* ctx, const tpc_tuning* t);

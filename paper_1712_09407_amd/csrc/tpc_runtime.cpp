@@ -144,6 +144,10 @@ static int32_t own_chunk(int64_t n_clusters, int64_t n_rowslots, int32_t n_rows)
 static int32_t dense_rows(int64_t n_clusters, int64_t n_rowslots) {
   return n_clusters > (int64_t)320 * (n_rowslots > 0 ? n_rowslots : 1) ? 1 : 0;
 }
+// The neighbours finder's stage: the tuning's choice, or by density.
+static int32_t nf_stage_of(int32_t stage, int64_t n_clusters, int64_t n_rowslots) {
+  return stage == 0 ? dense_rows(n_clusters, n_rowslots) : (stage == 2 ? 1 : 0);
+}
 
 KParams make_kparams(const tpc_geometry* geo, float bz, const tpc_params* p) {
   KParams k;
@@ -295,7 +299,7 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
   kp.construct_blocks = ctx->tuning.construct_blocks;
   kp.construct_schedule = ctx->tuning.construct_schedule;
   kp.construct_lanes = lanes_per_wave(ctx->tuning.construct_lanes, N);
-  kp.nf_dense = dense_rows(N, R);
+  kp.nf_dense = nf_stage_of(ctx->tuning.nf_stage, N, R);
   kp.own_chunk = own_chunk(N, R, kp.n_rows);
   {  // neighbouring sectors' centre lines are one sector width, 2 atan(tan_half), apart
     const double w = 2.0 * std::atan((double)geo->tan_half_angle);
@@ -581,7 +585,7 @@ int run_batch(tpc_ctx* ctx, const tpc_event* evs, int E, const tpc_geometry* geo
   kp.construct_blocks = ctx->tuning.construct_blocks;
   kp.construct_schedule = ctx->tuning.construct_schedule;
   kp.construct_lanes = lanes_per_wave(ctx->tuning.construct_lanes, N);
-  kp.nf_dense = dense_rows(N, R);
+  kp.nf_dense = nf_stage_of(ctx->tuning.nf_stage, N, R);
   kp.own_chunk = own_chunk(N, R, kp.n_rows);
   DevEvent dev = make_devevent(&bev);
   if (use_graph) {
@@ -770,6 +774,7 @@ void tpc_tuning_default(tpc_tuning* t) {
   t->bin_occupancy = 1.0f;
   t->construct_schedule = 0;
   t->construct_lanes = 0;
+  t->nf_stage = 0;
 }
 
 int tpc_ctx_set_tuning(tpc_ctx* ctx, const tpc_tuning* t) {
@@ -782,6 +787,8 @@ int tpc_ctx_set_tuning(tpc_ctx* ctx, const tpc_tuning* t) {
     return fail(TPC_ERR_INVALID_ARG, "construct_schedule must be 0 or 1");
   if (t->construct_lanes < 0 || t->construct_lanes > 64)
     return fail(TPC_ERR_INVALID_ARG, "construct_lanes outside [0, 64]");
+  if (t->nf_stage < 0 || t->nf_stage > 2)
+    return fail(TPC_ERR_INVALID_ARG, "nf_stage must be 0, 1 or 2");
   ctx->tuning = *t;
   return TPC_OK;
 }

@@ -1,7 +1,8 @@
 """Autotuner of the batched path: picks the constructor schedule, its lanes
 per wave and the search-grid bin occupancy that track a sample batch
-fastest, and caches the choice per GPU and multiplicity bucket.  Every
-candidate gives bitwise the same tracks, so tuning only ever changes speed.
+fastest, then the neighbours finder's LDS stage for that setting, and caches
+the choice per GPU and multiplicity bucket.  Every candidate gives bitwise
+the same tracks, so tuning only ever changes speed.
 """
 from __future__ import annotations
 
@@ -13,6 +14,7 @@ import time
 CANDIDATES = ([dict(construct_schedule=0, construct_blocks=0, construct_lanes=a, bin_occupancy=o)
                for a in (0, 16, 32, 64) for o in (1.0, 2.0)] +
               [dict(construct_schedule=1, construct_blocks=0, bin_occupancy=1.0)])
+NF_STAGES = (1, 2)   # tried with the best of CANDIDATES (0, automatic, is part of it)
 
 
 def bucket(evs) -> int:
@@ -48,7 +50,8 @@ def autotune(tracker, evs, geo, bz, params=None, reps: int = 2, candidates=None,
             tracker.set_tuning(use_graph=1, **hit["best"])
             return hit
     results = []
-    for cand in (candidates or CANDIDATES):
+
+    def timed(cand):
         tracker.set_tuning(use_graph=1, **cand)
         tracker.track_batch(evs, geo, bz, params)          # capture + warm
         torch.cuda.synchronize()
@@ -60,6 +63,13 @@ def autotune(tracker, evs, geo, bz, params=None, reps: int = 2, candidates=None,
         results.append(dict(setting=cand, seconds=best))
         if log:
             log(f"tune {cand}: {best * 1e3:.2f} ms")
+
+    for cand in (candidates or CANDIDATES):
+        timed(cand)
+    if candidates is None:   # then the neighbours finder's stage for the best setting
+        base = min(results, key=lambda r: r["seconds"])["setting"]
+        for stage in NF_STAGES:
+            timed(dict(base, nf_stage=stage))
     win = min(results, key=lambda r: r["seconds"])
     tracker.set_tuning(use_graph=1, **win["setting"])
     rec = dict(best=win["setting"], seconds=win["seconds"], tried=results,
