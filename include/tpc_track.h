@@ -18,7 +18,9 @@
  *  - Clusters of an event are one structure-of-arrays, sorted by
  *    (sector slot, row); the order inside a row is free.  Cluster indices in
  *    every output are event-global int32 indices into that array.
- *  - The device path computes in FP32.
+ *  - The device path computes in FP32, except the Kalman filter's covariance
+ *    and gain, which are FP64 (a diffuse q/pT prior makes the FP32 covariance
+ *    update lose precision on low-pT tracks).
  *
  * Pointers: every array inside tpc_event and tpc_tracks is DEVICE memory on
  * the context's GPU; tpc_geometry.row_x, tpc_params and the size fields
