@@ -860,8 +860,9 @@ __device__ __forceinline__ int search_row(const Scratch& sc, const RowGrid& g, i
   float best = INFINITY;
   int bid = -1;
   // the best is the smallest (chi^2, id) inside the gate, whatever the order
-  // of the candidates: two bin rows' ranges are loaded together and the
-  // records two at a time, so that one wait covers two loads
+  // of the candidates: two bin rows' ranges are loaded together and their
+  // records eight at a time, so that one wait covers a whole window in most
+  // searches
   auto consider = [&](const GridRec& v) {
     const float ry = v.y - s.y, rz = v.z - s.z;
     const float chi2 = (ry * ry * S11 - 2.f * ry * rz * S01 + rz * rz * S00) * idet;
@@ -878,12 +879,16 @@ __device__ __forceinline__ int search_row(const Scratch& sc, const RowGrid& g, i
     const int b0 = sc.bins[ib + iy0], b1 = sc.bins[ib + iy1 + 1];
     const int na = a1 - a0, n = na + (iz + 1 <= iz1 ? b1 - b0 : 0);
     wk.cands += n;
-    for (int k = 0; k < n; k += 2) {
-      const int k2 = min(k + 1, n - 1);
-      const GridRec v = sc.g_rec[rb + (k < na ? a0 + k : b0 + (k - na))];
-      const GridRec w = sc.g_rec[rb + (k2 < na ? a0 + k2 : b0 + (k2 - na))];
-      consider(v);
-      if (k + 1 < n) consider(w);
+    for (int k = 0; k < n; k += 8) {
+      GridRec v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int kk = min(k + u, n - 1);
+        v[u] = sc.g_rec[rb + (kk < na ? a0 + kk : b0 + (kk - na))];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k + u < n) consider(v[u]);
     }
   }
   return bid;
