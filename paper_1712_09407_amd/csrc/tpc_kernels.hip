@@ -56,7 +56,6 @@ constexpr int kNfCapSmall = 512, kNfListSmall = 12;
 constexpr int kNfCapLarge = 1024, kNfListLarge = 32;
 constexpr int kScanBlock = 1024;
 constexpr int kTlBlock = 64;     // one wave per block for per-tracklet kernels
-constexpr int kLdsHitLanes = 24; // the lane constructor keeps hits in LDS up to this many lanes
 
 // ------------------------------------------------------------------ helpers
 
@@ -2858,10 +2857,21 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
   } else {
     const int A = min(max(kp.construct_lanes, 1), kTlBlock);
     const int nb = xcd_grid(kp.construct_blocks > 0 ? kp.construct_blocks : tl_blocks(sc.cap_tl, A));
-    // the lanes' row slots in LDS while their LDS still leaves about ten
-    // workgroups per CU; with more lanes per wave the hits array holds them
+    // the lanes' row slots in LDS when the whole grid stays resident with
+    // them (their LDS must not make workgroups wait for others to finish);
+    // otherwise the hits array holds them
     const size_t lds = sizeof(int32_t) * kHitStride * A;
-    if (A <= kLdsHitLanes) {
+    int per_cu = 0;
+    const hipError_t oe =
+        sc.ends ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &per_cu, k_construct_lanes<true, true>, kTlBlock, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &per_cu, k_construct_lanes<false, true>, kTlBlock, lds);
+    if (oe != hipSuccess) {
+      (void)hipGetLastError();
+      per_cu = 0;
+    }
+    if ((int64_t)nb <= (int64_t)per_cu * kp.n_cu) {
       if (sc.ends)
         hipLaunchKernelGGL((k_construct_lanes<true, true>), dim3(nb), dim3(kTlBlock), lds, st, ev,
                            kp, sc);

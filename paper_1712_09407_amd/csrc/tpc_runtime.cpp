@@ -34,6 +34,7 @@ int hip_fail(hipError_t e, const char* what) {
 
 struct tpc_ctx {
   int device = 0;
+  int n_cu = 0;             // compute units of the device
   size_t budget = 0;        // 0 = unlimited
   void* arena = nullptr;
   size_t arena_bytes = 0;
@@ -123,10 +124,11 @@ int validate(const tpc_event* ev, const tpc_geometry* geo, const tpc_params* p) 
 // number of tracklets (one per 36 clusters), as a power of two in [8, 64].
 static int32_t lanes_per_wave(int32_t requested, int64_t n_clusters) {
   if (requested > 0) return requested;
-  // about one tracklet per 36 clusters; measured best: 24 lanes for a
-  // central event (1.3 M clusters), 48 to 56 for 4.6 M, 8 for small events
+  // about one tracklet per 36 clusters; measured best: 20 lanes at 0.33 M
+  // clusters, 32 to 40 for a central event (1.3 M), 56 to 64 for 4.6 M, 8
+  // for small events
   const double waves = (double)(n_clusters / 36 + 1) / 2048.0;
-  const int32_t a = 4 * (int32_t)std::lround(1.5 * std::sqrt(waves));
+  const int32_t a = 4 * (int32_t)std::lround(2.1 * std::sqrt(waves) + 0.5);
   return std::min(64, std::max(8, a));
 }
 
@@ -299,6 +301,7 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
   kp.construct_blocks = ctx->tuning.construct_blocks;
   kp.construct_schedule = ctx->tuning.construct_schedule;
   kp.construct_lanes = lanes_per_wave(ctx->tuning.construct_lanes, N);
+  kp.n_cu = ctx->n_cu;
   kp.nf_dense = nf_stage_of(ctx->tuning.nf_stage, N, R);
   kp.own_chunk = own_chunk(N, R, kp.n_rows);
   {  // neighbouring sectors' centre lines are one sector width, 2 atan(tan_half), apart
@@ -585,6 +588,7 @@ int run_batch(tpc_ctx* ctx, const tpc_event* evs, int E, const tpc_geometry* geo
   kp.construct_blocks = ctx->tuning.construct_blocks;
   kp.construct_schedule = ctx->tuning.construct_schedule;
   kp.construct_lanes = lanes_per_wave(ctx->tuning.construct_lanes, N);
+  kp.n_cu = ctx->n_cu;
   kp.nf_dense = nf_stage_of(ctx->tuning.nf_stage, N, R);
   kp.own_chunk = own_chunk(N, R, kp.n_rows);
   DevEvent dev = make_devevent(&bev);
@@ -746,6 +750,9 @@ int tpc_ctx_create(int device, size_t hbm_budget_bytes, tpc_ctx** out) {
   if (!c) return fail(TPC_ERR_OOM, "host allocation failed");
   c->device = device;
   c->budget = hbm_budget_bytes;
+  if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) !=
+      hipSuccess)
+    c->n_cu = 0;
   tpc_tuning_default(&c->tuning);
   e = hipHostMalloc((void**)&c->h_counters, sizeof(int32_t) * 3 * C_COUNT, hipHostMallocDefault);
   if (e != hipSuccess) {

@@ -265,9 +265,10 @@ def test_constructor_schedules_agree_bitwise(tracker, geo, name, seed):
     """The row-synchronous and the lane-per-tracklet constructor run the same
     lane steps: every output bit must agree (dense rows exercise the
     global-memory search of the row-synchronous schedule).  The lane
-    constructor runs twice: with its default lanes per wave (at most 24 on
-    these events), which keep their hit rows in LDS, and with 64, which keep
-    them in the hits array."""
+    constructor runs with its default lanes per wave and with 64; it keeps its
+    hit rows in LDS when its whole grid stays resident with them (the central
+    and smaller events here) and in the hits array otherwise (the stress
+    event), so both storages are compared with the row-synchronous one."""
     if name == "dense":
         e = synth.make_event(synth.EventConfig(n_tracks=150, sectors=(0,), phi_range_deg=(0, 20),
                                                ignore_membrane=True, noise_frac=20.0), seed)
