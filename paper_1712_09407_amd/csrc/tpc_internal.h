@@ -32,6 +32,7 @@ struct KParams {
   int32_t construct_lanes;     // lane schedule: lanes of a wave that take tracklets
   int32_t own_chunk;           // selection: clusters per LDS chunk of a sector (speed only)
   int32_t n_cu;                // compute units of the device (launch sizing only)
+  int32_t expect_tl;           // tracklets expected (launch sizing only)
   float rot_c, rot_s;          // cos, sin of one sector width (global tracking)
   float rot_tab[18][2];        // cos, sin of k sector widths, k = -9 .. 8 at [k + 9]
   float merge_chi2;            // track merger: chi^2(5) cut of a join

@@ -2857,9 +2857,10 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
   } else {
     const int A = min(max(kp.construct_lanes, 1), kTlBlock);
     const int nb = xcd_grid(kp.construct_blocks > 0 ? kp.construct_blocks : tl_blocks(sc.cap_tl, A));
-    // the lanes' row slots in LDS when the whole grid stays resident with
-    // them (their LDS must not make workgroups wait for others to finish);
-    // otherwise the hits array holds them
+    // the lanes' row slots in LDS when every wave that will get tracklets
+    // (as many as the last call found per cluster) stays resident with them:
+    // their LDS must not make waves wait for others to finish (waves beyond
+    // the tracklets end at once); otherwise the hits array holds them
     const size_t lds = sizeof(int32_t) * kHitStride * A;
     int per_cu = 0;
     const hipError_t oe =
@@ -2871,7 +2872,8 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
       (void)hipGetLastError();
       per_cu = 0;
     }
-    if ((int64_t)nb <= (int64_t)per_cu * kp.n_cu) {
+    const int64_t busy = ((int64_t)kp.expect_tl + A - 1) / A + 8;
+    if (busy <= (int64_t)per_cu * kp.n_cu) {
       if (sc.ends)
         hipLaunchKernelGGL((k_construct_lanes<true, true>), dim3(nb), dim3(kTlBlock), lds, st, ev,
                            kp, sc);

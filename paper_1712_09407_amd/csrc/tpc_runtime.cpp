@@ -44,6 +44,7 @@ struct tpc_ctx {
   // the merger's joins run beside the prolongations on a second stream
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  double seen_ratio = 0.0;     // tracklets per cluster of the last call (launch sizing)
   double learned_ratio = 0.0;  // tracklets per cluster learned from overflows: the
                                // reservation scales with the event (or batch) size
   tpc::KernelTimer timer;   // HIP events around selected kernels
@@ -213,6 +214,15 @@ int64_t default_tracklets(const tpc_ctx* ctx, int64_t N, const tpc_params* p) {
   return l > t ? l : t;
 }
 
+// Tracklets this call will probably find: as many per cluster as the last
+// call found, else one per 36 clusters (a central event).  Sizes launches
+// only; the reservation is default_tracklets.
+int32_t expected_tracklets(const tpc_ctx* ctx, int64_t N) {
+  const double r = ctx->seen_ratio > 0.0 ? ctx->seen_ratio : 1.0 / 36.0;
+  const double t = std::ceil(r * (double)N) + 1.0;
+  return t > 2e9 ? 2000000000 : (int32_t)t;
+}
+
 // After an overflow: the reservation for this call and the ratio learned from it.
 int64_t grow_tracklets(tpc_ctx* ctx, int64_t need, int64_t N) {
   const int64_t T = need + need / 8 + 64;
@@ -302,6 +312,7 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
   kp.construct_schedule = ctx->tuning.construct_schedule;
   kp.construct_lanes = lanes_per_wave(ctx->tuning.construct_lanes, N);
   kp.n_cu = ctx->n_cu;
+  kp.expect_tl = expected_tracklets(ctx, N);
   kp.nf_dense = nf_stage_of(ctx->tuning.nf_stage, N, R);
   kp.own_chunk = own_chunk(N, R, kp.n_rows);
   {  // neighbouring sectors' centre lines are one sector width, 2 atan(tan_half), apart
@@ -424,6 +435,7 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
     }
     ctx->work[0] += 1;
     ctx->work[1] += c[C_SEEDS];
+    if (N > 0 && upto >= STAGE_SEEDS) ctx->seen_ratio = (double)c[C_SEEDS] / (double)N;
     ctx->work[2] += (uint32_t)c[C_STEPS];
     ctx->work[3] += (uint32_t)c[C_UPDATES];
     ctx->work[4] += (uint32_t)c[C_CANDS];
@@ -589,6 +601,7 @@ int run_batch(tpc_ctx* ctx, const tpc_event* evs, int E, const tpc_geometry* geo
   kp.construct_schedule = ctx->tuning.construct_schedule;
   kp.construct_lanes = lanes_per_wave(ctx->tuning.construct_lanes, N);
   kp.n_cu = ctx->n_cu;
+  kp.expect_tl = expected_tracklets(ctx, N);
   kp.nf_dense = nf_stage_of(ctx->tuning.nf_stage, N, R);
   kp.own_chunk = own_chunk(N, R, kp.n_rows);
   DevEvent dev = make_devevent(&bev);
@@ -687,6 +700,7 @@ int run_batch(tpc_ctx* ctx, const tpc_event* evs, int E, const tpc_geometry* geo
     }
     ctx->work[0] += E;
     ctx->work[1] += c[C_SEEDS];
+    if (N > 0) ctx->seen_ratio = (double)c[C_SEEDS] / (double)N;
     ctx->work[2] += (uint32_t)c[C_STEPS];
     ctx->work[3] += (uint32_t)c[C_UPDATES];
     ctx->work[4] += (uint32_t)c[C_CANDS];
