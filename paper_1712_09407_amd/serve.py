@@ -60,4 +60,4 @@ def run(server, events, rate_hz: float, n_events: int, seed: int = 4, keep=None)
                 mean_ms=round(float(lat.mean() * 1e3), 3),
                 offered_events_per_s=round((n_events - 1) / span, 1),
                 sustained_events_per_s=round(n_events / (t_last[0] - arrive[0]), 1),
-                busy_retries=busy_retries, stats=server.stats()), fetched
+                busy_retries=busy_retries, stats=server.stats(), lat_ms=lat * 1e3), fetched
