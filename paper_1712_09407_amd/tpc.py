@@ -436,11 +436,12 @@ class Tracker:
     def reset_stats(self):
         _check(lib.tpc_ctx_reset_stats(self._h))
 
-    def track_batch(self, evs, geo: Geometry, bz: float, params: Params = None, outs=None,
-                    stream=None):
-        """Track several device events in one launch sequence.  Returns one
-        dict per event, like track_event.  `outs` may hold preallocated
-        outputs (one dict per event)."""
+    @staticmethod
+    def batch_args(evs, outs=None):
+        """The arguments of tpc_track_batch for the device events `evs`:
+        (events, E, tracks, outs, sizes), with outputs allocated here unless
+        `outs` holds them (one dict per event).  Built once, they serve
+        repeated track_batch_raw calls; sizes[i] receives event i's counts."""
         import torch
         E = len(evs)
         if outs is None:
@@ -461,6 +462,14 @@ class Tracker:
                                     o["cluster_track"].data_ptr())
                              for o, (a, b) in zip(outs, sizes)])
         es = (Event * E)(*[ev.cstruct() for ev in evs])
+        return es, E, trs, outs, sizes
+
+    def track_batch(self, evs, geo: Geometry, bz: float, params: Params = None, outs=None,
+                    stream=None):
+        """Track several device events in one launch sequence.  Returns one
+        dict per event, like track_event.  `outs` may hold preallocated
+        outputs (one dict per event)."""
+        es, E, trs, outs, sizes = self.batch_args(evs, outs)
         rc = lib.tpc_track_batch(self._h, es, E, C.byref(geo), float(bz),
                                  C.byref(params or default_params()), trs, _stream_handle(stream))
         _check(rc)
