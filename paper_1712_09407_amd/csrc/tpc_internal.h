@@ -89,6 +89,7 @@ struct Scratch {
   uint8_t* start;          // [N]
   unsigned long long* own; // [N] owner key per cluster
   int32_t* row_cnt;        // [R + 1] seeds per row, then exclusive offsets
+  int32_t* row_part;       // [R / kRowSpan + 1] sums of spans of row_cnt
   int32_t cap_tl;          // tracklet reservation T
   int32_t* seeds;          // [T]
   int32_t* seed_rs;        // [T]

@@ -15,7 +15,8 @@
 //                 straight neighbour pair of every cluster of row k
 //   k_evo         per row slot: keep reciprocal links, flag chain starts of
 //                 at least min_seed_len clusters, count them per row
-//   k_scan_rows   one block: exclusive scan of the per-row seed counts
+//   k_rows_reduce, exclusive scan of the per-row seed counts (spans of row
+//   k_scan_rows   slots summed, then scanned from the spans before them)
 //   k_seed_write  per row slot: ordered compaction of chain starts (the
 //                 tracklet id is the start cluster's index, so seeds come out
 //                 sorted)
@@ -55,6 +56,7 @@ constexpr int kMaxBins = 4096;   // bins per row (LDS counting sort)
 constexpr int kNfCapSmall = 512, kNfListSmall = 12;
 constexpr int kNfCapLarge = 1024, kNfListLarge = 32;
 constexpr int kScanBlock = 1024;
+constexpr int kRowSpan = 8 * kScanBlock;  // row slots per workgroup of the row scan
 constexpr int kTlBlock = 64;     // one wave per block for per-tracklet kernels
 
 // ------------------------------------------------------------------ helpers
@@ -787,23 +789,69 @@ __global__ __launch_bounds__(kGridBlock) void k_evo(DevEvent ev, KParams kp, Scr
 
 // ------------------------------------------------------------------ scans
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_rows(int R, Scratch sc) {
+// The per-row seed counts are scanned in spans of kRowSpan row slots, one
+// workgroup each (a batch of many events has hundreds of thousands of row
+// slots): k_rows_reduce sums every span, k_scan_rows scans each span from
+// the sum of the spans before it.  A span goes through LDS, so that global
+// reads and writes are coalesced while every thread scans eight consecutive
+// slots.
+__global__ __launch_bounds__(kScanBlock) void k_rows_reduce(int R, Scratch sc) {
   __shared__ int s_w[kScanBlock / 64];
   if (event_bad(sc.counters)) return;
-  const int tid = threadIdx.x;
-  int carry = 0;
-  for (int base = 0; base < R; base += kScanBlock) {
-    const int i = base + tid;
-    const int v = i < R ? sc.row_cnt[i] : 0;
-    int tot;
-    const int ex = block_excl_scan<kScanBlock>(v, s_w, &tot);
-    if (i < R) sc.row_cnt[i] = carry + ex;
-    carry += tot;
+  const int base = blockIdx.x * kRowSpan;
+  int sum = 0;
+#pragma unroll
+  for (int q = 0; q < kRowSpan / kScanBlock; ++q) {
+    const int i = base + q * kScanBlock + (int)threadIdx.x;
+    sum += i < R ? sc.row_cnt[i] : 0;
   }
-  if (tid == 0) {
-    sc.row_cnt[R] = carry;
-    sc.counters[C_SEEDS] = carry;
-    if (carry > sc.cap_tl) atomicOr(&sc.counters[C_ERR], E_TL_OVERFLOW);
+  int tot;
+  block_excl_scan<kScanBlock>(sum, s_w, &tot);
+  if (threadIdx.x == 0) sc.row_part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_rows(int R, Scratch sc) {
+  __shared__ int s_w[kScanBlock / 64];
+  __shared__ int s_v[kRowSpan + kRowSpan / 32];  // one pad word per 32
+  if (event_bad(sc.counters)) return;
+  constexpr int kPer = kRowSpan / kScanBlock;
+  const int tid = threadIdx.x, base = blockIdx.x * kRowSpan;
+  auto at = [](int k) { return k + (k >> 5); };
+  // offset of this span: the sums of the spans before it
+  int pre = 0;
+  for (int j = tid; j < (int)blockIdx.x; j += kScanBlock) pre += sc.row_part[j];
+  int off;
+  block_excl_scan<kScanBlock>(pre, s_w, &off);
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int k = q * kScanBlock + tid;
+    s_v[at(k)] = base + k < R ? sc.row_cnt[base + k] : 0;
+  }
+  __syncthreads();
+  int v[kPer], sum = 0;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    v[q] = s_v[at(tid * kPer + q)];
+    sum += v[q];
+  }
+  int tot;
+  int run = off + block_excl_scan<kScanBlock>(sum, s_w, &tot);
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    s_v[at(tid * kPer + q)] = run;
+    run += v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int k = q * kScanBlock + tid;
+    if (base + k < R) sc.row_cnt[base + k] = s_v[at(k)];
+  }
+  if (blockIdx.x == gridDim.x - 1 && tid == 0) {
+    const int all = off + tot;
+    sc.row_cnt[R] = all;
+    sc.counters[C_SEEDS] = all;
+    if (all > sc.cap_tl) atomicOr(&sc.counters[C_ERR], E_TL_OVERFLOW);
   }
 }
 
@@ -2682,6 +2730,7 @@ size_t scratch_bytes(int64_t N, int64_t R, int64_t T) {
   b += align_up(sizeof(int32_t) * N) * 5;  // up, dn, up2, dn2 + start (bytes, padded)
   b += align_up(sizeof(unsigned long long) * N);
   b += align_up(sizeof(int32_t) * (R + 1));
+  b += align_up(sizeof(int32_t) * (R / kRowSpan + 1));
   b += align_up(sizeof(int32_t) * T) * 2;
   b += align_up(sizeof(int32_t) * T * kHitStride);
   b += align_up(sizeof(float2) * T * kHitStride);
@@ -2712,6 +2761,7 @@ void scratch_carve(void* base, int64_t N, int64_t R, int64_t T, Scratch* sc) {
   sc->start = (uint8_t*)take(sizeof(int32_t) * N);
   sc->own = (unsigned long long*)take(sizeof(unsigned long long) * N);
   sc->row_cnt = (int32_t*)take(sizeof(int32_t) * (R + 1));
+  sc->row_part = (int32_t*)take(sizeof(int32_t) * (R / kRowSpan + 1));
   sc->cap_tl = (int32_t)T;
   sc->seeds = (int32_t*)take(sizeof(int32_t) * T);
   sc->seed_rs = (int32_t*)take(sizeof(int32_t) * T);
@@ -2840,7 +2890,11 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
   post(K_EVO);
   if (upto <= STAGE_LINKS) return hipGetLastError();
   pre(K_SCAN_ROWS);
-  hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(kScanBlock), 0, st, R, sc);
+  {
+    const int spans = max(1, (R + kRowSpan - 1) / kRowSpan);
+    if (spans > 1) hipLaunchKernelGGL(k_rows_reduce, dim3(spans), dim3(kScanBlock), 0, st, R, sc);
+    hipLaunchKernelGGL(k_scan_rows, dim3(spans), dim3(kScanBlock), 0, st, R, sc);
+  }
   post(K_SCAN_ROWS);
   pre(K_SEED_WRITE);
   hipLaunchKernelGGL(k_seed_write, dim3(R), dim3(kGridBlock), 0, st, ev, sc);
