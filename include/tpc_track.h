@@ -321,9 +321,15 @@ typedef struct {
   int32_t nf_stage;           /* neighbours finder's LDS stage: 1 = rows of up to 512
                                  clusters, 12 window candidates per lane and row
                                  (five workgroups per CU); 2 = rows of up to 1024
-                                 clusters, 32 candidates (three per CU); larger rows
-                                 take the global-memory search; 0 = automatic (2 when
-                                 the event averages more than 320 clusters per row) */
+                                 clusters, 32 candidates (three per CU); 3 = rows of
+                                 up to 256 clusters, one wave per row slot (fourteen
+                                 per CU), and one wave per row slot for the grid,
+                                 evolution and seed kernels too; larger rows take the
+                                 global-memory search;
+                                 0 = automatic (2 when the event or batch averages
+                                 more than 320 clusters per row, 3 when a batch of
+                                 32768 row slots or more averages fewer than 128,
+                                 else 1) */
 } tpc_tuning;
 void tpc_tuning_default(tpc_tuning* t);
 int tpc_ctx_set_tuning(tpc_ctx* ctx, const tpc_tuning* t);

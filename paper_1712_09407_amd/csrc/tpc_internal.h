@@ -28,7 +28,9 @@ struct KParams {
   float bin_occupancy;     // target clusters per search-grid bin
   int32_t construct_blocks;  // constructor grid (0 = sized from the reservation)
   int32_t construct_schedule;  // 0 = one lane per tracklet, 1 = row-synchronous
-  int32_t nf_dense;            // neighbours finder for dense rows (larger LDS stage)
+  int32_t nf_stage;            // neighbours finder's LDS stage: 1 = 512 clusters, four waves;
+                               // 2 = 1024 clusters; 3 = 256 clusters, one wave per row slot
+  int32_t row_wave;            // grid, evolution and seed kernels: one wave per row slot
   int32_t construct_lanes;     // lane schedule: lanes of a wave that take tracklets
   int32_t own_chunk;           // selection: clusters per LDS chunk of a sector (speed only)
   int32_t n_cu;                // compute units of the device (launch sizing only)

@@ -47,14 +47,18 @@ namespace tpc {
 
 constexpr int kGridBlock = 256;
 constexpr int kMaxBins = 4096;   // bins per row (LDS counting sort)
+constexpr int kGridWaveBins = 1024;  // LDS bins of the one-wave form of k_grid
 // k_nf stages neighbour rows of up to CAP clusters in LDS and keeps up to
-// LIST window candidates per row and lane: (512, 12) with 16-bit entries for
-// rows of central density (31 KB of LDS, five workgroups per CU), (1024, 32)
-// with 8-bit entries for dense events (49 KB, three workgroups per CU).  A
-// lane's longer list is searched by its whole wave, a longer row by the
-// global-memory search; every configuration gives the same links.
+// LIST window candidates per row and lane: (512, 12) with 16-bit entries and
+// four waves for rows of central density (31 KB of LDS, five workgroups per
+// CU), (1024, 32) with 8-bit entries for dense events (49 KB, three
+// workgroups per CU), and (256, 12) with one wave for sparse rows (11 KB,
+// fourteen workgroups per CU: many small events batched).  A lane's longer
+// list is searched by its whole wave, a longer row by the global-memory
+// search; every configuration gives the same links.
 constexpr int kNfCapSmall = 512, kNfListSmall = 12;
 constexpr int kNfCapLarge = 1024, kNfListLarge = 32;
+constexpr int kNfCapWave = 256;
 constexpr int kScanBlock = 1024;
 constexpr int kRowSpan = 8 * kScanBlock;  // row slots per workgroup of the row scan
 constexpr int kTlBlock = 64;     // one wave per block for per-tracklet kernels
@@ -131,11 +135,70 @@ __global__ void k_zero(int32_t* counters) {
 
 // ------------------------------------------------------------------ k_grid
 
-__global__ __launch_bounds__(kGridBlock) void k_grid(DevEvent ev, KParams kp, Scratch sc,
-                                                     int32_t* cluster_track) {
-  __shared__ int s_cnt[kMaxBins + 1];
-  __shared__ float s_red[2][kGridBlock / 64];
-  __shared__ int s_w[kGridBlock / 64];
+// Counting sort of a row's clusters into its bins, counts in cnt[0..nb):
+// LDS, or for a row with more bins than the LDS array holds global memory,
+// read past the CU's cache and fenced before each barrier so that every
+// lane sees the others' atomics.
+template <int BS, bool G>
+__device__ __forceinline__ void grid_sort(const DevEvent& ev, const Scratch& sc, const RowGrid& g,
+                                          int b, int e, int nb, int* cnt, int* s_w) {
+  const int tid = threadIdx.x, ny = g.ny;
+  auto ld = [](int* p) {
+    if constexpr (G) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+  };
+  auto sync = []() {
+    if constexpr (G) __threadfence();
+    __syncthreads();
+  };
+  for (int k = tid; k < nb; k += BS) cnt[k] = 0;
+  sync();
+  for (int i = b + tid; i < e; i += BS) {
+    float y = ev.y[i], z = ev.z[i];
+    if (!isfinite(y) || !isfinite(z)) continue;
+    atomicAdd(&cnt[bin_z(g, z) * ny + bin_y(g, y)], 1);
+  }
+  sync();
+  int tot;
+  {  // exclusive scan of cnt[0..nb) in place, each thread a contiguous piece
+    const int per = (nb + BS - 1) / BS;
+    const int lo = tid * per, hi = min(lo + per, nb);
+    int sum = 0;
+    for (int k = lo; k < hi; ++k) sum += ld(&cnt[k]);
+    int off = block_excl_scan<BS>(sum, s_w, &tot);
+    for (int k = lo; k < hi; ++k) {
+      int v = ld(&cnt[k]);
+      cnt[k] = off;
+      off += v;
+    }
+    sync();
+  }
+  for (int k = tid; k < nb; k += BS) sc.bins[g.bin_base + k] = ld(&cnt[k]);
+  if (tid == 0) sc.bins[g.bin_base + nb] = tot;
+  sync();
+  for (int i = b + tid; i < e; i += BS) {
+    float y = ev.y[i], z = ev.z[i];
+    if (!isfinite(y) || !isfinite(z)) continue;
+    int pos = atomicAdd(&cnt[bin_z(g, z) * ny + bin_y(g, y)], 1);
+    GridRec rec;
+    rec.y = y;
+    rec.z = z;
+    rec.id = i;
+    rec.pad = 0;
+    sc.g_rec[b + pos] = rec;
+  }
+}
+
+// One workgroup of BS threads per row slot: the row's z range, its grid and
+// the counting sort.  With BS = 64 (many sparse rows) the LDS counts hold
+// NB bins; a row with more takes its counts in global memory, in the
+// cluster links of its own clusters (up[b..e), written later by k_nf).
+template <int BS, int NB>
+__global__ __launch_bounds__(BS) void k_grid(DevEvent ev, KParams kp, Scratch sc,
+                                             int32_t* cluster_track) {
+  __shared__ int s_cnt[NB + 1];
+  __shared__ float s_red[2][BS / 64];
+  __shared__ int s_w[BS / 64];
   const int rs = blockIdx.x;
   const int R = ev.n_sectors * kp.n_rows;
   const int N = ev.n_dev ? *ev.n_dev : ev.n_clusters;
@@ -151,7 +214,7 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(DevEvent ev, KParams kp, Sc
   // z range of the row (min/max), non-finite values flagged
   float zmin = INFINITY, zmax = -INFINITY;
   int nonfin = 0;
-  for (int i = b + tid; i < e; i += kGridBlock) {
+  for (int i = b + tid; i < e; i += BS) {
     float y = ev.y[i], z = ev.z[i];
     if (!isfinite(y) || !isfinite(z)) {
       ++nonfin;
@@ -176,7 +239,7 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(DevEvent ev, KParams kp, Sc
   __syncthreads();
   zmin = s_red[0][0];
   zmax = s_red[1][0];
-  for (int i = 1; i < kGridBlock / 64; ++i) {
+  for (int i = 1; i < BS / 64; ++i) {
     zmin = fminf(zmin, s_red[0][i]);
     zmax = fmaxf(zmax, s_red[1][i]);
   }
@@ -204,44 +267,10 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(DevEvent ev, KParams kp, Sc
   const int nb = ny * nz;
   if (tid == 0) sc.grid[rs] = g;
   if (n == 0) return;  // searches test g.n first; an empty row owns no bins
-  // counting sort into the bins
-  for (int k = tid; k <= nb; k += kGridBlock) s_cnt[k] = 0;
-  __syncthreads();
-  for (int i = b + tid; i < e; i += kGridBlock) {
-    float y = ev.y[i], z = ev.z[i];
-    if (!isfinite(y) || !isfinite(z)) continue;
-    atomicAdd(&s_cnt[bin_z(g, z) * ny + bin_y(g, y)], 1);
-  }
-  __syncthreads();
-  {  // exclusive scan of s_cnt[0..nb) in place, each thread a contiguous piece
-    const int per = (nb + kGridBlock - 1) / kGridBlock;
-    const int lo = tid * per, hi = min(lo + per, nb);
-    int sum = 0;
-    for (int k = lo; k < hi; ++k) sum += s_cnt[k];
-    int tot;
-    int off = block_excl_scan<kGridBlock>(sum, s_w, &tot);
-    for (int k = lo; k < hi; ++k) {
-      int v = s_cnt[k];
-      s_cnt[k] = off;
-      off += v;
-    }
-    __syncthreads();
-    if (tid == 0) s_cnt[nb] = tot;
-    __syncthreads();
-  }
-  for (int k = tid; k <= nb; k += kGridBlock) sc.bins[g.bin_base + k] = s_cnt[k];
-  __syncthreads();
-  for (int i = b + tid; i < e; i += kGridBlock) {
-    float y = ev.y[i], z = ev.z[i];
-    if (!isfinite(y) || !isfinite(z)) continue;
-    int pos = atomicAdd(&s_cnt[bin_z(g, z) * ny + bin_y(g, y)], 1);
-    GridRec rec;
-    rec.y = y;
-    rec.z = z;
-    rec.id = i;
-    rec.pad = 0;
-    sc.g_rec[b + pos] = rec;
-  }
+  if (nb <= NB)
+    grid_sort<BS, false>(ev, sc, g, b, e, nb, s_cnt, s_w);
+  else
+    grid_sort<BS, true>(ev, sc, g, b, e, nb, sc.up + b, s_w);
 }
 
 // ------------------------------------------------------------------ k_nf
@@ -351,9 +380,9 @@ struct NfEntry<uint8_t> {
 // [LIST][blockDim] LDS array (NfEntry; *first = the first candidate's
 // position).  Returns the count, or LIST + 1 if the list cannot hold them
 // all.
-template <int LIST, class E>
+template <int LIST, class E, int BS>
 __device__ __forceinline__ int nf_collect(const RowView& V, float yc, float zc, float wy, float wz,
-                                          E (*list)[kGridBlock], int lane, int* first) {
+                                          E (*list)[BS], int lane, int* first) {
   const float m = 1e-3f;
   const int y0 = bin_y(V.g, yc - wy - m), y1 = bin_y(V.g, yc + wy + m);
   const int z0 = bin_z(V.g, zc - wz - m), z1 = bin_z(V.g, zc + wz + m);
@@ -415,8 +444,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Entry e of a wave's shared list: the 16-bit byte offset of a record in
 // the stage, in the wave's columns of a list, 32 sizeof(E) entries a row.
-template <class E>
-__device__ __forceinline__ uint16_t& wave_slot(E (*list)[kGridBlock], int col0, int e) {
+template <class E, int BS>
+__device__ __forceinline__ uint16_t& wave_slot(E (*list)[BS], int col0, int e) {
   constexpr int per = 32 * sizeof(E);
   return *reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(&list[e / per][col0]) +
                                       2 * (e % per));
@@ -426,9 +455,9 @@ __device__ __forceinline__ uint16_t& wave_slot(E (*list)[kGridBlock], int col0, 
 // every lane), listed by the whole wave into its columns of list (wave_slot),
 // in bin order.  Returns the count (the list is incomplete beyond cap
 // entries).
-template <class E>
+template <class E, int BS>
 __device__ __forceinline__ int nf_wave_collect(const RowView& V, float yc, float zc, float wy,
-                                               float wz, E (*list)[kGridBlock], int cap,
+                                               float wz, E (*list)[BS], int cap,
                                                int col0, int lane) {
   const float m = 1e-3f;
   const int y0 = bin_y(V.g, yc - wy - m), y1 = bin_y(V.g, yc + wy + m);
@@ -452,10 +481,10 @@ __device__ __forceinline__ int nf_wave_collect(const RowView& V, float yc, float
 // cluster at c, searched by the whole wave: both candidate lists, then the
 // pairs dealt out over the lanes and a 64-bit minimum.  *fits is false if a
 // list exceeded cap (the key is then not valid).
-template <class E>
+template <class E, int BS>
 __device__ __forceinline__ unsigned long long nf_wave_pairs(
     const RowView& D, const RowView& U, float2 c, const NfMetric& km, float wy, float wz,
-    E (*s_dl)[kGridBlock], E (*s_ul)[kGridBlock], int cap, int col0, int lane, bool* fits) {
+    E (*s_dl)[BS], E (*s_ul)[BS], int cap, int col0, int lane, bool* fits) {
   const int nd = nf_wave_collect(D, c.x, c.y, wy, wz, s_dl, cap, col0, lane);
   const int nu = nd ? nf_wave_collect(U, c.x, c.y, wy, wz, s_ul, cap, col0, lane) : 0;
   *fits = nd <= cap && nu <= cap;
@@ -497,19 +526,18 @@ __device__ __forceinline__ unsigned long long nf_wave_pairs(
 // one: s_ul has three rows more than LIST, and with relative entries the
 // upper row's stage 256 records more than CAP, so that these reads stay in
 // place; their pairs are not counted.
-template <int CAP, int LIST, class E>
+template <int CAP, int LIST, class E, int BS>
 __device__ __forceinline__ void nf_pairs_staged(
     const DevEvent& ev, const KParams& kp, const Scratch& sc, int b, int e, int bd_, int bu_,
     const RowGrid& gd, const RowGrid& gu, const GridRec& me_first, const NfMetric& km,
     float wy, float wz, const float2* s_yzd, const float2* s_yzu, uint16_t (*s_id)[CAP],
-    uint16_t (*s_bins)[CAP + 2], E (*s_dl)[kGridBlock], E (*s_ul)[kGridBlock],
-    NfPairs<E>* s_pw) {
+    uint16_t (*s_bins)[CAP + 2], E (*s_dl)[BS], E (*s_ul)[BS], NfPairs<E>* s_pw) {
   constexpr bool kRel = sizeof(E) == 1;  // relative (8-bit) list entries
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, col0 = tid - lane;
   NfPairs<E>& P = s_pw[w];
   const RowView D{s_yzd, s_id[0], s_bins[0], gd, bd_}, U{s_yzu, s_id[1], s_bins[1], gu, bu_};
   const bool both = gd.n > 0 && gu.n > 0;
-  for (int base = col0; base < e - b; base += kGridBlock) {  // uniform over the wave
+  for (int base = col0; base < e - b; base += BS) {  // uniform over the wave
     const int ii = base + lane;
     const bool have = ii < e - b;
     GridRec me = {};
@@ -572,7 +600,7 @@ __device__ __forceinline__ void nf_pairs_staged(
         int ku[4];
         float x[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) ku[i] = NfEntry<E>::off(lu[i * kGridBlock], ub);
+        for (int i = 0; i < 4; ++i) ku[i] = NfEntry<E>::off(lu[i * BS], ub);
 #pragma unroll
         for (int i = 0; i < 4; ++i) x[i] = nf_chi2(km, a, yz_off(s_yzu, ku[i]), c);
         const float bc0 = bc;
@@ -669,16 +697,16 @@ __device__ __forceinline__ void nf_pairs_staged(
   }
 }
 
-template <int CAP, int LIST, class E>
-__global__ __launch_bounds__(kGridBlock) void k_nf(DevEvent ev, KParams kp, Scratch sc) {
+template <int CAP, int LIST, class E, int BS>
+__global__ __launch_bounds__(BS) void k_nf(DevEvent ev, KParams kp, Scratch sc) {
   static_assert(CAP * 8 <= 65536, "stage offsets are 16-bit");
   static_assert(LIST * 32 * (int)sizeof(E) >= CAP, "a wave's lists hold a whole staged row");
   __shared__ float2 s_yzd[CAP], s_yzu[CAP + (sizeof(E) == 1 ? 256 : 0)];
   __shared__ uint16_t s_id[2][CAP];
   __shared__ uint16_t s_bins[2][CAP + 2];
-  __shared__ E s_dl[LIST][kGridBlock];
-  __shared__ E s_ul[LIST + 3][kGridBlock];
-  __shared__ NfPairs<E> s_pw[kGridBlock / 64];
+  __shared__ E s_dl[LIST][BS];
+  __shared__ E s_ul[LIST + 3][BS];
+  __shared__ NfPairs<E> s_pw[BS / 64];
   if (event_bad(sc.counters)) return;
   // blocks in row-major order over the sectors: the dense inner rows of every
   // sector start first, and the sparse outer rows fill in behind them
@@ -687,7 +715,7 @@ __global__ __launch_bounds__(kGridBlock) void k_nf(DevEvent ev, KParams kp, Scra
   const int tid = threadIdx.x;
   const int b = ev.ro[rs], e = ev.ro[rs + 1];
   if (r == 0 || r == kp.n_rows - 1) {
-    for (int i = b + tid; i < e; i += kGridBlock) {
+    for (int i = b + tid; i < e; i += BS) {
       sc.up[i] = -1;
       sc.dn[i] = -1;
     }
@@ -712,31 +740,31 @@ __global__ __launch_bounds__(kGridBlock) void k_nf(DevEvent ev, KParams kp, Scra
   const float wy = kp.nf_win_y, wz = kp.nf_win_z;
   if (stage) {
     const int nbd = gd.ny * gd.nz, nbu = gu.ny * gu.nz;
-    for (int i = tid; i < gd.n; i += kGridBlock) {
+    for (int i = tid; i < gd.n; i += BS) {
       const GridRec v = sc.g_rec[bd_ + i];
       s_yzd[i] = make_float2(v.y, v.z);
       s_id[0][i] = (uint16_t)(v.id - bd_);
     }
-    for (int i = tid; i < gu.n; i += kGridBlock) {
+    for (int i = tid; i < gu.n; i += BS) {
       const GridRec v = sc.g_rec[bu_ + i];
       s_yzu[i] = make_float2(v.y, v.z);
       s_id[1][i] = (uint16_t)(v.id - bu_);
     }
     if (gd.n > 0)
-      for (int i = tid; i <= nbd; i += kGridBlock) s_bins[0][i] = (uint16_t)sc.bins[gd.bin_base + i];
+      for (int i = tid; i <= nbd; i += BS) s_bins[0][i] = (uint16_t)sc.bins[gd.bin_base + i];
     if (gu.n > 0)
-      for (int i = tid; i <= nbu; i += kGridBlock) s_bins[1][i] = (uint16_t)sc.bins[gu.bin_base + i];
+      for (int i = tid; i <= nbu; i += BS) s_bins[1][i] = (uint16_t)sc.bins[gu.bin_base + i];
     for (int i = 0; i < LIST + 3; ++i) s_ul[i][tid] = 0;
     __syncthreads();
   }
   // lanes take the row's clusters in grid order: neighbouring lanes sit at
   // nearby positions and visit similar bins, so a wave diverges less
   if (stage) {
-    nf_pairs_staged<CAP, LIST, E>(ev, kp, sc, b, e, bd_, bu_, gd, gu, me_first, km, wy, wz, s_yzd,
+    nf_pairs_staged<CAP, LIST, E, BS>(ev, kp, sc, b, e, bd_, bu_, gd, gu, me_first, km, wy, wz, s_yzd,
                                s_yzu, s_id, s_bins, s_dl, s_ul, s_pw);
     return;
   }
-  for (int ii = tid; ii < e - b; ii += kGridBlock) {
+  for (int ii = tid; ii < e - b; ii += BS) {
     const GridRec me = ii == tid ? me_first : sc.g_rec[b + ii];
     const int i = me.id;
     float best = INFINITY;
@@ -754,14 +782,15 @@ __global__ __launch_bounds__(kGridBlock) void k_nf(DevEvent ev, KParams kp, Scra
 
 // ------------------------------------------------------------------ k_evo
 
-__global__ __launch_bounds__(kGridBlock) void k_evo(DevEvent ev, KParams kp, Scratch sc) {
-  __shared__ int s_w[kGridBlock / 64];
+template <int BS>
+__global__ __launch_bounds__(BS) void k_evo(DevEvent ev, KParams kp, Scratch sc) {
+  __shared__ int s_w[BS / 64];
   if (event_bad(sc.counters)) return;
   const int rs = blockIdx.x;
   const int tid = threadIdx.x;
   const int b = ev.ro[rs], e = ev.ro[rs + 1];
   int cnt = 0;
-  for (int i = b + tid; i < e; i += kGridBlock) {
+  for (int i = b + tid; i < e; i += BS) {
     const int u = sc.up[i], d = sc.dn[i];
     const int u2 = (u >= 0 && sc.dn[u] == i) ? u : -1;
     const int d2 = (d >= 0 && sc.up[d] == i) ? d : -1;
@@ -783,7 +812,7 @@ __global__ __launch_bounds__(kGridBlock) void k_evo(DevEvent ev, KParams kp, Scr
     cnt += start ? 1 : 0;
   }
   int tot;
-  block_excl_scan<kGridBlock>(cnt, s_w, &tot);
+  block_excl_scan<BS>(cnt, s_w, &tot);
   if (tid == 0) sc.row_cnt[rs] = tot;
 }
 
@@ -855,19 +884,20 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_rows(int R, Scratch sc) {
   }
 }
 
-__global__ __launch_bounds__(kGridBlock) void k_seed_write(DevEvent ev, Scratch sc) {
-  __shared__ int s_w[kGridBlock / 64];
+template <int BS>
+__global__ __launch_bounds__(BS) void k_seed_write(DevEvent ev, Scratch sc) {
+  __shared__ int s_w[BS / 64];
   if (event_bad(sc.counters)) return;
   const int rs = blockIdx.x;
   const int tid = threadIdx.x;
   const int b = ev.ro[rs], e = ev.ro[rs + 1];
   int base = sc.row_cnt[rs];
   if (sc.row_cnt[rs + 1] == base) return;  // uniform: no start in this row
-  for (int c0 = b; c0 < e; c0 += kGridBlock) {
+  for (int c0 = b; c0 < e; c0 += BS) {
     const int i = c0 + tid;
     const int f = (i < e) ? sc.start[i] : 0;
     int tot;
-    const int rank = block_excl_scan<kGridBlock>(f, s_w, &tot);
+    const int rank = block_excl_scan<BS>(f, s_w, &tot);
     if (f && base + rank < sc.cap_tl) {
       sc.seeds[base + rank] = i;
       sc.seed_rs[base + rank] = rs;
@@ -2874,19 +2904,30 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
   if (zero_counters) hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, sc.counters);
   post(K_ZERO);
   pre(K_GRID);
-  hipLaunchKernelGGL(k_grid, dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc, out.cluster_track);
+  if (kp.row_wave)
+    hipLaunchKernelGGL((k_grid<64, kGridWaveBins>), dim3(R), dim3(64), 0, st, ev, kp, sc,
+                       out.cluster_track);
+  else
+    hipLaunchKernelGGL((k_grid<kGridBlock, kMaxBins>), dim3(R), dim3(kGridBlock), 0, st, ev, kp,
+                       sc, out.cluster_track);
   post(K_GRID);
   if (upto <= STAGE_GRID) return hipGetLastError();
   pre(K_NF);
-  if (kp.nf_dense)
-    hipLaunchKernelGGL((k_nf<kNfCapLarge, kNfListLarge, uint8_t>), dim3(R), dim3(kGridBlock), 0, st,
+  if (kp.nf_stage == 2)
+    hipLaunchKernelGGL((k_nf<kNfCapLarge, kNfListLarge, uint8_t, kGridBlock>), dim3(R),
+                       dim3(kGridBlock), 0, st, ev, kp, sc);
+  else if (kp.nf_stage == 3)
+    hipLaunchKernelGGL((k_nf<kNfCapWave, kNfListSmall, uint16_t, 64>), dim3(R), dim3(64), 0, st,
                        ev, kp, sc);
   else
-    hipLaunchKernelGGL((k_nf<kNfCapSmall, kNfListSmall, uint16_t>), dim3(R), dim3(kGridBlock), 0, st,
-                       ev, kp, sc);
+    hipLaunchKernelGGL((k_nf<kNfCapSmall, kNfListSmall, uint16_t, kGridBlock>), dim3(R),
+                       dim3(kGridBlock), 0, st, ev, kp, sc);
   post(K_NF);
   pre(K_EVO);
-  hipLaunchKernelGGL(k_evo, dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc);
+  if (kp.row_wave)
+    hipLaunchKernelGGL(k_evo<64>, dim3(R), dim3(64), 0, st, ev, kp, sc);
+  else
+    hipLaunchKernelGGL(k_evo<kGridBlock>, dim3(R), dim3(kGridBlock), 0, st, ev, kp, sc);
   post(K_EVO);
   if (upto <= STAGE_LINKS) return hipGetLastError();
   pre(K_SCAN_ROWS);
@@ -2897,7 +2938,10 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
   }
   post(K_SCAN_ROWS);
   pre(K_SEED_WRITE);
-  hipLaunchKernelGGL(k_seed_write, dim3(R), dim3(kGridBlock), 0, st, ev, sc);
+  if (kp.row_wave)
+    hipLaunchKernelGGL(k_seed_write<64>, dim3(R), dim3(64), 0, st, ev, sc);
+  else
+    hipLaunchKernelGGL(k_seed_write<kGridBlock>, dim3(R), dim3(kGridBlock), 0, st, ev, sc);
   post(K_SEED_WRITE);
   if (upto <= STAGE_SEEDS) return hipGetLastError();
   pre(K_CONSTRUCT);

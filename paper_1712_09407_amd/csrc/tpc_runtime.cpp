@@ -142,14 +142,27 @@ static int32_t own_chunk(int64_t n_clusters, int64_t n_rowslots, int32_t n_rows)
   return n_clusters / sectors < 65536 ? 2048 : 4096;
 }
 
-// Mean clusters per row slot above which the neighbours finder stages
-// larger rows and keeps longer candidate lists (speed only).
-static int32_t dense_rows(int64_t n_clusters, int64_t n_rowslots) {
-  return n_clusters > (int64_t)320 * (n_rowslots > 0 ? n_rowslots : 1) ? 1 : 0;
+// Mean clusters per row slot of an event or batch (speed only: every form of
+// the per-row kernels gives the same results).
+static int64_t row_mean(int64_t n_clusters, int64_t n_rowslots) {
+  return n_clusters / (n_rowslots > 0 ? n_rowslots : 1);
 }
-// The neighbours finder's stage: the tuning's choice, or by density.
+// Many sparse row slots (a batch of six or more events averaging fewer than
+// 128 clusters per row): the per-row kernels are then bound by how many row
+// slots the chip holds at once, and one wave per row slot holds more.  A
+// single event keeps four waves per row slot: its rows are few, and a sparse
+// mean can hide a few full sectors.
+static bool sparse_rows(int64_t n_clusters, int64_t n_rowslots) {
+  return n_rowslots >= 32768 && row_mean(n_clusters, n_rowslots) < 128;
+}
+// The neighbours finder's stage: the tuning's choice, or by density (larger
+// rows and longer candidate lists above 320 clusters per row; on many sparse
+// rows one wave per row slot, whose workgroups fit the CU three times as
+// often, which the grid, evolution and seed kernels then take too).
 static int32_t nf_stage_of(int32_t stage, int64_t n_clusters, int64_t n_rowslots) {
-  return stage == 0 ? dense_rows(n_clusters, n_rowslots) : (stage == 2 ? 1 : 0);
+  if (stage != 0) return stage;
+  if (row_mean(n_clusters, n_rowslots) > 320) return 2;
+  return sparse_rows(n_clusters, n_rowslots) ? 3 : 1;
 }
 
 KParams make_kparams(const tpc_geometry* geo, float bz, const tpc_params* p) {
@@ -183,7 +196,7 @@ KParams make_kparams(const tpc_geometry* geo, float bz, const tpc_params* p) {
   k.bin_occupancy = 1.0f;
   k.construct_blocks = 0;
   k.construct_schedule = 0;
-  k.nf_dense = 0;
+  k.nf_stage = 1;
   k.own_chunk = 4096;
   k.construct_lanes = 64;
   return k;
@@ -313,7 +326,8 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
   kp.construct_lanes = lanes_per_wave(ctx->tuning.construct_lanes, N);
   kp.n_cu = ctx->n_cu;
   kp.expect_tl = expected_tracklets(ctx, N);
-  kp.nf_dense = nf_stage_of(ctx->tuning.nf_stage, N, R);
+  kp.nf_stage = nf_stage_of(ctx->tuning.nf_stage, N, R);
+  kp.row_wave = kp.nf_stage == 3;
   kp.own_chunk = own_chunk(N, R, kp.n_rows);
   {  // neighbouring sectors' centre lines are one sector width, 2 atan(tan_half), apart
     const double w = 2.0 * std::atan((double)geo->tan_half_angle);
@@ -602,7 +616,8 @@ int run_batch(tpc_ctx* ctx, const tpc_event* evs, int E, const tpc_geometry* geo
   kp.construct_lanes = lanes_per_wave(ctx->tuning.construct_lanes, N);
   kp.n_cu = ctx->n_cu;
   kp.expect_tl = expected_tracklets(ctx, N);
-  kp.nf_dense = nf_stage_of(ctx->tuning.nf_stage, N, R);
+  kp.nf_stage = nf_stage_of(ctx->tuning.nf_stage, N, R);
+  kp.row_wave = kp.nf_stage == 3;
   kp.own_chunk = own_chunk(N, R, kp.n_rows);
   DevEvent dev = make_devevent(&bev);
   if (use_graph) {
@@ -808,8 +823,8 @@ int tpc_ctx_set_tuning(tpc_ctx* ctx, const tpc_tuning* t) {
     return fail(TPC_ERR_INVALID_ARG, "construct_schedule must be 0 or 1");
   if (t->construct_lanes < 0 || t->construct_lanes > 64)
     return fail(TPC_ERR_INVALID_ARG, "construct_lanes outside [0, 64]");
-  if (t->nf_stage < 0 || t->nf_stage > 2)
-    return fail(TPC_ERR_INVALID_ARG, "nf_stage must be 0, 1 or 2");
+  if (t->nf_stage < 0 || t->nf_stage > 3)
+    return fail(TPC_ERR_INVALID_ARG, "nf_stage must be 0, 1, 2 or 3");
   ctx->tuning = *t;
   return TPC_OK;
 }

@@ -14,7 +14,7 @@ import time
 CANDIDATES = ([dict(construct_schedule=0, construct_blocks=0, construct_lanes=a, bin_occupancy=o)
                for a in (0, 16, 32, 64) for o in (1.0, 2.0)] +
               [dict(construct_schedule=1, construct_blocks=0, bin_occupancy=1.0)])
-NF_STAGES = (1, 2)   # tried with the best of CANDIDATES (0, automatic, is part of it)
+NF_STAGES = (1, 2, 3)   # tried with the best of CANDIDATES (0, automatic, is part of it)
 
 
 def bucket(evs) -> int:

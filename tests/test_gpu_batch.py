@@ -124,7 +124,8 @@ def test_graph_replays_match_eager(tracker, geo, events):
     (0, 1.0, 0, 64, 0), (0, 1.0, 1, 64, 0), (64, 1.0, 0, 64, 0), (64, 1.0, 1, 64, 0),
     (7, 1.0, 0, 64, 0), (512, 2.0, 1, 64, 0), (0, 1.5, 0, 64, 0), (2048, 4.0, 0, 64, 0),
     (2048, 4.0, 1, 64, 0), (0, 1.0, 0, 16, 0), (0, 1.0, 0, 1, 0), (40, 1.0, 0, 8, 0),
-    (0, 1.0, 0, 0, 1), (0, 1.0, 0, 0, 2), (0, 2.0, 1, 64, 2)])
+    (0, 1.0, 0, 0, 1), (0, 1.0, 0, 0, 2), (0, 2.0, 1, 64, 2), (0, 1.0, 0, 0, 3),
+    (0, 2.0, 1, 64, 3)])
 def test_tuning_never_changes_results(tracker, geo, events, blocks, occ, sched, lanes, nf):
     devs = [dev(e) for e in events[:4]]
     tracker.set_tuning(use_graph=0, construct_schedule=0)
@@ -158,5 +159,5 @@ def test_tuning_rejects_out_of_range_settings(tracker):
     with pytest.raises(tpc.TpcError):
         tracker.set_tuning(construct_lanes=65)
     with pytest.raises(tpc.TpcError):
-        tracker.set_tuning(nf_stage=3)
+        tracker.set_tuning(nf_stage=4)
     tracker.set_tuning()

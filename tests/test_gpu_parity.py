@@ -299,6 +299,44 @@ def test_constructor_schedules_agree_bitwise(tracker, geo, name, seed):
             assert np.array_equal(ra[k].view(np.uint8), rb[k].view(np.uint8)), k
 
 
+@pytest.mark.parametrize("name", ["c1_sector", "c2_central", "crowded", "dense"])
+def test_neighbour_forms_agree_bitwise(tracker, geo, name):
+    """The neighbours finder's three forms (512-cluster stage with four waves,
+    1024-cluster stage with 8-bit lists, 256-cluster stage with one wave per
+    row slot, which also runs the grid, evolution and seed kernels with one
+    wave per row slot) give the same links and tracks bit for bit: on the
+    central event the one-wave form takes its rows of more than 256 clusters
+    through the global-memory search, on the crowded one its wave-wide
+    search, on the dense one every form takes some rows through the
+    global-memory search, and the one-wave grid kernel counts its rows of more
+    than 1024 bins in global memory."""
+    if name == "crowded":
+        e = crowded_event(41, 3.0, 140)
+    elif name == "dense":
+        e = synth.make_event(synth.EventConfig(n_tracks=150, sectors=(0,), phi_range_deg=(0, 20),
+                                               ignore_membrane=True, noise_frac=20.0), 31)
+    else:
+        e = get_event(name, {"c1_sector": 1, "c2_central": 2}[name])
+    say("neighbour forms", name, e.n_clusters)
+    dev = dev_event(e)
+    links, res = [], []
+    for form in (1, 2, 3):
+        tracker.set_tuning(nf_stage=form)
+        links.append([x.cpu().numpy() for x in tracker.links(dev, geo)])
+        res.append(tpc.to_numpy(tracker.track_event(dev, geo, e.bz)))
+    tracker.set_tuning()
+    if name == "c2_central":
+        assert np.diff(e.row_offsets).max() > 256
+    if name == "dense":
+        assert np.diff(e.row_offsets).max() > 1024
+    for other in links[1:]:
+        for a, b in zip(links[0], other):
+            assert np.array_equal(a, b)
+    for other in res[1:]:
+        for k in ("track_par", "track_meta", "track_cluster", "cluster_track"):
+            assert np.array_equal(res[0][k].view(np.uint8), other[k].view(np.uint8)), k
+
+
 # ------------------------------------------------------------- edge cases
 def test_empty_and_sparse_events(orc, tracker, geo):
     ro = np.zeros(36 * 159 + 1, np.int32)
