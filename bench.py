@@ -302,6 +302,43 @@ def central_concordance_section(tr, tpc, synth, geo, prm, events, log_):
                 clusters=int(sum(len(h["y"]) for h, _ in runs)))
 
 
+def central_batched_section(tr, tpc, synth, geo, prm, events, steps, log_):
+    """Central events tracked several at a time (one launch sequence per
+    batch, graph replay): the constructor's tail, in which a single event's
+    longest tracklets run on an otherwise idle chip, is shared by the batch.
+    Throughput against the plain per-event path of the headline; the first
+    event's tracks must be bitwise those of the event alone."""
+    import torch
+    devs = [tpc.DeviceEvent.from_host(e.y, e.z, e.row_offsets, e.sector_id) for e in events]
+    n_cl = sum(d.n_clusters for d in devs)
+    tr.set_tuning(use_graph=0)
+    st = timed_probe(tr, lambda: tr.track_batch(devs, geo, events[0].bz, prm), reps=2)
+    per = {k: v / 2 / len(devs) for k, v in st["kernel_ms"].items() if v > 0}
+    tr.set_tuning()
+    res = tr.track_batch(devs, geo, events[0].bz, prm)
+    alone = tr.track_event(devs[0], geo, events[0].bz, prm)
+    a, b = tpc.to_numpy(res[0]), tpc.to_numpy(alone)
+    same = all(np.array_equal(np.asarray(a[k]).view(np.uint8), np.asarray(b[k]).view(np.uint8))
+               for k in ("track_par", "track_meta", "track_cluster", "cluster_track"))
+    call, _, _ = raw_batch(tr, tpc, devs, geo, events[0].bz, prm)
+    call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        call()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return dict(workload=f"{len(devs)} central events per batch (seeds {CENTRAL_SEEDS[0]}-"
+                         f"{CENTRAL_SEEDS[len(devs) - 1]}), {n_cl} clusters",
+                events_per_s=round(len(devs) * steps / el, 1),
+                clusters_per_s=round(n_cl * steps / el, 1),
+                ms_per_batch=round(el / steps * 1e3, 3),
+                ms_per_event=round(el / steps / len(devs) * 1e3, 4),
+                path_hbm=staged_hbm(n_cl * steps / el),
+                kernels_ms_per_event={k: round(v, 4) for k, v in per.items()},
+                first_event_bitwise_as_alone=bool(same))
+
+
 def stress_section(tr, tpc, synth, geo, host, steps, log_):
     """Stress events (20000 primaries + 6000 loopers, 10% noise, sigma 0.15)
     in batches of len(host): throughput, the dominant kernel's roofline and
@@ -883,6 +920,8 @@ def main():
         sections = (("single_sector", lambda: single_sector_section(tr, tpc, synth, geo, prm, 500, log)),
                     ("central_concordance", lambda: central_concordance_section(
                         tr, tpc, synth, geo, prm, host["central"], log)),
+                    ("central_batched", lambda: central_batched_section(
+                        tr, tpc, synth, geo, prm, host["central"][:8], 10, log)),
                     ("stress", lambda: stress_section(tr, tpc, synth, geo, host["stress"], 3, log)),
                     ("global_tracking", lambda: global_section(tr, tpc, synth, geo, prm, e,
                                                                dev_ev, 20, log)),
