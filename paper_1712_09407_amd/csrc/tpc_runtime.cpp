@@ -121,15 +121,15 @@ int validate(const tpc_event* ev, const tpc_geometry* geo, const tpc_params* p) 
 // Lanes per wave of the lane-schedule constructor.  Its time is the critical
 // path of the longest tracklets; a wave with fewer lanes takes shorter steps
 // (fewer scattered loads and phases per step) as long as the waves do not
-// queue on the SIMDs.  Automatic (0): about 2048 waves for the expected
-// number of tracklets (one per 36 clusters), as a power of two in [8, 64].
+// queue on the SIMDs.  Automatic (0): a multiple of four in [8, 64] that
+// grows with the square root of the expected number of tracklets (one per
+// 36 clusters).
 static int32_t lanes_per_wave(int32_t requested, int64_t n_clusters) {
   if (requested > 0) return requested;
-  // about one tracklet per 36 clusters; measured best: 20 lanes at 0.33 M
-  // clusters, 32 to 40 for a central event (1.3 M), 56 to 64 for 4.6 M, 8
-  // for small events
+  // measured best: 20 lanes at 0.33 M clusters, 40 for a central event
+  // (1.3 M; 32 and 36 within 1.5%), 56 to 64 for 4.6 M, 8 for small events
   const double waves = (double)(n_clusters / 36 + 1) / 2048.0;
-  const int32_t a = 4 * (int32_t)std::lround(2.1 * std::sqrt(waves) + 0.5);
+  const int32_t a = 4 * (int32_t)std::lround(2.2 * std::sqrt(waves) + 0.5);
   return std::min(64, std::max(8, a));
 }
 
