@@ -330,6 +330,11 @@ typedef struct {
                                  more than 320 clusters per row, 3 when a batch of
                                  32768 row slots or more averages fewer than 128,
                                  else 1) */
+  int32_t own_order;          /* selection's launch order: 1 = every sector's first
+                                 workgroups first; 2 = a sector's workgroups one
+                                 after another (they share its tracklets' rows in
+                                 the caches); 0 = automatic (2 for more than 144
+                                 sectors of 64k clusters or more on average, else 1) */
 } tpc_tuning;
 void tpc_tuning_default(tpc_tuning* t);
 int tpc_ctx_set_tuning(tpc_ctx* ctx, const tpc_tuning* t);

@@ -33,6 +33,7 @@ struct KParams {
   int32_t row_wave;            // grid, evolution and seed kernels: one wave per row slot
   int32_t construct_lanes;     // lane schedule: lanes of a wave that take tracklets
   int32_t own_chunk;           // selection: clusters per LDS chunk of a sector (speed only)
+  int32_t own_by_sector;       // selection: a sector's workgroups consecutive in launch order
   int32_t n_cu;                // compute units of the device (launch sizing only)
   int32_t expect_tl;           // tracklets expected (launch sizing only)
   float rot_c, rot_s;          // cos, sin of one sector width (global tracking)

@@ -1657,14 +1657,18 @@ __global__ __launch_bounds__(kOwnBlock) void k_own(DevEvent ev, KParams kp, Scra
   __shared__ int s_rows[2];
   if (event_bad(sc.counters)) return;
   const int nr = kp.n_rows;
-  const int s = blockIdx.x;
+  // workgroup -> (sector, first chunk): a grid of (sectors, kOwnSplit), every
+  // sector's first workgroups first, or with KParams::own_by_sector a grid of
+  // sectors x kOwnSplit in which a sector's workgroups are consecutive
+  const int s = kp.own_by_sector ? (int)blockIdx.x / kOwnSplit : (int)blockIdx.x;
+  const int split = kp.own_by_sector ? (int)blockIdx.x % kOwnSplit : (int)blockIdx.y;
   const int tid = threadIdx.x;
   const int n_tl = min(sc.counters[C_SEEDS], sc.cap_tl);
   const int t0 = min(sc.row_cnt[s * nr], n_tl), t1 = min(sc.row_cnt[(s + 1) * nr], n_tl);
   const int c0 = ev.ro[s * nr], c1 = ev.ro[(s + 1) * nr];
   const int chunk = min(max(kp.own_chunk, 256), kOwnChunk);
   const int nch = (c1 - c0 + chunk - 1) / chunk;
-  for (int ch = blockIdx.y; ch < nch; ch += gridDim.y) {
+  for (int ch = split; ch < nch; ch += kOwnSplit) {
     const int cb = c0 + ch * chunk, ce = min(cb + chunk, c1);
     // rows of the sector with clusters in [cb, ce)
     if (tid == 0) {
@@ -2995,7 +2999,10 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
   if (upto <= STAGE_TRACKLETS) return hipGetLastError();
   const int wb = wave_blocks(sc.cap_tl);
   pre(K_OWN);
-  hipLaunchKernelGGL(k_own, dim3(ev.n_sectors, kOwnSplit), dim3(kOwnBlock), 0, st, ev, kp, sc);
+  if (kp.own_by_sector)
+    hipLaunchKernelGGL(k_own, dim3(ev.n_sectors * kOwnSplit), dim3(kOwnBlock), 0, st, ev, kp, sc);
+  else
+    hipLaunchKernelGGL(k_own, dim3(ev.n_sectors, kOwnSplit), dim3(kOwnBlock), 0, st, ev, kp, sc);
   post(K_OWN);
   const int spans = (int)((sc.cap_tl + kSpan - 1) / kSpan);
   pre(K_TL_REDUCE);

@@ -141,6 +141,17 @@ static int32_t own_chunk(int64_t n_clusters, int64_t n_rowslots, int32_t n_rows)
   const int64_t sectors = std::max<int64_t>(1, n_rowslots / std::max<int32_t>(1, n_rows));
   return n_clusters / sectors < 65536 ? 2048 : 4096;
 }
+// The selection's launch order (speed only): by sector when many dense
+// sectors (more than four events' worth, 64k clusters or more each) make
+// many rounds of workgroups, so that the workgroups of a sector run together
+// and share its tracklets' headers and hit rows in the caches; otherwise
+// every sector's first workgroups first, which puts the busy ones of sparse
+// sectors (fewer chunks than workgroups) together.
+static int32_t own_by_sector(int32_t order, int64_t n_rowslots, int32_t n_rows, int32_t chunk) {
+  if (order != 0) return order == 2 ? 1 : 0;
+  const int64_t sectors = n_rowslots / std::max<int32_t>(1, n_rows);
+  return chunk == 4096 && sectors > 144 ? 1 : 0;
+}
 
 // Mean clusters per row slot of an event or batch (speed only: every form of
 // the per-row kernels gives the same results).
@@ -329,6 +340,7 @@ int run_event(tpc_ctx* ctx, const tpc_event* ev, const tpc_geometry* geo, float 
   kp.nf_stage = nf_stage_of(ctx->tuning.nf_stage, N, R);
   kp.row_wave = kp.nf_stage == 3;
   kp.own_chunk = own_chunk(N, R, kp.n_rows);
+  kp.own_by_sector = own_by_sector(ctx->tuning.own_order, R, kp.n_rows, kp.own_chunk);
   {  // neighbouring sectors' centre lines are one sector width, 2 atan(tan_half), apart
     const double w = 2.0 * std::atan((double)geo->tan_half_angle);
     kp.rot_c = (float)std::cos(w);
@@ -619,6 +631,7 @@ int run_batch(tpc_ctx* ctx, const tpc_event* evs, int E, const tpc_geometry* geo
   kp.nf_stage = nf_stage_of(ctx->tuning.nf_stage, N, R);
   kp.row_wave = kp.nf_stage == 3;
   kp.own_chunk = own_chunk(N, R, kp.n_rows);
+  kp.own_by_sector = own_by_sector(ctx->tuning.own_order, R, kp.n_rows, kp.own_chunk);
   DevEvent dev = make_devevent(&bev);
   if (use_graph) {
     dev.n_clusters = (int32_t)ncap;
@@ -811,6 +824,7 @@ void tpc_tuning_default(tpc_tuning* t) {
   t->construct_schedule = 0;
   t->construct_lanes = 0;
   t->nf_stage = 0;
+  t->own_order = 0;
 }
 
 int tpc_ctx_set_tuning(tpc_ctx* ctx, const tpc_tuning* t) {
@@ -825,6 +839,8 @@ int tpc_ctx_set_tuning(tpc_ctx* ctx, const tpc_tuning* t) {
     return fail(TPC_ERR_INVALID_ARG, "construct_lanes outside [0, 64]");
   if (t->nf_stage < 0 || t->nf_stage > 3)
     return fail(TPC_ERR_INVALID_ARG, "nf_stage must be 0, 1, 2 or 3");
+  if (t->own_order < 0 || t->own_order > 2)
+    return fail(TPC_ERR_INVALID_ARG, "own_order must be 0, 1 or 2");
   ctx->tuning = *t;
   return TPC_OK;
 }

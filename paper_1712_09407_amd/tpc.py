@@ -48,7 +48,8 @@ class Params(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("use_graph", C.c_int32), ("construct_blocks", C.c_int32),
                 ("bin_occupancy", C.c_float), ("construct_schedule", C.c_int32),
-                ("construct_lanes", C.c_int32), ("nf_stage", C.c_int32)]
+                ("construct_lanes", C.c_int32), ("nf_stage", C.c_int32),
+                ("own_order", C.c_int32)]
 
 
 class ServerConfig(C.Structure):
@@ -400,7 +401,7 @@ class Tracker:
 
     def set_tuning(self, **kw):
         """Speed knobs (results never change): use_graph, construct_blocks,
-        bin_occupancy, construct_schedule, construct_lanes, nf_stage.  Unnamed
+        bin_occupancy, construct_schedule, construct_lanes, nf_stage, own_order.  Unnamed
         knobs keep their defaults."""
         tu = Tuning()
         lib.tpc_tuning_default(C.byref(tu))

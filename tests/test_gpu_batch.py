@@ -120,18 +120,19 @@ def test_graph_replays_match_eager(tracker, geo, events):
             assert np.array_equal(a[k], b[k]), k
 
 
-@pytest.mark.parametrize("blocks,occ,sched,lanes,nf", [
-    (0, 1.0, 0, 64, 0), (0, 1.0, 1, 64, 0), (64, 1.0, 0, 64, 0), (64, 1.0, 1, 64, 0),
-    (7, 1.0, 0, 64, 0), (512, 2.0, 1, 64, 0), (0, 1.5, 0, 64, 0), (2048, 4.0, 0, 64, 0),
-    (2048, 4.0, 1, 64, 0), (0, 1.0, 0, 16, 0), (0, 1.0, 0, 1, 0), (40, 1.0, 0, 8, 0),
-    (0, 1.0, 0, 0, 1), (0, 1.0, 0, 0, 2), (0, 2.0, 1, 64, 2), (0, 1.0, 0, 0, 3),
-    (0, 2.0, 1, 64, 3)])
-def test_tuning_never_changes_results(tracker, geo, events, blocks, occ, sched, lanes, nf):
+@pytest.mark.parametrize("blocks,occ,sched,lanes,nf,own", [
+    (0, 1.0, 0, 64, 0, 0), (0, 1.0, 1, 64, 0, 0), (64, 1.0, 0, 64, 0, 0), (64, 1.0, 1, 64, 0, 0),
+    (7, 1.0, 0, 64, 0, 0), (512, 2.0, 1, 64, 0, 0), (0, 1.5, 0, 64, 0, 0), (2048, 4.0, 0, 64, 0, 0),
+    (2048, 4.0, 1, 64, 0, 0), (0, 1.0, 0, 16, 0, 0), (0, 1.0, 0, 1, 0, 0), (40, 1.0, 0, 8, 0, 0),
+    (0, 1.0, 0, 0, 1, 0), (0, 1.0, 0, 0, 2, 0), (0, 2.0, 1, 64, 2, 0), (0, 1.0, 0, 0, 3, 0),
+    (0, 2.0, 1, 64, 3, 0), (0, 1.0, 0, 0, 0, 1), (0, 1.0, 0, 0, 0, 2), (0, 2.0, 1, 64, 2, 2)])
+def test_tuning_never_changes_results(tracker, geo, events, blocks, occ, sched, lanes, nf, own):
     devs = [dev(e) for e in events[:4]]
     tracker.set_tuning(use_graph=0, construct_schedule=0)
     ref = [tpc.to_numpy(r) for r in tracker.track_batch(devs, geo, 0.5)]
     tracker.set_tuning(use_graph=1, construct_blocks=blocks, bin_occupancy=occ,
-                       construct_schedule=sched, construct_lanes=lanes, nf_stage=nf)
+                       construct_schedule=sched, construct_lanes=lanes, nf_stage=nf,
+                       own_order=own)
     got = [tpc.to_numpy(r) for r in tracker.track_batch(devs, geo, 0.5)]
     tracker.set_tuning()
     for a, b in zip(ref, got):
@@ -160,4 +161,6 @@ def test_tuning_rejects_out_of_range_settings(tracker):
         tracker.set_tuning(construct_lanes=65)
     with pytest.raises(tpc.TpcError):
         tracker.set_tuning(nf_stage=4)
+    with pytest.raises(tpc.TpcError):
+        tracker.set_tuning(own_order=3)
     tracker.set_tuning()
