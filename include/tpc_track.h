@@ -317,7 +317,8 @@ typedef struct {
                                  tracklets (1 .. 64); fewer lanes per wave shorten
                                  each wave's steps at the cost of more waves;
                                  0 = automatic (grows with the square root of the
-                                 clusters: 20 at 0.33 M, 40 at 1.3 M, 64 from 4 M) */
+                                 clusters: 1 below about 15k, 20 at 0.33 M, 40 at
+                                 1.3 M, 64 from 4 M) */
   int32_t nf_stage;           /* neighbours finder's LDS stage: 1 = rows of up to 512
                                  clusters, 12 window candidates per lane and row
                                  (five workgroups per CU); 2 = rows of up to 1024

@@ -127,9 +127,13 @@ int validate(const tpc_event* ev, const tpc_geometry* geo, const tpc_params* p) 
 static int32_t lanes_per_wave(int32_t requested, int64_t n_clusters) {
   if (requested > 0) return requested;
   // measured best: 20 lanes at 0.33 M clusters, 40 for a central event
-  // (1.3 M; 32 and 36 within 1.5%), 56 to 64 for 4.6 M, 8 for small events
+  // (1.3 M; 32 and 36 within 1.5%), 56 to 64 for 4.6 M, 12 to 16 at 0.17 M,
+  // and one lane per wave below about 15k clusters (a single sector: its few
+  // hundred tracklets never fill the chip, and a lone lane's steps are the
+  // shortest; 0.56 ms in the constructor against 0.63 ms at 8 lanes)
   const double waves = (double)(n_clusters / 36 + 1) / 2048.0;
   const int32_t a = 4 * (int32_t)std::lround(2.2 * std::sqrt(waves) + 0.5);
+  if (a < 8) return 1;
   return std::min(64, std::max(8, a));
 }
 
