@@ -316,9 +316,9 @@ typedef struct {
   int32_t construct_lanes;    /* lane schedule: lanes of each 64-lane wave that take
                                  tracklets (1 .. 64); fewer lanes per wave shorten
                                  each wave's steps at the cost of more waves;
-                                 0 = automatic (grows with the square root of the
-                                 clusters: 1 below about 15k, 20 at 0.33 M, 40 at
-                                 1.3 M, 64 from 4 M) */
+                                 0 = automatic (one per 16k clusters up to 0.3 M,
+                                 at least 1, then with the square root of the
+                                 clusters: 24 at 0.5 M, 40 at 1.3 M, 64 from 4 M) */
   int32_t nf_stage;           /* neighbours finder's LDS stage: 1 = rows of up to 512
                                  clusters, 12 window candidates per lane and row
                                  (five workgroups per CU); 2 = rows of up to 1024

@@ -126,15 +126,15 @@ int validate(const tpc_event* ev, const tpc_geometry* geo, const tpc_params* p) 
 // 36 clusters).
 static int32_t lanes_per_wave(int32_t requested, int64_t n_clusters) {
   if (requested > 0) return requested;
-  // measured best: 20 lanes at 0.33 M clusters, 40 for a central event
-  // (1.3 M; 32 and 36 within 1.5%), 56 to 64 for 4.6 M, 12 to 16 at 0.17 M,
-  // and one lane per wave below about 15k clusters (a single sector: its few
-  // hundred tracklets never fill the chip, and a lone lane's steps are the
-  // shortest; 0.56 ms in the constructor against 0.63 ms at 8 lanes)
+  // measured best: about one lane per 16k clusters up to 0.27 M (1 to 2 at
+  // 17k to 33k, 4 at 67k, 8 at 0.13 M, 16 to 20 at 0.27 M: a small event's
+  // tracklets never fill the chip, and the fewer lanes a wave has, the
+  // shorter its steps), then the square-root rule: 24 to 32 at 0.53 M, 40
+  // for a central event (1.3 M; 32 and 36 within 1.5%), 64 for 4.6 M
   const double waves = (double)(n_clusters / 36 + 1) / 2048.0;
   const int32_t a = 4 * (int32_t)std::lround(2.2 * std::sqrt(waves) + 0.5);
-  if (a < 8) return 1;
-  return std::min(64, std::max(8, a));
+  const int64_t lin = n_clusters / 16384;
+  return (int32_t)std::max<int64_t>(1, std::min<int64_t>(std::min(64, std::max(8, a)), lin));
 }
 
 // Clusters per chunk of the selection's LDS argmax: smaller chunks give more
