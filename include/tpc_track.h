@@ -322,7 +322,8 @@ typedef struct {
   int32_t nf_stage;           /* neighbours finder's LDS stage: 1 = rows of up to 512
                                  clusters, 12 window candidates per lane and row
                                  (five workgroups per CU); 2 = rows of up to 1024
-                                 clusters, 32 candidates (three per CU); 3 = rows of
+                                 clusters, 32 candidates, eight waves (two per CU);
+                                 3 = rows of
                                  up to 256 clusters, one wave per row slot (fourteen
                                  per CU), and one wave per row slot for the grid,
                                  evolution and seed kernels too; larger rows take the

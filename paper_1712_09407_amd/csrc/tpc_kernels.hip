@@ -51,14 +51,16 @@ constexpr int kGridWaveBins = 1024;  // LDS bins of the one-wave form of k_grid
 // k_nf stages neighbour rows of up to CAP clusters in LDS and keeps up to
 // LIST window candidates per row and lane: (512, 12) with 16-bit entries and
 // four waves for rows of central density (31 KB of LDS, five workgroups per
-// CU), (1024, 32) with 8-bit entries for dense events (49 KB, three
-// workgroups per CU), and (256, 12) with one wave for sparse rows (11 KB,
-// fourteen workgroups per CU: many small events batched).  A lane's longer
+// CU), (1024, 32) with 8-bit entries and eight waves for dense events (74 KB,
+// two workgroups per CU: a dense row's clusters are shared by more waves),
+// and (256, 12) with one wave for sparse rows (11 KB, fourteen workgroups per
+// CU: many small events batched).  A lane's longer
 // list is searched by its whole wave, a longer row by the global-memory
 // search; every configuration gives the same links.
 constexpr int kNfCapSmall = 512, kNfListSmall = 12;
 constexpr int kNfCapLarge = 1024, kNfListLarge = 32;
 constexpr int kNfCapWave = 256;
+constexpr int kNfDenseBlock = 512;  // threads of the dense form's workgroups
 constexpr int kScanBlock = 1024;
 constexpr int kRowSpan = 8 * kScanBlock;  // row slots per workgroup of the row scan
 constexpr int kTlBlock = 64;     // one wave per block for per-tracklet kernels
@@ -2922,8 +2924,8 @@ hipError_t enqueue_event(const DevEvent& ev, const KParams& kp, const Scratch& s
   if (upto <= STAGE_GRID) return hipGetLastError();
   pre(K_NF);
   if (kp.nf_stage == 2)
-    hipLaunchKernelGGL((k_nf<kNfCapLarge, kNfListLarge, uint8_t, kGridBlock>), dim3(R),
-                       dim3(kGridBlock), 0, st, ev, kp, sc);
+    hipLaunchKernelGGL((k_nf<kNfCapLarge, kNfListLarge, uint8_t, kNfDenseBlock>), dim3(R),
+                       dim3(kNfDenseBlock), 0, st, ev, kp, sc);
   else if (kp.nf_stage == 3)
     hipLaunchKernelGGL((k_nf<kNfCapWave, kNfListSmall, uint16_t, 64>), dim3(R), dim3(64), 0, st,
                        ev, kp, sc);
