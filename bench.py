@@ -738,7 +738,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on a single GPU; --gpus must be 1 "
+        print("bench.py: the tracker runs on a single GPU; --gpus must be 1 "
               "(the path shards by event across GPUs, see the design notes)", file=sys.stderr)
         sys.exit(2)
 
