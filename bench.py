@@ -739,7 +739,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: the tracker runs on a single GPU; --gpus must be 1 "
-              "(the path shards by event across GPUs, see the design notes)", file=sys.stderr)
+              "(several GPUs would each track their own events, one process per GPU)", file=sys.stderr)
         sys.exit(2)
 
     # every host event first: nothing may fork once the GPU is initialised
